@@ -1,0 +1,229 @@
+"""Plain FP64 CPU oracle for the pressure-correction step (test infrastructure).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  The product package
+``paper_2502_04189_amd`` never imports it, and the two share no code.
+
+The numerical work is in ``oracle.c`` (single-threaded C, built with
+``-ffp-contract=off``); this module only marshals numpy arrays through ctypes.
+Each function states the passage of the CaNS-Fizzy paper it follows
+("Methods and Implementation strategy": staggered second-order finite
+differences, pressure-correction projection, constant-coefficient splitting,
+FFT-based direct Poisson solver).  Arrays are C-contiguous ``[k][j][i]`` FP64.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_DP = C.POINTER(C.c_double)
+
+
+class OrGrid(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+        ("lx", C.c_double), ("ly", C.c_double),
+        ("zf", _DP),
+        ("bcx", C.c_int), ("bcy", C.c_int), ("bcz", C.c_int),
+    ]
+
+
+class OrDiag(C.Structure):
+    _fields_ = [
+        ("f_inf", C.c_double), ("rel_residual", C.c_double),
+        ("max_div_abs", C.c_double), ("max_div_rel", C.c_double),
+        ("mean_p", C.c_double),
+    ]
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (plain C, no contraction, no fast-math)."""
+    src = os.path.join(_HERE, "oracle.c")
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-ffp-contract=off",
+                               "-fno-fast-math", "-fPIC", "-shared", "-o", tmp, src, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = C.CDLL(_LIB_PATH)
+        G = C.POINTER(OrGrid)
+        L.oracle_check_grid.argtypes = [G]
+        L.oracle_step.argtypes = [G, C.c_double, C.c_double] + [_DP] * 9 + [C.POINTER(OrDiag)]
+        L.oracle_rhs.argtypes = [G, C.c_double, C.c_double] + [_DP] * 6
+        L.oracle_poisson.argtypes = [G, _DP, _DP]
+        L.oracle_correct.argtypes = [G, C.c_double, C.c_double] + [_DP] * 9
+        L.oracle_grad.argtypes = [G, _DP, _DP, _DP, _DP]
+        L.oracle_div.argtypes = [G, _DP, _DP, _DP, _DP]
+        L.oracle_apply_L.argtypes = [G, _DP, _DP]
+        L.oracle_volume_mean.argtypes = [G, _DP]
+        L.oracle_volume_mean.restype = C.c_double
+        L.oracle_dense_poisson.argtypes = [G, _DP, _DP]
+        L.oracle_fft.argtypes = [C.c_int, _DP, _DP, C.c_int]
+        L.oracle_dct2.argtypes = [C.c_int, _DP, _DP]
+        L.oracle_dct3.argtypes = [C.c_int, _DP, _DP]
+        L.oracle_thomas.argtypes = [C.c_int, _DP, _DP, _DP, _DP]
+        L.oracle_cyclic.argtypes = [C.c_int, _DP, _DP, _DP, _DP]
+        L.oracle_eig.argtypes = [C.c_int, C.c_double, C.c_int, C.c_int]
+        L.oracle_eig.restype = C.c_double
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_DP)
+
+
+class Grid:
+    """Grid/BC descriptor (bc: 0 periodic, 1 wall); zf holds nz+1 z faces."""
+
+    def __init__(self, nx, ny, nz, lx, ly, zf, bcx=0, bcy=0, bcz=1):
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.lx, self.ly = float(lx), float(ly)
+        self.zf = np.ascontiguousarray(zf, dtype=np.float64)
+        self.bcx, self.bcy, self.bcz = int(bcx), int(bcy), int(bcz)
+        self._c = OrGrid(self.nx, self.ny, self.nz, self.lx, self.ly, _p(self.zf),
+                         self.bcx, self.bcy, self.bcz)
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def cref(self):
+        return C.byref(self._c)
+
+    @classmethod
+    def from_workload(cls, g):
+        return cls(g.nx, g.ny, g.nz, g.lx, g.ly, g.zf, g.bcx, g.bcy, g.bcz)
+
+
+def _chk(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed (rc={rc})")
+
+
+def _arr(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def step(g: Grid, dt, rho0, rho, pstar, u, v, w):
+    """Whole pressure-correction step (projection with the constant-coefficient
+    splitting).  Returns (u_out, v_out, w_out, p, diag dict)."""
+    ins = [_arr(a) for a in (rho, pstar, u, v, w)]
+    outs = [np.empty(g.shape) for _ in range(4)]
+    d = OrDiag()
+    rc = lib().oracle_step(g.cref, float(dt), float(rho0), *[_p(a) for a in ins],
+                           *[_p(a) for a in outs], C.byref(d))
+    _chk(rc, "step")
+    diag = {k: getattr(d, k) for k, _ in OrDiag._fields_}
+    return outs[0], outs[1], outs[2], outs[3], diag
+
+
+def rhs(g, dt, rho0, rho, pstar, u, v, w):
+    ins = [_arr(a) for a in (rho, pstar, u, v, w)]
+    f = np.empty(g.shape)
+    _chk(lib().oracle_rhs(g.cref, float(dt), float(rho0), *[_p(a) for a in ins], _p(f)), "rhs")
+    return f
+
+
+def poisson(g, f):
+    f = _arr(f)
+    p = np.empty(g.shape)
+    _chk(lib().oracle_poisson(g.cref, _p(f), _p(p)), "poisson")
+    return p
+
+
+def correct(g, dt, rho0, rho, pstar, u, v, w, p):
+    ins = [_arr(a) for a in (rho, pstar, u, v, w, p)]
+    outs = [np.empty(g.shape) for _ in range(3)]
+    _chk(lib().oracle_correct(g.cref, float(dt), float(rho0), *[_p(a) for a in ins],
+                              *[_p(a) for a in outs]), "correct")
+    return tuple(outs)
+
+
+def grad(g, q):
+    q = _arr(q)
+    outs = [np.empty(g.shape) for _ in range(3)]
+    _chk(lib().oracle_grad(g.cref, _p(q), *[_p(a) for a in outs]), "grad")
+    return tuple(outs)
+
+
+def div(g, u, v, w):
+    ins = [_arr(a) for a in (u, v, w)]
+    out = np.empty(g.shape)
+    _chk(lib().oracle_div(g.cref, *[_p(a) for a in ins], _p(out)), "div")
+    return out
+
+
+def apply_L(g, p):
+    p = _arr(p)
+    out = np.empty(g.shape)
+    _chk(lib().oracle_apply_L(g.cref, _p(p), _p(out)), "apply_L")
+    return out
+
+
+def volume_mean(g, q):
+    q = _arr(q)
+    return lib().oracle_volume_mean(g.cref, _p(q))
+
+
+def dense_poisson(g, f):
+    f = _arr(f)
+    p = np.empty(g.shape)
+    _chk(lib().oracle_dense_poisson(g.cref, _p(f), _p(p)), "dense_poisson")
+    return p
+
+
+def fft(x, sign=-1):
+    x = np.asarray(x, dtype=np.complex128)
+    re = np.ascontiguousarray(x.real)
+    im = np.ascontiguousarray(x.imag)
+    _chk(lib().oracle_fft(len(re), _p(re), _p(im), int(sign)), "fft")
+    return re + 1j * im
+
+
+def dct2(x):
+    x = _arr(x)
+    X = np.empty_like(x)
+    _chk(lib().oracle_dct2(len(x), _p(x), _p(X)), "dct2")
+    return X
+
+
+def dct3(X):
+    X = _arr(X)
+    x = np.empty_like(X)
+    _chk(lib().oracle_dct3(len(X), _p(X), _p(x)), "dct3")
+    return x
+
+
+def thomas(a, b, c, d):
+    a, b, c = _arr(a), _arr(b), _arr(c)
+    x = _arr(d).copy()
+    _chk(lib().oracle_thomas(len(x), _p(a), _p(b), _p(c), _p(x)), "thomas")
+    return x
+
+
+def cyclic(a, b, c, d):
+    a, b, c = _arr(a), _arr(b), _arr(c)
+    x = _arr(d).copy()
+    _chk(lib().oracle_cyclic(len(x), _p(a), _p(b), _p(c), _p(x)), "cyclic")
+    return x
+
+
+def eig(n, h, bc, l):
+    return lib().oracle_eig(int(n), float(h), int(bc), int(l))

@@ -1,0 +1,155 @@
+"""Manufactured fixed point of the pressure-correction step (test helper).
+
+For any density rho, any q with zero volume-weighted mean and any discretely
+divergence-free staggered field u_df, the inputs
+    p* = q,   u* = u_df + dt G q / rho_face   (0 on wall faces)
+make the splitting right-hand side equal to L q, so the exact step returns
+p = q and u_out = u_df.  Proof: D u_df = 0, so
+    f = (rho0/dt) D(dt G q / rho_face) + D[(1 - rho0/rho_face) G q] = D G q,
+and u_out = u* - dt [G q / rho0 + (1/rho_face - 1/rho0) G q] = u_df.
+
+u_df is the discrete curl of an edge-centred vector potential whose edges on
+wall faces are zero, so D u_df vanishes identically (differences commute) and
+wall-normal components vanish on the walls.
+
+Everything here is plain vectorised numpy written for this construction; it is
+neither the oracle nor the GPU path.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from paper_2502_04189_amd.workloads import WALL, GridSpec
+
+
+def _shift_minus(a, axis, wall):
+    """a[idx-1] along axis; index -1 wraps when periodic, reads 0 at a wall."""
+    if wall:
+        out = np.zeros_like(a)
+        src = [slice(None)] * 3
+        dst = [slice(None)] * 3
+        src[axis] = slice(0, -1)
+        dst[axis] = slice(1, None)
+        out[tuple(dst)] = a[tuple(src)]
+        return out
+    return np.roll(a, 1, axis=axis)
+
+
+def _shift_plus(a, axis, wall):
+    """a[idx+1] along axis (wrap when periodic; the value past the end is
+    unused at walls and returned as 0)."""
+    if wall:
+        out = np.zeros_like(a)
+        src = [slice(None)] * 3
+        dst = [slice(None)] * 3
+        src[axis] = slice(1, None)
+        dst[axis] = slice(0, -1)
+        out[tuple(dst)] = a[tuple(src)]
+        return out
+    return np.roll(a, -1, axis=axis)
+
+
+def metrics(g: GridSpec):
+    zf = np.asarray(g.zf, dtype=np.float64)
+    dzf = np.diff(zf)
+    zc = 0.5 * (zf[:-1] + zf[1:])
+    dzc = np.empty(g.nz)
+    dzc[:-1] = zc[1:] - zc[:-1]
+    dzc[-1] = 0.5 * (dzf[-1] + dzf[0])
+    return dzf, dzc
+
+
+def divfree_field(rng, g: GridSpec, amp: float = 1.0):
+    """Discrete curl of a random edge potential (zero on wall edges)."""
+    dzf, _ = metrics(g)
+    sh = g.shape
+    Ax = rng.standard_normal(sh) * amp
+    Ay = rng.standard_normal(sh) * amp
+    Az = rng.standard_normal(sh) * amp
+    if g.bcx == WALL:
+        Ay[:, :, -1] = 0.0
+        Az[:, :, -1] = 0.0
+    if g.bcy == WALL:
+        Ax[:, -1, :] = 0.0
+        Az[:, -1, :] = 0.0
+    if g.bcz == WALL:
+        Ax[-1, :, :] = 0.0
+        Ay[-1, :, :] = 0.0
+    wx, wy, wz = g.bcx == WALL, g.bcy == WALL, g.bcz == WALL
+    dz = dzf[:, None, None]
+    u = (Az - _shift_minus(Az, 1, wy)) / g.dy - (Ay - _shift_minus(Ay, 0, wz)) / dz
+    v = (Ax - _shift_minus(Ax, 0, wz)) / dz - (Az - _shift_minus(Az, 2, wx)) / g.dx
+    w = (Ay - _shift_minus(Ay, 2, wx)) / g.dx - (Ax - _shift_minus(Ax, 1, wy)) / g.dy
+    return u, v, w
+
+
+def grad_faces(g: GridSpec, q):
+    _, dzc = metrics(g)
+    wx, wy, wz = g.bcx == WALL, g.bcy == WALL, g.bcz == WALL
+    gx = (_shift_plus(q, 2, wx) - q) / g.dx
+    gy = (_shift_plus(q, 1, wy) - q) / g.dy
+    gz = (_shift_plus(q, 0, wz) - q) / dzc[:, None, None]
+    if wx:
+        gx[:, :, -1] = 0.0
+    if wy:
+        gy[:, -1, :] = 0.0
+    if wz:
+        gz[-1, :, :] = 0.0
+    return gx, gy, gz
+
+
+def rho_faces(g: GridSpec, rho):
+    dzf, dzc = metrics(g)
+    wx, wy, wz = g.bcx == WALL, g.bcy == WALL, g.bcz == WALL
+    rx = 0.5 * (rho + _shift_plus(rho, 2, wx))
+    ry = 0.5 * (rho + _shift_plus(rho, 1, wy))
+    dzf_up = np.roll(dzf, -1)
+    rz = (rho * dzf_up[:, None, None] + _shift_plus(rho, 0, wz) * dzf[:, None, None]) / (2.0 * dzc[:, None, None])
+    # wall faces are never used; keep them finite
+    if wx:
+        rx[:, :, -1] = 1.0
+    if wy:
+        ry[:, -1, :] = 1.0
+    if wz:
+        rz[-1, :, :] = 1.0
+    return rx, ry, rz
+
+
+def fixed_point_inputs(rng, g: GridSpec, rho, dt: float, q=None):
+    """(pstar, u*, v*, w*, q, u_df, v_df, w_df) of the manufactured fixed point."""
+    if q is None:
+        q = rng.standard_normal(g.shape)
+    dzf, _ = metrics(g)
+    m = float((q.sum(axis=(1, 2)) * dzf).sum() / (g.nx * g.ny * dzf.sum()))
+    q = q - m
+    # potentials of size h give velocities of order one, like the workloads
+    ud, vd, wd = divfree_field(rng, g, amp=min(g.dx, g.dy))
+    gx, gy, gz = grad_faces(g, q)
+    rx, ry, rz = rho_faces(g, rho)
+    us = ud + dt * gx / rx
+    vs = vd + dt * gy / ry
+    ws = wd + dt * gz / rz
+    if g.bcx == WALL:
+        us[:, :, -1] = 0.0
+    if g.bcy == WALL:
+        vs[:, -1, :] = 0.0
+    if g.bcz == WALL:
+        ws[-1, :, :] = 0.0
+    return q.copy(), us, vs, ws, q, ud, vd, wd
+
+
+def cos_mode(g: GridSpec, lx: int, my: int, nzm: int):
+    """Discrete eigenfunction cos in each direction: periodic directions use
+    cos(2 pi l i / n), wall directions cos(pi l (i + 1/2) / n); z is uniform."""
+    def ax(n, l, bc):
+        i = np.arange(n)
+        return np.cos(2 * np.pi * l * i / n) if bc != WALL else np.cos(np.pi * l * (i + 0.5) / n)
+    return (ax(g.nz, nzm, g.bcz)[:, None, None] * ax(g.ny, my, g.bcy)[None, :, None]
+            * ax(g.nx, lx, g.bcx)[None, None, :])
+
+
+def relerr(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    den = np.abs(b).max()
+    return float(np.abs(a - b).max() / (den if den > 0 else 1.0))
