@@ -1,0 +1,290 @@
+"""Benchmark of the pressure-correction step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 512] [--no-cpu]
+
+Workload: the 512^3 wall-bounded channel with 512 bubbles (density ratio
+1000, tanh-stretched z, x/y periodic), seeded synthetic inputs resident in
+HBM.  A step is one whole pressure-correction step: RHS assembly, forward
+transforms, tridiagonal z solves, inverse transforms, velocity correction and
+divergence check.  `value` is the plain FP64 form's throughput in Mpts/s
+(grid points per second / 1e6); the same line carries the FP32 +
+FP64-refinement form on the same inputs, the batched form, the dominant
+kernel's roofline, and the CPU oracle timed on the host.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def spectral_bytes(gs, csz):
+    return (gs.nx // 2 + 1) * gs.ny * gs.nz * csz
+
+
+def kernel_bytes(name, gs, csz):
+    """Compulsory HBM bytes of one launch of a pass (algorithmic model: every
+    input read once, every output written once)."""
+    n = gs.cells
+    sp = spectral_bytes(gs, csz)
+    table = {
+        "rhs_stencil": 5 * 8 * n + 8 * n,          # rho, p*, u*, v*, w* -> f
+        "resid_stencil": 2 * 8 * n + 8 * n,        # f, p -> r
+        "x_fft_fwd": 8 * n + sp,                   # f -> S1
+        "x_fft_fwd_resid": 8 * n + sp,             # r -> S1
+        "y_fft_fwd": 2 * sp, "z_solve": 2 * sp, "y_fft_inv": 2 * sp,
+        "x_fft_inv_store_p": sp + 8 * n,           # S1 -> p
+        "x_fft_inv_accum_p": sp + 16 * n,          # S1, p -> p
+        "p_mean": 0,
+        "correct_div": 6 * 8 * n + 3 * 8 * n,      # u*, v*, w*, rho, p*, p -> u, v, w
+        "div_check": 3 * 8 * n,
+    }
+    return table.get(name, 0)
+
+
+def time_plan(plan, case_dev, dt, rho0, steps, warmup, outs):
+    import torch
+    rho, ps, u, v, w = case_dev
+    uo, vo, wo, po = outs
+    for _ in range(warmup):
+        plan.step(dt, rho0, rho, ps, u, v, w, uo, vo, wo, po, report=False)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(st)
+    for _ in range(steps):
+        plan.step(dt, rho0, rho, ps, u, v, w, uo, vo, wo, po, report=False)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / steps
+    passes = plan.pass_times()
+    plan.set_timing(False)
+    return ms, wall, passes
+
+
+def summarize_passes(passes, steps):
+    agg = {}
+    for name, t in passes:
+        a = agg.setdefault(name, [0.0, 0])
+        a[0] += t
+        a[1] += 1
+    return {k: {"ms_avg": v[0] / v[1], "launches_per_step": v[1] / steps} for k, v in agg.items()}
+
+
+def roofline(pass_summary, gs, csz):
+    # dominant kernel = largest total time per step
+    best = max(pass_summary.items(), key=lambda kv: kv[1]["ms_avg"] * kv[1]["launches_per_step"])
+    name, s = best
+    by = kernel_bytes(name, gs, csz)
+    gbs = by / (s["ms_avg"] * 1e-3) / 1e9
+    return name, {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                  "kernel": name, "bytes_per_launch": by, "ms_per_launch": round(s["ms_avg"], 4)}
+
+
+def cpu_baseline(n_cpu):
+    """The oracle, single-threaded, on one full step of the same recipe at
+    n_cpu^3 (a bounded sample of the workload)."""
+    import oracle
+    from paper_2502_04189_amd import workloads as W
+    case = W.channel_bubbles(n_cpu, max(1, (n_cpu // 64) ** 3), 1003, f"cpu_sample_{n_cpu}^3")
+    g = oracle.Grid.from_workload(case.grid)
+    t0 = time.perf_counter()
+    oracle.step(g, case.dt, case.rho0, *case.fields())
+    t = time.perf_counter() - t0
+    return {"value": round(case.grid.cells / t / 1e6, 3), "unit": "Mpts/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full oracle step (FP64, 1 thread) of the wall-channel bubble recipe at "
+                      f"{n_cpu}^3 ({case.grid.cells} cells) in {t:.1f} s"}
+
+
+def run_batch(steps, warmup, ndom):
+    """192 domains of uneven size (refined form) in one persistent graph
+    launch, against the same domains run one after another with plain FP64
+    plans on the same GPU."""
+    import torch
+    from paper_2502_04189_amd import pcx
+    from paper_2502_04189_amd import workloads as W
+    t0 = time.perf_counter()
+    cases = W.config4(ndom=ndom)
+    log(f"generated {len(cases)} batch domains in {time.perf_counter() - t0:.1f} s")
+    cells = sum(c.grid.cells for c in cases)
+    doms = []
+    for c in cases:
+        f = [torch.from_numpy(a).to("cuda") for a in c.fields()]
+        o = [torch.empty(c.grid.shape, dtype=torch.float64, device="cuda") for _ in range(4)]
+        doms.append({"grid": c.grid, "dt": c.dt, "rho0": c.rho0, "rho": f[0], "pstar": f[1], "u": f[2],
+                     "v": f[3], "w": f[4], "u_out": o[0], "v_out": o[1], "w_out": o[2], "p_out": o[3]})
+    cache = os.path.join(ROOT, "gpurun_out", "batch_tune_cache.txt") if os.path.isdir(
+        os.path.join(ROOT, "gpurun_out")) else None
+    t0 = time.perf_counter()
+    b = pcx.Batch(doms, "fp32_refined", autotune=True, tune_cache=cache)
+    t_create = time.perf_counter() - t0
+    for _ in range(warmup):
+        b.launch()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(steps):
+        b.launch()
+    e1.record(st)
+    torch.cuda.synchronize()
+    bms = e0.elapsed_time(e1) / steps
+    reps, status = b.reports()
+    worst = max(r["rel_residual"] for r in reps)
+    nconv = sum(r["converged"] for r in reps)
+    # sequential plain FP64 plans
+    plans = [pcx.Plan(d["grid"], "fp64") for d in doms]
+    def seq():
+        for p, d in zip(plans, doms):
+            p.step(d["dt"], d["rho0"], d["rho"], d["pstar"], d["u"], d["v"], d["w"], d["u_out"], d["v_out"],
+                   d["w_out"], d["p_out"], report=False)
+    for _ in range(warmup):
+        seq()
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(steps):
+        seq()
+    e1.record(st)
+    torch.cuda.synchronize()
+    sms = e0.elapsed_time(e1) / steps
+    log(f"batch: {bms:.3f} ms per launch ({cells} cells), sequential fp64 {sms:.3f} ms, create {t_create:.1f} s")
+    return {"domains": len(doms), "cells": cells, "ms_per_launch": round(bms, 4),
+            "value": round(cells / (bms * 1e-3) / 1e6, 1), "unit": "Mpts/s",
+            "solves_per_domain": reps[0]["solves"], "worst_rel_residual": worst,
+            "domains_converged": nconv, "status": status,
+            "sequential_fp64_ms": round(sms, 4), "speedup_vs_sequential_fp64": round(sms / bms, 3),
+            "create_s_incl_autotune": round(t_create, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=512, help="grid size n^3 of the channel workload")
+    ap.add_argument("--cpu-n", type=int, default=256, help="grid of the CPU-oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-refined", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--ndom", type=int, default=192)
+    ap.add_argument("--prof", action="store_true",
+                    help="profiling mode: a few FP64 (or --prof-refined) steps plus a 1 GiB torch copy "
+                         "that calibrates the HBM byte counters; prints no JSON")
+    ap.add_argument("--prof-refined", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is "
+              f"a design, not a build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2502_04189_amd import pcx
+    from paper_2502_04189_amd import workloads as W
+    pcx.lib()
+
+    t0 = time.perf_counter()
+    nb = 512 if args.n == 512 else max(1, (args.n // 64) ** 3)
+    case = W.channel_bubbles(args.n, nb, 1003, f"channel_{args.n}^3")
+    log(f"generated {case.name} in {time.perf_counter() - t0:.1f} s")
+    gs = case.grid
+    dev = [torch.from_numpy(a).to("cuda") for a in case.fields()]
+    rho0 = pcx.rho_min(dev[0])
+    assert rho0 == case.rho0
+    outs = [torch.empty(gs.shape, dtype=torch.float64, device="cuda") for _ in range(4)]
+    cells = gs.cells
+
+    if args.prof:
+        plan = pcx.Plan(gs, "fp32_refined" if args.prof_refined else "fp64", fixed_iters=3)
+        for _ in range(args.warmup + args.steps):
+            plan.step(case.dt, rho0, *dev, *outs, report=False)
+        torch.cuda.synchronize()
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("prof mode done: steps", args.warmup + args.steps, "copy bytes", 2 * src.numel() * 8)
+        return
+
+    # ---- FP64
+    plan = pcx.Plan(gs, "fp64")
+    ms, wall, passes = time_plan(plan, dev, case.dt, rho0, args.steps, args.warmup, outs)
+    summ = summarize_passes(passes, args.steps)
+    kname, roof = roofline(summ, gs, 16)
+    _, _, _, _, rep = plan.step(case.dt, rho0, *dev, *outs, report=True)
+    p64 = outs[3].clone()
+    log(f"fp64: {ms:.3f} ms/step, passes {json.dumps(summ)}")
+    log(f"fp64 report {rep}")
+    bytes_model = 176 * cells
+    res = {
+        "metric": "Mpts/s and Poisson steps/s at 512^3: FP64 vs FP32+refine at 1e-10, HBM %",
+        "value": round(cells / (ms * 1e-3) / 1e6, 1),
+        "unit": "Mpts/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"wall-channel {args.n}^3, {nb} bubbles, density ratio 1000, tanh z (a=1.8), "
+                               f"x/y periodic; plain FP64 pressure-correction step",
+                   "nx": gs.nx, "ny": gs.ny, "nz": gs.nz},
+        "steps_per_s": round(1000.0 / ms, 2),
+        "hbm_frac_step_model": round(bytes_model / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "fp64_rel_residual": rep["rel_residual"],
+        "passes_fp64": summ,
+        "roofline": roof,
+    }
+    del plan
+
+    # ---- FP32 + FP64 refinement on the same inputs
+    if not args.no_refined:
+        rplan = pcx.Plan(gs, "fp32_refined")
+        _, _, _, _, rrep = rplan.step(case.dt, rho0, *dev, *outs, report=True, raise_on_status=False)
+        solves = rrep["solves"]
+        rplan.close()
+        rplan = pcx.Plan(gs, "fp32_refined", fixed_iters=solves)
+        rms, _, rpasses = time_plan(rplan, dev, case.dt, rho0, args.steps, args.warmup, outs)
+        _, _, _, _, rrep = rplan.step(case.dt, rho0, *dev, *outs, report=True, raise_on_status=False)
+        dp = float((outs[3] - p64).abs().max() / p64.abs().max())
+        log(f"refined: {rms:.3f} ms/step solves {solves} report {rrep} |p - p64|/|p64| {dp:.3e}")
+        res["refined"] = {"ms_per_step": round(rms, 4), "value": round(cells / (rms * 1e-3) / 1e6, 1),
+                          "unit": "Mpts/s", "solves": rrep["solves"], "rel_residual": rrep["rel_residual"],
+                          "converged": bool(rrep["converged"]), "p_rel_diff_vs_fp64_gpu": dp,
+                          "speedup_vs_fp64": round(ms / rms, 3),
+                          "passes": summarize_passes(rpasses, args.steps)}
+        del rplan
+
+    del dev, outs, p64
+    torch.cuda.empty_cache()
+
+    # ---- batched form
+    if not args.no_batch:
+        res["batched"] = run_batch(args.steps, args.warmup, args.ndom)
+
+    if not args.no_cpu:
+        cb = cpu_baseline(args.cpu_n)
+        res["cpu_baseline"] = cb
+        res["speedup_vs_cpu_oracle"] = round(res["value"] / cb["value"], 1)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

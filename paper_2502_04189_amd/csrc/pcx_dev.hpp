@@ -1,0 +1,329 @@
+// pcx_dev.hpp -- device-side building blocks of the pressure-correction step
+// for gfx950 (CDNA4, wave64).
+//
+// The step (CaNS-Fizzy, "Methods and Implementation strategy"): the
+// right-hand side of the constant-coefficient pressure equation obtained by
+// the splitting, a fast direct solve (real FFT in x, complex FFT in y, one
+// tridiagonal solve in z per wavenumber pair on a possibly stretched z grid),
+// and the staggered velocity correction.
+//
+// Spectral data live in two workspace layouts, chosen so that every pass
+// reads or writes long contiguous runs and does its corner turn in LDS:
+//   S1 "y-columns": ((k*NL + l)*NY + j)   one (k,l) column contiguous in j/m
+//   S2 "z-lines"  : ((l*NY + m)*NZ + k)   one (l,m) line contiguous in k
+// with NL = nx/2 + 1 half-spectrum x modes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pcx {
+
+constexpr int NT = 256;       // threads per workgroup (4 wave64)
+constexpr int MAXST = 16;     // max FFT stages
+constexpr int PPT = 16;       // complex points per thread per FFT stage
+constexpr int NSTAT = 64;     // reduction slots per domain
+constexpr int MAXIT = 12;     // max refinement solves tracked
+
+enum { PREC_F64 = 0, PREC_F32 = 1 };
+enum { BC_PER = 0, BC_WALL = 1 };
+enum { SRC_RHS = 0, SRC_RESID = 1 }; // x-transform source buffer: f or r
+enum { XOUT_STORE = 0, XOUT_ACCUM = 1 };
+
+// reduction slots (uint64 bit patterns of non-negative doubles, atomicMax)
+enum {
+    ST_FINF = 0,      // ||f||inf
+    ST_DIV = 1,       // max |D u_out|
+    ST_NONFIN = 2,    // max over outputs of |.| (NaN/Inf show up here)
+    ST_SOLVE0 = 8     // per solve s: [8+4s] ||rhs||, [9+4s] ||e||, [10+4s] ||p||
+};
+
+// Division by a runtime constant d < 2^16 for numerators a < 2^16 via a
+// multiply-high: q = umulhi(a, m), m = floor(2^32/d) + 1 (exact when a*d < 2^32).
+struct FastDiv {
+    uint32_t d, m;
+};
+__device__ __forceinline__ uint32_t fdiv(uint32_t a, FastDiv f) { return f.d == 1 ? a : __umulhi(a, f.m); }
+
+struct FftDesc {
+    int n;                 // length
+    int nst;               // number of stages
+    int rad[MAXST];        // radix of each stage (2, 3, 4 or 8)
+    int ns[MAXST];         // product of the radices before the stage
+    int tws[MAXST];        // table stride n / (ns * rad)
+    FastDiv dnb[MAXST];    // division by n / rad
+    FastDiv dns[MAXST];    // division by ns
+    const void *tw;        // n roots exp(-2 pi i e / n), T2
+};
+
+// Everything one domain needs on the device.
+struct Dom {
+    int nx, ny, nz, nl, M;            // M = nx/2 (half-length complex FFT)
+    int bcx, bcy, bcz;
+    int tj, ntj;                      // x-pass rows per tile, j tiles
+    int tk, ntk;                      // y-pass columns per tile, k tiles
+    int zg, zlpw, nzt;                // z lanes per line, lines per WG, z tiles
+    int ncell_tiles;                  // correction tiles (see pass_corr)
+    int ndiv_tiles;                   // divergence-only tiles (NT cells each)
+    int cti, ctj, cnti, cntj, ckc, cnk; // correction tile TI x TJ cells, k chunk
+    FastDiv dnx, dny, dtj, dtk, dnyc, dcti;
+    double dx, dy, idx, idy, dt, rho0, irho0, lz, scale;
+    // z tables (FP64): dzf, 1/dzf, 1/dzc, rho interpolation weights
+    const double *dzf, *idzf, *idzc, *rzlo, *rzhi;
+    // z tridiagonal coefficients and eigenvalues in the solve precision
+    const void *za, *zb, *zc, *dzf_s, *lamx, *lamy;
+    const void *twr;                  // post-twiddles exp(-2 pi i l / nx), l in [0, M]
+    FftDesc fx, fy;
+    // fields
+    const double *rho, *ps, *u, *v, *w;
+    double *uo, *vo, *wo, *po;
+    double *f;                        // FP64 right-hand side
+    double *r;                        // FP64 residual f - L p (refined form)
+    void *s1, *s2;                    // spectral workspaces
+    unsigned long long *stats;        // NSTAT slots
+    double *ppart;                    // per x-tile dzf-weighted sums of p
+    double *pmean;                    // [0]: volume mean of p after the last xinv pass
+};
+
+// ------------------------------------------------------------ complex math
+template <typename T> struct T2;
+template <> struct T2<double> { using type = double2; };
+template <> struct T2<float> { using type = float2; };
+template <typename T> using c2 = typename T2<T>::type;
+
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return {a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return {a.x - b.x, a.y - b.y}; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+template <typename C> __device__ __forceinline__ C cconj(C a) { return {a.x, -a.y}; }
+template <typename C, typename T> __device__ __forceinline__ C cscale(C a, T s) { return {a.x * s, a.y * s}; }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV, typename C> __device__ __forceinline__ C rot90(C a) { return INV ? C{-a.y, a.x} : C{a.y, -a.x}; }
+
+// ---------------------------------------------------------- radix kernels
+// In-register DFT of R points; forward uses exp(-2 pi i/R), INV the conjugate.
+template <bool INV, typename C> __device__ __forceinline__ void bfly2(C &a0, C &a1)
+{
+    C t = a0;
+    a0 = cadd(t, a1);
+    a1 = csub(t, a1);
+}
+
+template <bool INV, typename C, typename T> __device__ __forceinline__ void bfly3(C &a0, C &a1, C &a2)
+{
+    const T c = T(-0.5);
+    const T s = T(0.86602540378443864676); // sqrt(3)/2
+    C sm = cadd(a1, a2), df = csub(a1, a2);
+    C b = {a0.x + c * sm.x, a0.y + c * sm.y};
+    // forward: y1 = b - i s df, y2 = b + i s df
+    C isd = {-s * df.y, s * df.x}; // i * s * df
+    a0 = cadd(a0, sm);
+    if (INV) { a1 = cadd(b, isd); a2 = csub(b, isd); }
+    else { a1 = csub(b, isd); a2 = cadd(b, isd); }
+}
+
+template <bool INV, typename C> __device__ __forceinline__ void bfly4(C &a0, C &a1, C &a2, C &a3)
+{
+    C t0 = cadd(a0, a2), t1 = csub(a0, a2);
+    C t2 = cadd(a1, a3), t3 = rot90<INV>(csub(a1, a3));
+    a0 = cadd(t0, t2);
+    a2 = csub(t0, t2);
+    a1 = cadd(t1, t3);
+    a3 = csub(t1, t3);
+}
+
+template <bool INV, typename C, typename T> __device__ __forceinline__ void bfly8(C *a)
+{
+    const T r = T(0.70710678118654752440); // 1/sqrt(2)
+    C e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
+    C o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
+    bfly4<INV>(e0, e1, e2, e3);
+    bfly4<INV>(o0, o1, o2, o3);
+    // twiddles W8^k on the odd half
+    C w1 = INV ? C{r * (o1.x - o1.y), r * (o1.x + o1.y)} : C{r * (o1.x + o1.y), r * (o1.y - o1.x)};
+    C w2 = rot90<INV>(o2);
+    C w3 = INV ? C{-r * (o3.x + o3.y), r * (o3.x - o3.y)} : C{r * (o3.y - o3.x), -r * (o3.x + o3.y)};
+    a[0] = cadd(e0, o0); a[4] = csub(e0, o0);
+    a[1] = cadd(e1, w1); a[5] = csub(e1, w1);
+    a[2] = cadd(e2, w2); a[6] = csub(e2, w2);
+    a[3] = cadd(e3, w3); a[7] = csub(e3, w3);
+}
+
+template <bool INV, int R, typename C, typename T> __device__ __forceinline__ void bfly(C *a)
+{
+    if constexpr (R == 2) bfly2<INV>(a[0], a[1]);
+    else if constexpr (R == 3) bfly3<INV, C, T>(a[0], a[1], a[2]);
+    else if constexpr (R == 4) bfly4<INV>(a[0], a[1], a[2], a[3]);
+    else bfly8<INV, C, T>(a);
+}
+
+// LDS position of element e of a line: one spare slot after every 8
+// elements, so that the stride-R stores of the early Stockham stages (and the
+// strided corner-turn accesses) spread over the LDS banks.
+__device__ __forceinline__ int pidx(int e) { return e + (e >> 3); }
+// Line stride for n elements: padded length rounded to 16 slots, plus one,
+// so consecutive lines start in different banks.
+__host__ __device__ constexpr int lds_line(int n) { return (((n - 1) + ((n - 1) >> 3) + 1 + 15) & ~15) + 1; }
+
+// One Stockham autosort stage over `nlines` LDS lines of length n (line
+// stride ldb, padded positions): butterfly b = (line, j), j in [0, n/R):
+//   inputs  x[line][j + r n/R], r < R
+//   twiddle W_{ns R}^{(j mod ns) r}
+//   outputs y[line][(j / ns) ns R + (j mod ns) + r ns]
+// Results are held in registers across a barrier, so the stage is in place.
+template <typename T, bool INV, int R>
+__device__ __forceinline__ void fft_stage(c2<T> *buf, int ldb, int nlines, const FftDesc &fd, int s)
+{
+    using C = c2<T>;
+    constexpr int K = (PPT + R - 1) / R;
+    const int nb = fd.n / R;
+    const int total = nlines * nb;
+    const int ns = fd.ns[s];
+    const int tws = fd.tws[s];
+    const C *tw = (const C *)fd.tw;
+    C v[K][R];
+    int lo[K], oo[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        int b = threadIdx.x + t * NT;
+        lo[t] = -1;
+        oo[t] = 0;
+        if (b < total) {
+            int line = (int)fdiv((uint32_t)b, fd.dnb[s]);
+            int j = b - line * nb;
+            const C *src = buf + line * ldb;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[t][r] = src[pidx(j + r * nb)];
+            int jq = (int)fdiv((uint32_t)j, fd.dns[s]);
+            int jm = j - jq * ns;
+            if (ns > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    C w = tw[jm * r * tws];
+                    if (INV) w.y = -w.y;
+                    v[t][r] = cmul(v[t][r], w);
+                }
+            }
+            lo[t] = line * ldb;
+            oo[t] = jq * ns * R + jm;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        if (lo[t] >= 0) {
+            bfly<INV, R, C, T>(v[t]);
+            C *dst = buf + lo[t];
+#pragma unroll
+            for (int r = 0; r < R; ++r) dst[pidx(oo[t] + r * ns)] = v[t][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Complex FFT (unnormalised) of nlines LDS lines; all threads participate.
+// Entry and exit are barrier-separated from the caller's LDS traffic.
+template <typename T, bool INV>
+__device__ void lds_fft(c2<T> *buf, int ldb, int nlines, const FftDesc &fd)
+{
+    for (int s = 0; s < fd.nst; ++s) {
+        switch (fd.rad[s]) {
+        case 2: fft_stage<T, INV, 2>(buf, ldb, nlines, fd, s); break;
+        case 3: fft_stage<T, INV, 3>(buf, ldb, nlines, fd, s); break;
+        case 4: fft_stage<T, INV, 4>(buf, ldb, nlines, fd, s); break;
+        default: fft_stage<T, INV, 8>(buf, ldb, nlines, fd, s); break;
+        }
+    }
+}
+
+// ------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Block-wide max of non-negative values (NaN propagates), then one atomicMax
+// on the uint64 bit pattern (order-preserving for non-negative doubles).
+__device__ __forceinline__ void block_max_to(unsigned long long *slot, double v, double *red)
+{
+    // keep NaN visible: fmax drops NaN, so map NaN to +Inf-plus pattern
+    if (v != v) v = __longlong_as_double(0x7ff8000000000000LL);
+    double w = v;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        double x = __shfl_xor(w, o, 64);
+        w = (x != x || x > w) ? x : w;
+    }
+    int wid = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[wid] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int i = 1; i < NT / 64; ++i) m = (red[i] != red[i] || red[i] > m) ? red[i] : m;
+        atomicMax(slot, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+// Deterministic block-wide sum (fixed shuffle tree, then waves in order);
+// the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *red)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < NT / 64; ++i) t += red[i];
+    return t;
+}
+
+// -------------------------------------------------------------- stencils
+// 1/x for positive normal x: hardware estimate refined by two Newton-Raphson
+// steps r <- r + r (1 - x r) (about one ulp; no scaling is needed for the
+// densities and spacings this is used on).
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// Corrected +x (dir 0), +y (1) or +z (2) face velocity of cell (i,j,k):
+// u* - dt [ (1/rho0) G p + (1/rho_face - 1/rho0) G p* ], 0 on wall faces.
+__device__ __forceinline__ double corr_face(const Dom &d, int dir, int i, int j, int k)
+{
+    const int nx = d.nx, ny = d.ny, nz = d.nz, sz = nx * ny;
+    const int c = k * sz + j * nx + i;
+    int o;
+    double h, irf;
+    const double *rho = d.rho + c;
+    if (dir == 0) {
+        if (d.bcx == BC_WALL && i == nx - 1) return 0.0;
+        o = (i == nx - 1) ? -(nx - 1) : 1;
+        h = d.idx;
+        irf = 2.0 * rcp_nr(rho[0] + rho[o]);
+    } else if (dir == 1) {
+        if (d.bcy == BC_WALL && j == ny - 1) return 0.0;
+        o = (j == ny - 1) ? -(ny - 1) * nx : nx;
+        h = d.idy;
+        irf = 2.0 * rcp_nr(rho[0] + rho[o]);
+    } else {
+        if (d.bcz == BC_WALL && k == nz - 1) return 0.0;
+        o = (k == nz - 1) ? -(nz - 1) * sz : sz;
+        h = d.idzc[k];
+        irf = rcp_nr(rho[0] * d.rzlo[k] + rho[o] * d.rzhi[k]);
+    }
+    const double *vin = (dir == 0 ? d.u : (dir == 1 ? d.v : d.w)) + c;
+    const double *p = d.po + c, *ps = d.ps + c;
+    const double gp = (p[o] - p[0]) * h;
+    const double gs = (ps[o] - ps[0]) * h;
+    return vin[0] - d.dt * (d.irho0 * gp + (irf - d.irho0) * gs);
+}
+
+} // namespace pcx

@@ -1,0 +1,629 @@
+// pcx_host.cpp -- host runtime behind the C ABI: validation, tables
+// (eigenvalues, z coefficients, twiddles), workspace, pass sequencing, the
+// refinement loop and reports.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pcx.h"
+#include "pcx_launch.hpp"
+#include "pcx_plan.hpp"
+#include "pcx_tune.hpp"
+
+namespace pcx {
+
+thread_local std::string g_err;
+
+pcx_status fail(pcx_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+static bool is_2a3b(int n)
+{
+    if (n < 1) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+FastDiv mkdiv(uint32_t d)
+{
+    FastDiv f;
+    f.d = d;
+    f.m = d <= 1 ? 0u : (uint32_t)((0x100000000ull / d) + 1ull);
+    return f;
+}
+
+std::vector<int> default_radices(int n)
+{
+    std::vector<int> r;
+    int a = 0, b = 0;
+    while (n % 2 == 0) { n /= 2; ++a; }
+    while (n % 3 == 0) { n /= 3; ++b; }
+    while (a >= 3) { r.push_back(8); a -= 3; }
+    if (a == 2) r.push_back(4);
+    else if (a == 1) r.push_back(2);
+    for (int i = 0; i < b; ++i) r.push_back(3);
+    return r;
+}
+
+void fill_fft(FftDesc &fd, int n, const std::vector<int> &rad)
+{
+    std::memset(&fd, 0, sizeof(fd));
+    fd.n = n;
+    fd.nst = (int)rad.size();
+    int ns = 1;
+    for (int s = 0; s < fd.nst; ++s) {
+        int R = rad[s];
+        fd.rad[s] = R;
+        fd.ns[s] = ns;
+        fd.tws[s] = n / (ns * R);
+        fd.dnb[s] = mkdiv((uint32_t)(n / R));
+        fd.dns[s] = mkdiv((uint32_t)ns);
+        ns *= R;
+    }
+}
+
+// ---------------------------------------------------------------- tables
+struct Blob {
+    std::vector<char> bytes;
+    size_t add(const void *p, size_t n)
+    {
+        size_t off = (bytes.size() + 255) & ~(size_t)255;
+        bytes.resize(off + n);
+        if (n) std::memcpy(bytes.data() + off, p, n);
+        return off;
+    }
+};
+
+template <typename T> static std::vector<T> cast_vec(const std::vector<long double> &v)
+{
+    std::vector<T> o(v.size());
+    for (size_t i = 0; i < v.size(); ++i) o[i] = (T)v[i];
+    return o;
+}
+
+template <typename T> static std::vector<T> roots(int n, bool extra)
+{
+    // exp(-2 pi i e / n), e in [0, n) (+1 entry when extra), two T per entry
+    int cnt = n + (extra ? 1 : 0);
+    std::vector<T> o(2 * (size_t)cnt);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int e = 0; e < cnt; ++e) {
+        long double a = 2.0L * pi * (long double)e / (long double)n;
+        o[2 * e] = (T)cosl(a);
+        o[2 * e + 1] = (T)(-sinl(a));
+    }
+    return o;
+}
+
+pcx_status validate_grid(const pcx_grid *g)
+{
+    if (!g) return fail(PCX_ERR_INVALID, "grid is NULL");
+    if (!g->zf) return fail(PCX_ERR_INVALID, "grid.zf is NULL");
+    if (g->nx < 2 || g->ny < 2 || g->nz < 2) return fail(PCX_ERR_INVALID, "nx, ny, nz must be >= 2");
+    if (!(g->lx > 0.0) || !(g->ly > 0.0)) return fail(PCX_ERR_INVALID, "lx and ly must be > 0");
+    for (int b : {g->bc_x, g->bc_y, g->bc_z})
+        if (b != PCX_BC_PERIODIC && b != PCX_BC_WALL) return fail(PCX_ERR_INVALID, "unknown boundary condition");
+    if (g->bc_x == PCX_BC_PERIODIC && (g->nx % 2)) return fail(PCX_ERR_INVALID, "nx must be even in a periodic direction");
+    if (g->bc_y == PCX_BC_PERIODIC && (g->ny % 2)) return fail(PCX_ERR_INVALID, "ny must be even in a periodic direction");
+    for (int k = 0; k < g->nz; ++k)
+        if (!(g->zf[k + 1] > g->zf[k])) return fail(PCX_ERR_INVALID, "zf must be strictly increasing");
+    if (!is_2a3b(g->nx) || !is_2a3b(g->ny) || g->nx > 4096 || g->ny > 4096)
+        return fail(PCX_ERR_UNSUPPORTED, "transform lengths must be 2^a 3^b and at most 4096");
+    if (g->nz > 1024) return fail(PCX_ERR_UNSUPPORTED, "nz above 1024 is not supported");
+    if (g->bc_x != PCX_BC_PERIODIC || g->bc_y != PCX_BC_PERIODIC)
+        return fail(PCX_ERR_UNSUPPORTED, "wall x or y (cosine transforms) is not built in this version");
+    return PCX_OK;
+}
+
+static int pow2_floor(long v)
+{
+    int p = 1;
+    while ((long)p * 2 <= v) p *= 2;
+    return p;
+}
+
+// Tile shapes: rows per x tile, columns per y tile, z lanes per line.
+void choose_shapes(const pcx_grid &g, int prec, const TuneParams *tp, Shapes &sh)
+{
+    const int M = g.nx / 2;
+    const size_t csz = prec == PREC_F64 ? 16 : 8;
+    const long lds_cap = 80 * 1024;
+    int tj = pow2_floor(std::max(1, (PPT * NT) / std::max(M, 1)));
+    tj = std::min(tj, pow2_floor(lds_cap / (long)(lds_line(M + 1) * csz)));
+    tj = std::min(tj, prec == PREC_F64 ? 8 : 16);
+    int tk = pow2_floor(std::max(1, (PPT * NT) / g.ny));
+    tk = std::min(tk, pow2_floor(lds_cap / (long)(lds_line(g.ny) * csz)));
+    tk = std::min(tk, prec == PREC_F64 ? 4 : 8);
+    int G = std::min(64, pow2_floor(std::max(1, g.nz / 2)));
+    if (tp) {
+        if (tp->tj > 0) tj = tp->tj;
+        if (tp->tk > 0) tk = tp->tk;
+        if (tp->zg > 0) G = tp->zg;
+    }
+    sh.tj = std::max(1, tj);
+    sh.tk = std::max(1, tk);
+    sh.zg = G;
+    int smax_need = (g.nz + G - 1) / G;
+    sh.smax = smax_need <= 4 ? 4 : (smax_need <= 8 ? 8 : 16);
+}
+
+pcx_status build_domain(const pcx_grid &g, int prec, const Shapes &sh, const RadixChoice *rc, DomTables &tb, Dom &d)
+{
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int M = nx / 2, nl = M + 1;
+    std::memset(&d, 0, sizeof(d));
+    d.nx = nx; d.ny = ny; d.nz = nz; d.nl = nl; d.M = M;
+    d.bcx = g.bc_x; d.bcy = g.bc_y; d.bcz = g.bc_z;
+    d.tj = sh.tj; d.ntj = (ny + sh.tj - 1) / sh.tj;
+    d.tk = sh.tk; d.ntk = (nz + sh.tk - 1) / sh.tk;
+    d.zg = sh.zg; d.zlpw = (NT / 64) * (64 / sh.zg);
+    long nlines = (long)nl * ny;
+    d.nzt = (int)((nlines + d.zlpw - 1) / d.zlpw);
+    d.ndiv_tiles = (int)(((long)nx * ny * nz + NT - 1) / NT);
+    // correction: TI x TJ cell tiles marching over chunks of ckc planes
+    d.cti = std::min(nx, 64);
+    d.ctj = std::max(1, std::min(ny, NT / d.cti));
+    d.cnti = (nx + d.cti - 1) / d.cti;
+    d.cntj = (ny + d.ctj - 1) / d.ctj;
+    {
+        long txy = (long)d.cnti * d.cntj;
+        long chunks = std::max(1L, std::min((long)nz, (4096 + txy - 1) / txy));
+        d.ckc = (int)((nz + chunks - 1) / chunks);
+        d.cnk = (nz + d.ckc - 1) / d.ckc;
+    }
+    d.ncell_tiles = d.cnti * d.cntj * d.cnk;
+    d.dnx = mkdiv(nx); d.dny = mkdiv(ny); d.dtj = mkdiv(sh.tj); d.dtk = mkdiv(sh.tk); d.dnyc = mkdiv(ny);
+    d.dcti = mkdiv(d.cti);
+    d.dx = g.lx / nx; d.dy = g.ly / ny;
+    d.idx = 1.0 / d.dx; d.idy = 1.0 / d.dy;
+    d.lz = g.zf[nz] - g.zf[0];
+    d.scale = 1.0 / ((double)nx * (double)ny);
+
+    // z metrics
+    std::vector<long double> dzf(nz), zc(nz), dzc(nz);
+    for (int k = 0; k < nz; ++k) {
+        dzf[k] = (long double)g.zf[k + 1] - (long double)g.zf[k];
+        zc[k] = 0.5L * ((long double)g.zf[k] + (long double)g.zf[k + 1]);
+    }
+    for (int k = 0; k < nz - 1; ++k) dzc[k] = zc[k + 1] - zc[k];
+    dzc[nz - 1] = 0.5L * (dzf[nz - 1] + dzf[0]);
+    std::vector<long double> idzf(nz), idzc(nz), rzlo(nz), rzhi(nz), za(nz), zb(nz), zcc(nz);
+    const bool per = g.bc_z == PCX_BC_PERIODIC;
+    for (int k = 0; k < nz; ++k) {
+        int kp = (k + 1) % nz, km = (k + nz - 1) % nz;
+        idzf[k] = 1.0L / dzf[k];
+        idzc[k] = 1.0L / dzc[k];
+        rzlo[k] = dzf[kp] / (2.0L * dzc[k]);
+        rzhi[k] = dzf[k] / (2.0L * dzc[k]);
+        bool lo = per || k > 0, hi = per || k < nz - 1;
+        za[k] = lo ? 1.0L / (dzf[k] * dzc[km]) : 0.0L;
+        zcc[k] = hi ? 1.0L / (dzf[k] * dzc[k]) : 0.0L;
+        zb[k] = -(za[k] + zcc[k]);
+    }
+    const long double pi = 3.141592653589793238462643383279502884L;
+    std::vector<long double> lamx(nl), lamy(ny);
+    for (int l = 0; l < nl; ++l) {
+        long double s = sinl(pi * (long double)l / (long double)nx);
+        lamx[l] = -4.0L / ((long double)d.dx * d.dx) * s * s;
+    }
+    for (int m = 0; m < ny; ++m) {
+        int mm = std::min(m, ny - m);
+        long double s = sinl(pi * (long double)mm / (long double)ny);
+        lamy[m] = -4.0L / ((long double)d.dy * d.dy) * s * s;
+    }
+
+    Blob b;
+    auto addd = [&](const std::vector<long double> &v) { auto c = cast_vec<double>(v); return b.add(c.data(), c.size() * 8); };
+    auto adds = [&](const std::vector<long double> &v) {
+        if (prec == PREC_F64) { auto c = cast_vec<double>(v); return b.add(c.data(), c.size() * 8); }
+        auto c = cast_vec<float>(v);
+        return b.add(c.data(), c.size() * 4);
+    };
+    auto addr = [&](int n, bool extra) {
+        if (prec == PREC_F64) { auto c = roots<double>(n, extra); return b.add(c.data(), c.size() * 8); }
+        auto c = roots<float>(n, extra);
+        return b.add(c.data(), c.size() * 4);
+    };
+    size_t o_dzf = addd(dzf), o_idzf = addd(idzf), o_idzc = addd(idzc), o_rzlo = addd(rzlo), o_rzhi = addd(rzhi);
+    size_t o_za = adds(za), o_zb = adds(zb), o_zc = adds(zcc), o_dzfs = adds(dzf);
+    size_t o_lx = adds(lamx), o_ly = adds(lamy);
+    size_t o_twr = addr(nx, false); // first M+1 entries of the nx roots are W_nx^l
+    size_t o_twx = addr(M, false);
+    size_t o_twy = addr(ny, false);
+
+    tb.bytes = b.bytes.size();
+    hipError_t e = hipMalloc(&tb.dev, tb.bytes);
+    if (e != hipSuccess) { tb.dev = nullptr; return fail(PCX_ERR_NOMEM, "hipMalloc(tables) failed"); }
+    e = hipMemcpy(tb.dev, b.bytes.data(), tb.bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(PCX_ERR_HIP, std::string("hipMemcpy(tables): ") + hipGetErrorString(e));
+    char *base = (char *)tb.dev;
+    d.dzf = (const double *)(base + o_dzf);
+    d.idzf = (const double *)(base + o_idzf);
+    d.idzc = (const double *)(base + o_idzc);
+    d.rzlo = (const double *)(base + o_rzlo);
+    d.rzhi = (const double *)(base + o_rzhi);
+    d.za = base + o_za; d.zb = base + o_zb; d.zc = base + o_zc; d.dzf_s = base + o_dzfs;
+    d.lamx = base + o_lx; d.lamy = base + o_ly;
+    d.twr = base + o_twr;
+    fill_fft(d.fx, M, rc && !rc->x.empty() ? rc->x : default_radices(M));
+    d.fx.tw = base + o_twx;
+    fill_fft(d.fy, ny, rc && !rc->y.empty() ? rc->y : default_radices(ny));
+    d.fy.tw = base + o_twy;
+    return PCX_OK;
+}
+
+size_t lds_x(const Dom &d, int prec) { return (size_t)d.tj * lds_line(d.M + 1) * (prec == PREC_F64 ? 16 : 8) + 64; }
+size_t lds_y(const Dom &d, int prec) { return (size_t)d.tk * lds_line(d.ny) * (prec == PREC_F64 ? 16 : 8) + 64; }
+size_t lds_z(const Dom &d, int prec)
+{
+    size_t e = (size_t)d.zlpw * d.nz;
+    return (e + e / 16 + 1) * (prec == PREC_F64 ? 16 : 8) + 64;
+}
+
+} // namespace pcx
+
+using namespace pcx;
+
+// =================================================================== plan
+
+static pcx_status plan_free(pcx_plan P)
+{
+    if (!P) return PCX_OK;
+    if (P->tables.dev) (void)hipFree(P->tables.dev);
+    if (P->s1) (void)hipFree(P->s1);
+    if (P->s2) (void)hipFree(P->s2);
+    if (P->f) (void)hipFree(P->f);
+    if (P->r) (void)hipFree(P->r);
+    if (P->stats) (void)hipFree(P->stats);
+    if (P->psum) (void)hipFree(P->psum);
+    if (P->ppart) (void)hipFree(P->ppart);
+    for (auto e : P->ev) (void)hipEventDestroy(e);
+    delete P;
+    return PCX_OK;
+}
+
+extern "C" pcx_status pcx_plan_create(const pcx_grid *grid, const pcx_options *opts, pcx_plan *out)
+{
+    if (!out) return fail(PCX_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    pcx_status st = validate_grid(grid);
+    if (st != PCX_OK) return st;
+    pcx_options o = {PCX_FP64, 1e-10, 8, 0, 0, 0, nullptr};
+    if (opts) o = *opts;
+    if (o.precision != PCX_FP64 && o.precision != PCX_FP32_REFINED) return fail(PCX_ERR_INVALID, "unknown precision");
+    if (!(o.rtol > 0.0)) o.rtol = 1e-10;
+    if (o.max_iters <= 0) o.max_iters = 8;
+    if (o.max_iters > MAXIT) o.max_iters = MAXIT;
+    if (o.fixed_iters <= 0) o.fixed_iters = 3;
+    if (o.fixed_iters > o.max_iters) o.fixed_iters = o.max_iters;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev < 1) return fail(PCX_ERR_HIP, "no HIP device available");
+
+    pcx_plan P = new pcx_plan_s();
+    P->grid = *grid;
+    P->zf.assign(grid->zf, grid->zf + grid->nz + 1);
+    P->grid.zf = P->zf.data();
+    P->opt = o;
+    P->prec = o.precision == PCX_FP64 ? PREC_F64 : PREC_F32;
+    (void)hipGetDevice(&P->device);
+    TuneParams tp;
+    RadixChoice rc;
+    TuneCache cache;
+    bool have = o.tune_cache && cache.load(o.tune_cache) && cache.lookup(P->grid, P->prec, tp, rc);
+    if (!have && o.autotune) {
+        st = autotune_class(P->grid, P->prec, nullptr, tp, rc);
+        if (st != PCX_OK) { delete P; return st; }
+        have = true;
+        if (o.tune_cache) {
+            cache.store(P->grid, P->prec, tp, rc);
+            cache.save(o.tune_cache);
+        }
+    }
+    choose_shapes(P->grid, P->prec, have ? &tp : nullptr, P->sh);
+    st = build_domain(P->grid, P->prec, P->sh, have ? &rc : nullptr, P->tables, P->dom);
+    if (st != PCX_OK) { plan_free(P); return st; }
+    const size_t csz = P->prec == PREC_F64 ? 16 : 8;
+    const size_t nspec = (size_t)P->dom.nl * grid->ny * grid->nz;
+    const size_t ncell = (size_t)grid->nx * grid->ny * grid->nz;
+    if (hipMalloc(&P->s1, nspec * csz) != hipSuccess || hipMalloc(&P->s2, nspec * csz) != hipSuccess ||
+        hipMalloc(&P->stats, NSTAT * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&P->psum, (size_t)grid->nz * sizeof(double)) != hipSuccess) {
+        plan_free(P);
+        return fail(PCX_ERR_NOMEM, "workspace allocation failed");
+    }
+    if (hipMalloc(&P->f, ncell * sizeof(double)) != hipSuccess ||
+        (P->prec == PREC_F32 &&
+         (hipMalloc(&P->r, ncell * sizeof(double)) != hipSuccess ||
+          hipMalloc(&P->ppart, ((size_t)P->dom.ntj * grid->nz + 8) * sizeof(double)) != hipSuccess))) {
+        plan_free(P);
+        return fail(PCX_ERR_NOMEM, "workspace allocation failed (f, r)");
+    }
+    P->ws_bytes = 2 * nspec * csz + NSTAT * 8 + grid->nz * 8 + P->tables.bytes + ncell * 8 + (P->r ? ncell * 8 : 0) +
+                  (P->ppart ? ((size_t)P->dom.ntj * grid->nz + 8) * 8 : 0);
+    P->dom.s1 = P->s1;
+    P->dom.s2 = P->s2;
+    P->dom.f = P->f;
+    P->dom.r = P->r;
+    P->dom.stats = P->stats;
+    P->dom.ppart = P->ppart;
+    P->dom.pmean = P->ppart ? P->ppart + (size_t)P->dom.ntj * grid->nz : nullptr;
+    P->lx = lds_x(P->dom, P->prec);
+    P->ly = lds_y(P->dom, P->prec);
+    P->lzs = lds_z(P->dom, P->prec);
+    *out = P;
+    return PCX_OK;
+}
+
+extern "C" pcx_status pcx_plan_workspace_bytes(pcx_plan P, size_t *bytes)
+{
+    if (!P || !bytes) return fail(PCX_ERR_INVALID, "NULL argument");
+    *bytes = P->ws_bytes;
+    return PCX_OK;
+}
+
+extern "C" pcx_status pcx_plan_destroy(pcx_plan P) { return plan_free(P); }
+
+// --------------------------------------------------------------- timing
+// When timing is on, every step appends HIP events recorded on its stream
+// between passes; pcx_plan_pass_times returns the durations of all passes of
+// all steps since timing was (re)enabled.
+static void tmark(pcx_plan P, hipStream_t s, const char *name)
+{
+    if (!P->timing) return;
+    if (P->nev >= (int)P->ev.size()) {
+        if (P->ev.size() >= 4096) return;
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        P->ev.push_back(e);
+        P->names.push_back("");
+    }
+    (void)hipEventRecord(P->ev[P->nev], s);
+    P->names[P->nev] = name ? name : "";
+    P->nev++;
+}
+
+extern "C" pcx_status pcx_plan_set_timing(pcx_plan P, int32_t enable)
+{
+    if (!P) return fail(PCX_ERR_INVALID, "plan is NULL");
+    P->timing = enable != 0;
+    P->nev = 0;
+    P->npass = 0;
+    return PCX_OK;
+}
+
+extern "C" pcx_status pcx_plan_pass_times(pcx_plan P, double *ms, int32_t cap, int32_t *n_out)
+{
+    if (!P || !n_out) return fail(PCX_ERR_INVALID, "NULL argument");
+    *n_out = 0;
+    if (P->nev == 0) return PCX_OK;
+    hipError_t e = hipEventSynchronize(P->ev[P->nev - 1]);
+    if (e != hipSuccess) return fail(PCX_ERR_HIP, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+    P->pass_names.clear();
+    int n = 0;
+    for (int i = 1; i < P->nev; ++i) {
+        if (P->names[i].empty()) continue; // step start marker
+        float t = 0.f;
+        e = hipEventElapsedTime(&t, P->ev[i - 1], P->ev[i]);
+        if (e != hipSuccess) return fail(PCX_ERR_HIP, std::string("hipEventElapsedTime: ") + hipGetErrorString(e));
+        if (n < cap && ms) ms[n] = t;
+        P->pass_names.push_back(P->names[i]);
+        ++n;
+    }
+    *n_out = n;
+    return PCX_OK;
+}
+
+extern "C" const char *pcx_plan_pass_name(pcx_plan P, int32_t i)
+{
+    if (!P || i < 0 || i >= (int)P->pass_names.size()) return "";
+    return P->pass_names[i].c_str();
+}
+
+// ----------------------------------------------------------------- step
+#define HIPCHK(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess) return fail(PCX_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// One FP32/FP64 solve: transforms and tridiagonal solve on the right-hand
+// side already placed (x-transformed) in S1, ending with p stored/accumulated.
+static pcx_status solve_tail(pcx_plan P, const Dom &d, int solve, int mode, hipStream_t s)
+{
+    HIPCHK(launch_y(d, P->prec, false, P->ly, s));
+    tmark(P, s, "y_fft_fwd");
+    HIPCHK(launch_z(d, P->prec, P->sh.smax, P->lzs, s));
+    tmark(P, s, "z_solve");
+    HIPCHK(launch_y(d, P->prec, true, P->ly, s));
+    tmark(P, s, "y_fft_inv");
+    HIPCHK(launch_xinv(d, P->prec, mode, solve, P->lx, s));
+    tmark(P, s, mode == XOUT_STORE ? "x_fft_inv_store_p" : "x_fft_inv_accum_p");
+    if (d.ppart) {
+        HIPCHK(launch_pmean(d, s));
+        tmark(P, s, "p_mean");
+    }
+    return PCX_OK;
+}
+
+static double stat_d(const std::vector<unsigned long long> &h, int i)
+{
+    double v;
+    std::memcpy(&v, &h[i], 8);
+    return v;
+}
+
+// Stop test of the refinement: the relative residual must be within rtol and
+// the error left after the last update, estimated from the observed
+// contraction q = |e_s| / |e_{s-1}| as q |e_s| / (1 - q), must be below
+// 0.1 rtol |p|.  The first solve alone never stops (no rate is known).
+extern "C" int32_t pcx_refine_should_stop(double rel_residual, double update_inf, double prev_update_inf, double p_inf,
+                                          double rtol)
+{
+    if (!(rel_residual <= rtol)) return 0;
+    if (!(prev_update_inf > 0.0) || !(update_inf >= 0.0)) return 0;
+    const double q = update_inf / prev_update_inf;
+    if (!(q < 1.0)) return 0;
+    const double est = q * update_inf / (1.0 - q);
+    return est <= 0.1 * rtol * p_inf ? 1 : 0;
+}
+
+extern "C" pcx_status pcx_step(pcx_plan P, double dt, double rho0, const double *rho, const double *p_star,
+                               const double *u_in, const double *v_in, const double *w_in, double *u_out,
+                               double *v_out, double *w_out, double *p_out, void *stream, pcx_report *report)
+{
+    if (!P) return fail(PCX_ERR_INVALID, "plan is NULL");
+    if (!rho || !p_star || !u_in || !v_in || !w_in || !u_out || !v_out || !w_out || !p_out)
+        return fail(PCX_ERR_INVALID, "NULL field pointer");
+    if (!(dt > 0.0) || !(rho0 > 0.0) || !std::isfinite(dt) || !std::isfinite(rho0))
+        return fail(PCX_ERR_INVALID, "dt and rho0 must be finite and > 0");
+    const void *ins[] = {rho, p_star, u_in, v_in, w_in, u_out, v_out, w_out};
+    for (const void *q : ins)
+        if (q == p_out) return fail(PCX_ERR_INVALID, "p_out aliases another field");
+    const double *velin[] = {u_in, v_in, w_in};
+    const double *velout[] = {u_out, v_out, w_out};
+    bool inplace = false;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            if (velout[a] == velin[b]) {
+                if (a != b) return fail(PCX_ERR_INVALID, "velocity output aliases a different input component");
+                inplace = true;
+            }
+            if (velout[a] == rho || velout[a] == p_star) return fail(PCX_ERR_INVALID, "velocity output aliases rho or p_star");
+            if (a != b && velout[a] == velout[b]) return fail(PCX_ERR_INVALID, "velocity outputs alias each other");
+        }
+    hipStream_t s = (hipStream_t)stream;
+    Dom d = P->dom;
+    d.dt = dt; d.rho0 = rho0; d.irho0 = 1.0 / rho0;
+    d.rho = rho; d.ps = p_star; d.u = u_in; d.v = v_in; d.w = w_in;
+    d.uo = u_out; d.vo = v_out; d.wo = w_out; d.po = p_out;
+    tmark(P, s, nullptr);
+    HIPCHK(launch_zero(P->stats, NSTAT, s));
+    int solves = 0;
+    HIPCHK(launch_rhs(d, s));
+    tmark(P, s, "rhs_stencil");
+    HIPCHK(launch_xfwd(d, P->prec, SRC_RHS, P->lx, s));
+    tmark(P, s, "x_fft_fwd");
+    pcx_status st0 = solve_tail(P, d, 0, XOUT_STORE, s);
+    if (st0 != PCX_OK) return st0;
+    solves = 1;
+    auto refine_once = [&](int solve) -> pcx_status {
+        HIPCHK(launch_resid(d, solve, s));
+        tmark(P, s, "resid_stencil");
+        HIPCHK(launch_xfwd(d, P->prec, SRC_RESID, P->lx, s));
+        tmark(P, s, "x_fft_fwd_resid");
+        return solve_tail(P, d, solve, XOUT_ACCUM, s);
+    };
+    if (P->prec == PREC_F32) {
+        for (; solves < P->opt.fixed_iters; ++solves) {
+            pcx_status st = refine_once(solves);
+            if (st != PCX_OK) return st;
+        }
+    }
+    auto correct = [&]() -> pcx_status {
+        HIPCHK(launch_corr(d, !inplace, s));
+        tmark(P, s, "correct_div");
+        if (inplace) {
+            HIPCHK(launch_div(d, s));
+            tmark(P, s, "div_check");
+        }
+        return PCX_OK;
+    };
+    // With a report the refined form keeps refining until rtol is met.  The
+    // correction is computed from p only after the decision: the step is
+    // re-corrected after each extra solve (u* is untouched unless in place,
+    // where no extra solve can be taken after the first correction).
+    pcx_status st = PCX_OK;
+    std::vector<unsigned long long> h(NSTAT);
+    if (!report) return correct();
+    while (true) {
+        st = correct();
+        if (st != PCX_OK) return st;
+        HIPCHK(hipMemcpyAsync(h.data(), P->stats, NSTAT * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        double finf = stat_d(h, ST_FINF), dv = stat_d(h, ST_DIV);
+        double rel = dv / ((dt / rho0) * finf);
+        double einf = stat_d(h, ST_SOLVE0 + 4 * (solves - 1) + 1);
+        double eprev = solves >= 2 ? stat_d(h, ST_SOLVE0 + 4 * (solves - 2) + 1) : 0.0;
+        double pinf = stat_d(h, ST_SOLVE0 + 4 * (solves - 1) + 2);
+        bool stop = P->prec == PREC_F64 || pcx_refine_should_stop(rel, einf, eprev, pinf, P->opt.rtol);
+        if (stop || solves >= P->opt.max_iters || inplace) break;
+        HIPCHK(launch_zero(P->stats + ST_DIV, 1, s));
+        st = refine_once(solves);
+        if (st != PCX_OK) return st;
+        ++solves;
+    }
+    // report
+    HIPCHK(launch_plane_sums(p_out, P->grid.nx * P->grid.ny, P->grid.nz, P->psum, s));
+    std::vector<double> ps(P->grid.nz);
+    HIPCHK(hipMemcpyAsync(ps.data(), P->psum, ps.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double num = 0.0, lz = P->zf[P->grid.nz] - P->zf[0];
+    for (int k = 0; k < P->grid.nz; ++k) num += (P->zf[k + 1] - P->zf[k]) * ps[k];
+    pcx_report r;
+    std::memset(&r, 0, sizeof(r));
+    r.solves = solves;
+    r.f_inf = stat_d(h, ST_FINF);
+    r.max_div_abs = stat_d(h, ST_DIV);
+    r.rel_residual = r.max_div_abs / ((dt / rho0) * r.f_inf);
+    r.max_div_rel = r.rel_residual;
+    r.mean_p = num / ((double)P->grid.nx * P->grid.ny * lz);
+    r.last_update_inf = stat_d(h, ST_SOLVE0 + 4 * (solves - 1) + 1);
+    double eprev = solves >= 2 ? stat_d(h, ST_SOLVE0 + 4 * (solves - 2) + 1) : 0.0;
+    double pinf = stat_d(h, ST_SOLVE0 + 4 * (solves - 1) + 2);
+    r.converged = P->prec == PREC_F64 ? (r.rel_residual <= P->opt.rtol)
+                                      : pcx_refine_should_stop(r.rel_residual, r.last_update_inf, eprev, pinf, P->opt.rtol);
+    *report = r;
+    if (P->opt.check_finite) {
+        double om = stat_d(h, ST_NONFIN);
+        if (!std::isfinite(om) || !std::isfinite(r.f_inf) || !std::isfinite(r.max_div_abs))
+            return fail(PCX_ERR_NONFINITE, "non-finite value in the outputs");
+    }
+    if (P->prec == PREC_F32 && !r.converged) return fail(PCX_ERR_NOT_CONVERGED, "refinement did not reach rtol within max_iters");
+    return PCX_OK;
+}
+
+// ------------------------------------------------------------------ misc
+
+extern "C" pcx_status pcx_rho_min(const double *rho, int64_t n, void *stream, double *out)
+{
+    if (!rho || !out || n <= 0) return fail(PCX_ERR_INVALID, "bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long *key = nullptr;
+    HIPCHK(hipMalloc(&key, 8));
+    unsigned long long init = ~0ull, hk = 0;
+    hipError_t e = hipMemcpyAsync(key, &init, 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_min(rho, (long long)n, key, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hk, key, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(key);
+    if (e != hipSuccess) return fail(PCX_ERR_HIP, std::string("rho_min: ") + hipGetErrorString(e));
+    unsigned long long u = (hk >> 63) ? (hk & 0x7fffffffffffffffull) : ~hk;
+    std::memcpy(out, &u, 8);
+    return PCX_OK;
+}
+
+extern "C" const char *pcx_status_str(pcx_status s)
+{
+    switch (s) {
+    case PCX_OK: return "PCX_OK";
+    case PCX_ERR_INVALID: return "PCX_ERR_INVALID";
+    case PCX_ERR_UNSUPPORTED: return "PCX_ERR_UNSUPPORTED";
+    case PCX_ERR_NOMEM: return "PCX_ERR_NOMEM";
+    case PCX_ERR_HIP: return "PCX_ERR_HIP";
+    case PCX_ERR_NOT_CONVERGED: return "PCX_ERR_NOT_CONVERGED";
+    case PCX_ERR_NONFINITE: return "PCX_ERR_NONFINITE";
+    }
+    return "PCX_ERR_UNKNOWN";
+}
+
+extern "C" const char *pcx_last_error(void) { return g_err.c_str(); }
+
+extern "C" int32_t pcx_abi_version(void) { return PCX_ABI_VERSION; }

@@ -1,0 +1,359 @@
+// pcx_kernels.hip -- __global__ entry points and their host launchers.
+// One kernel per pass for a single domain (the descriptor travels by value
+// in the kernel arguments), small reduction helpers, and the persistent
+// multi-domain kernel of the batched form.
+#include "pcx_launch.hpp"
+#include "pcx_passes.hpp"
+
+namespace pcx {
+
+// Logical tile of a marching stencil launch: consecutive blockIdx values go
+// to different XCDs (round-robin), so the launch hands XCD x a contiguous
+// range of tiles; tiles adjacent in j then share that XCD's L2 for their halo
+// rows.  The grid is padded to a multiple of 8; surplus blocks exit.
+__device__ __forceinline__ int xcd_tile(int ntiles)
+{
+    const int per = (ntiles + 7) >> 3;
+    const int b = blockIdx.x;
+    return (b & 7) * per + (b >> 3);
+}
+
+__global__ __launch_bounds__(NT) void k_rhs(Dom d)
+{
+    __shared__ double sm[8 + 2 * NT];
+    const int t = xcd_tile(d.ncell_tiles);
+    if (t >= d.ncell_tiles) return;
+    pass_rhs(d, t, (char *)sm);
+}
+
+__global__ __launch_bounds__(NT) void k_resid(Dom d, int solve)
+{
+    __shared__ double sm[8 + NT];
+    const int t = xcd_tile(d.ncell_tiles);
+    if (t >= d.ncell_tiles) return;
+    pass_resid(d, t, (char *)sm, solve);
+}
+
+template <typename T, int SRC>
+__global__ __launch_bounds__(NT) void k_xfwd(Dom d)
+{
+    extern __shared__ __align__(16) char smem[];
+    pass_xfwd<T, SRC>(d, blockIdx.x, smem);
+}
+
+template <typename T, bool INV>
+__global__ __launch_bounds__(NT) void k_y(Dom d)
+{
+    extern __shared__ __align__(16) char smem[];
+    pass_y<T, INV>(d, blockIdx.x, smem);
+}
+
+template <typename T, int SMAX>
+__global__ __launch_bounds__(NT) void k_z(Dom d)
+{
+    extern __shared__ __align__(16) char smem[];
+    pass_z<T, SMAX>(d, blockIdx.x, smem);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(NT) void k_xinv(Dom d, int solve)
+{
+    extern __shared__ __align__(16) char smem[];
+    pass_xinv<T, MODE>(d, blockIdx.x, smem, solve);
+}
+
+__global__ __launch_bounds__(NT) void k_corr(Dom d, int divcheck)
+{
+    __shared__ double sm[8 + 4 * NT];
+    const int t = xcd_tile(d.ncell_tiles);
+    if (t >= d.ncell_tiles) return;
+    pass_corr(d, t, (char *)sm, divcheck != 0);
+}
+
+__global__ __launch_bounds__(NT) void k_div(Dom d)
+{
+    __shared__ double red[NT / 64];
+    pass_div(d, blockIdx.x, (char *)red);
+}
+
+__global__ __launch_bounds__(NT) void k_pmean(Dom d)
+{
+    __shared__ double red[NT / 64];
+    pass_pmean(d, (char *)red);
+}
+
+__global__ void k_zero(unsigned long long *p, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// Per-plane sums of p in a fixed order (deterministic), one workgroup per k.
+__global__ __launch_bounds__(NT) void k_plane_sums(const double *p, int nxy, double *out)
+{
+    __shared__ double part[NT];
+    const double *pl = p + (size_t)blockIdx.x * nxy;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nxy; i += NT) s += pl[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = part[0];
+}
+
+// min over doubles via an order-preserving uint64 key and atomicMin.
+__device__ __forceinline__ unsigned long long dkey(double v)
+{
+    unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
+__global__ __launch_bounds__(NT) void k_min(const double *a, long long n, unsigned long long *key)
+{
+    __shared__ unsigned long long part[NT / 64];
+    unsigned long long m = ~0ull;
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
+        unsigned long long kk = dkey(a[i]);
+        m = kk < m ? kk : m;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long x = __shfl_xor(m, o, 64);
+        m = x < m ? x : m;
+    }
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < NT / 64; ++i) m = part[i] < m ? part[i] : m;
+        m = part[0] < m ? part[0] : m;
+        atomicMin(key, m);
+    }
+}
+
+// ----------------------------------------------------------------- launch
+
+static hipError_t lds_attr(const void *fn, size_t lds)
+{
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+#define PCX_LAUNCH(fn, grid, lds, st, ...)                                              \
+    do {                                                                                \
+        hipError_t e_ = lds_attr((const void *)(fn), (lds));                            \
+        if (e_ != hipSuccess) return e_;                                                \
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), (lds), (st), __VA_ARGS__);         \
+        return hipGetLastError();                                                       \
+    } while (0)
+
+hipError_t launch_zero(unsigned long long *p, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero, dim3((n + 63) / 64), dim3(64), 0, s, p, n);
+    return hipGetLastError();
+}
+
+static int xcd_grid(int ntiles) { return ((ntiles + 7) >> 3) << 3; }
+
+hipError_t launch_rhs(const Dom &d, hipStream_t s)
+{
+    PCX_LAUNCH(k_rhs, xcd_grid(d.ncell_tiles), 0, s, d);
+}
+
+hipError_t launch_resid(const Dom &d, int solve, hipStream_t s)
+{
+    PCX_LAUNCH(k_resid, xcd_grid(d.ncell_tiles), 0, s, d, solve);
+}
+
+hipError_t launch_xfwd(const Dom &d, int prec, int src, size_t lds, hipStream_t s)
+{
+    const int grid = d.ntj * d.nz;
+    if (prec == PREC_F64) {
+        if (src == SRC_RHS) PCX_LAUNCH((k_xfwd<double, SRC_RHS>), grid, lds, s, d);
+        PCX_LAUNCH((k_xfwd<double, SRC_RESID>), grid, lds, s, d);
+    }
+    if (src == SRC_RHS) PCX_LAUNCH((k_xfwd<float, SRC_RHS>), grid, lds, s, d);
+    PCX_LAUNCH((k_xfwd<float, SRC_RESID>), grid, lds, s, d);
+}
+
+hipError_t launch_y(const Dom &d, int prec, bool inv, size_t lds, hipStream_t s)
+{
+    const int grid = d.ntk * d.nl;
+    if (prec == PREC_F64) {
+        if (inv) PCX_LAUNCH((k_y<double, true>), grid, lds, s, d);
+        PCX_LAUNCH((k_y<double, false>), grid, lds, s, d);
+    }
+    if (inv) PCX_LAUNCH((k_y<float, true>), grid, lds, s, d);
+    PCX_LAUNCH((k_y<float, false>), grid, lds, s, d);
+}
+
+hipError_t launch_z(const Dom &d, int prec, int smax, size_t lds, hipStream_t s)
+{
+    const int grid = d.nzt;
+    if (prec == PREC_F64) {
+        if (smax <= 4) PCX_LAUNCH((k_z<double, 4>), grid, lds, s, d);
+        if (smax <= 8) PCX_LAUNCH((k_z<double, 8>), grid, lds, s, d);
+        PCX_LAUNCH((k_z<double, 16>), grid, lds, s, d);
+    }
+    if (smax <= 4) PCX_LAUNCH((k_z<float, 4>), grid, lds, s, d);
+    if (smax <= 8) PCX_LAUNCH((k_z<float, 8>), grid, lds, s, d);
+    PCX_LAUNCH((k_z<float, 16>), grid, lds, s, d);
+}
+
+hipError_t launch_xinv(const Dom &d, int prec, int mode, int solve, size_t lds, hipStream_t s)
+{
+    const int grid = d.ntj * d.nz;
+    if (prec == PREC_F64) PCX_LAUNCH((k_xinv<double, XOUT_STORE>), grid, lds, s, d, solve);
+    if (mode == XOUT_STORE) PCX_LAUNCH((k_xinv<float, XOUT_STORE>), grid, lds, s, d, solve);
+    PCX_LAUNCH((k_xinv<float, XOUT_ACCUM>), grid, lds, s, d, solve);
+}
+
+hipError_t launch_corr(const Dom &d, bool divcheck, hipStream_t s)
+{
+    PCX_LAUNCH(k_corr, xcd_grid(d.ncell_tiles), 0, s, d, divcheck ? 1 : 0);
+}
+
+hipError_t launch_pmean(const Dom &d, hipStream_t s)
+{
+    PCX_LAUNCH(k_pmean, 1, 0, s, d);
+}
+
+hipError_t launch_div(const Dom &d, hipStream_t s)
+{
+    PCX_LAUNCH(k_div, d.ndiv_tiles, 0, s, d);
+}
+
+hipError_t launch_plane_sums(const double *p, int nxy, int nz, double *out, hipStream_t s)
+{
+    PCX_LAUNCH(k_plane_sums, nz, 0, s, p, nxy, out);
+}
+
+hipError_t launch_min(const double *a, long long n, unsigned long long *key, hipStream_t s)
+{
+    long long blocks = (n + NT - 1) / NT;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    PCX_LAUNCH(k_min, (unsigned)blocks, 0, s, a, n, key);
+}
+
+} // namespace pcx
+
+namespace pcx {
+
+// Persistent multi-domain kernel.  Workgroups pull items (domain, phase,
+// tile) from one queue in list order; the list holds every tile of phase p
+// of a domain before any tile of phase p+1 of that domain, so a workgroup
+// only ever waits for items already taken by running workgroups and the
+// queue drains.  Each dependency wait is bounded by spin_limit polls; on
+// expiry the error flag is set and the item runs anyway, so every workgroup
+// exits.  Stores are released with a device-scope fence before the phase
+// counter is incremented, and acquired with a device-scope fence after the
+// wait.
+template <typename T, int SMAX>
+__global__ __launch_bounds__(NT) void k_persist(PersistArgs a)
+{
+    extern __shared__ __align__(16) char smem[];
+    __shared__ int s_item;
+    // All control flow of the work loop is uniform: the queue fetch, the
+    // dependency wait and the completion count are done by the whole of wave
+    // 0 under a wave-uniform branch, with only lane 0 contributing 1 to each
+    // atomic, and every value that steers a branch or a loop around a barrier
+    // goes through readfirstlane.  (With a per-lane loop exit or a
+    // `threadIdx.x == 0` block next to the back edge, the compiler may
+    // restructure the loop so that lane 0 and the rest of its wave run
+    // different iterations around the barriers.)
+    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const unsigned one = (threadIdx.x & 63) == 0 ? 1u : 0u;
+    for (;;) {
+        if (wid == 0) {
+            unsigned old = atomicAdd(a.head, one);
+            s_item = __builtin_amdgcn_readfirstlane((int)old);
+        }
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads(); // s_item is rewritten only after every wave has read it
+        if (it >= a.nitems) break;
+        const Item X = a.items[it];
+        const int dom = __builtin_amdgcn_readfirstlane((int)X.dom);
+        const int ph = __builtin_amdgcn_readfirstlane((int)X.phase);
+        const int tile = __builtin_amdgcn_readfirstlane((int)X.tile);
+        const unsigned slot = (unsigned)dom * a.tab.nphase + ph;
+        if (ph > 0 && wid == 0) {
+            const unsigned want = (unsigned)__builtin_amdgcn_readfirstlane((int)a.need[slot - 1]);
+            for (unsigned polls = 0;; ++polls) {
+                unsigned cur = __builtin_amdgcn_readfirstlane(
+                    (int)__hip_atomic_load(&a.done[slot - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                if (cur >= want) break;
+                if (polls >= a.spin_limit) {
+                    atomicOr(a.err, one);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(8);
+            }
+        }
+        __syncthreads();
+        __threadfence();
+        const Dom &d = a.doms[dom];
+        const int sv = a.tab.solve[ph];
+        switch (a.tab.kind[ph]) {
+        case PK_RHS: pass_rhs(d, tile, smem); break;
+        case PK_RESID: pass_resid(d, tile, smem, sv); break;
+        case PK_XFWD_RHS: pass_xfwd<T, SRC_RHS>(d, tile, smem); break;
+        case PK_XFWD_RESID: pass_xfwd<T, SRC_RESID>(d, tile, smem); break;
+        case PK_YF: pass_y<T, false>(d, tile, smem); break;
+        case PK_Z: pass_z<T, SMAX>(d, tile, smem); break;
+        case PK_YI: pass_y<T, true>(d, tile, smem); break;
+        case PK_XINV_STORE: pass_xinv<T, XOUT_STORE>(d, tile, smem, sv); break;
+        case PK_XINV_ACCUM: pass_xinv<T, XOUT_ACCUM>(d, tile, smem, sv); break;
+        case PK_PMEAN: pass_pmean(d, smem); break;
+        default: pass_corr(d, tile, smem, true); break;
+        }
+        __threadfence();
+        __syncthreads();
+        if (wid == 0) atomicAdd(&a.done[slot], one);
+    }
+}
+
+__global__ void k_reset(unsigned *p, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_reset(unsigned *p, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reset, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+template <typename T, int SMAX> static const void *persist_fn() { return (const void *)k_persist<T, SMAX>; }
+
+static const void *persist_sel(int prec, int smax)
+{
+    if (prec == PREC_F64) return smax <= 4 ? persist_fn<double, 4>() : (smax <= 8 ? persist_fn<double, 8>() : persist_fn<double, 16>());
+    return smax <= 4 ? persist_fn<float, 4>() : (smax <= 8 ? persist_fn<float, 8>() : persist_fn<float, 16>());
+}
+
+hipError_t persist_occupancy(int prec, int smax, size_t lds, int *blocks_per_cu)
+{
+    const void *fn = persist_sel(prec, smax);
+    hipError_t e = lds_attr(fn, lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, NT, lds);
+}
+
+hipError_t launch_persist(const PersistArgs &a, int prec, int smax, int blocks, size_t lds, hipStream_t s)
+{
+    if (prec == PREC_F64) {
+        if (smax <= 4) PCX_LAUNCH((k_persist<double, 4>), blocks, lds, s, a);
+        if (smax <= 8) PCX_LAUNCH((k_persist<double, 8>), blocks, lds, s, a);
+        PCX_LAUNCH((k_persist<double, 16>), blocks, lds, s, a);
+    }
+    if (smax <= 4) PCX_LAUNCH((k_persist<float, 4>), blocks, lds, s, a);
+    if (smax <= 8) PCX_LAUNCH((k_persist<float, 8>), blocks, lds, s, a);
+    PCX_LAUNCH((k_persist<float, 16>), blocks, lds, s, a);
+}
+
+} // namespace pcx

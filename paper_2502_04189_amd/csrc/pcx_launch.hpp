@@ -1,0 +1,57 @@
+// pcx_launch.hpp -- host-side launchers of the device passes.
+#pragma once
+
+#include "pcx_dev.hpp"
+
+namespace pcx {
+
+hipError_t launch_zero(unsigned long long *p, int n, hipStream_t s);
+hipError_t launch_rhs(const Dom &d, hipStream_t s);
+hipError_t launch_resid(const Dom &d, int solve, hipStream_t s);
+hipError_t launch_xfwd(const Dom &d, int prec, int src, size_t lds, hipStream_t s);
+hipError_t launch_y(const Dom &d, int prec, bool inv, size_t lds, hipStream_t s);
+hipError_t launch_z(const Dom &d, int prec, int smax, size_t lds, hipStream_t s);
+hipError_t launch_xinv(const Dom &d, int prec, int mode, int solve, size_t lds, hipStream_t s);
+hipError_t launch_corr(const Dom &d, bool divcheck, hipStream_t s);
+hipError_t launch_div(const Dom &d, hipStream_t s);
+hipError_t launch_pmean(const Dom &d, hipStream_t s);
+hipError_t launch_plane_sums(const double *p, int nxy, int nz, double *out, hipStream_t s);
+hipError_t launch_min(const double *a, long long n, unsigned long long *key, hipStream_t s);
+
+} // namespace pcx
+
+namespace pcx {
+
+// ---------------------------------------------------------------- batched
+constexpr int MAXPH = 64;
+enum { PK_RHS = 0, PK_RESID, PK_XFWD_RHS, PK_XFWD_RESID, PK_YF, PK_Z, PK_YI, PK_XINV_STORE, PK_XINV_ACCUM, PK_PMEAN, PK_CORR };
+
+struct Item {
+    uint16_t dom, phase;
+    uint32_t tile;
+};
+
+// Pass kind and solve index of each phase (the same for every domain).
+struct PhaseTab {
+    int nphase;
+    uint8_t kind[MAXPH];
+    uint8_t solve[MAXPH];
+};
+
+struct PersistArgs {
+    const Dom *doms;
+    const Item *items;
+    int nitems;
+    unsigned *head;           // queue head
+    unsigned *done;           // [ndom * nphase] finished tiles
+    const unsigned *need;     // [ndom * nphase] tiles of each phase
+    unsigned *err;            // set when a dependency wait gives up
+    unsigned spin_limit;      // max polls of one dependency wait
+    PhaseTab tab;
+};
+
+hipError_t launch_persist(const PersistArgs &a, int prec, int smax, int blocks, size_t lds, hipStream_t s);
+hipError_t launch_reset(unsigned *p, int n, hipStream_t s);
+hipError_t persist_occupancy(int prec, int smax, size_t lds, int *blocks_per_cu);
+
+} // namespace pcx

@@ -1,0 +1,659 @@
+// pcx_passes.hpp -- the passes of one pressure-correction step, as device
+// functions over one tile of one domain.  The same bodies serve the
+// one-kernel-per-pass launches of a single domain and the persistent
+// multi-domain kernel.
+//
+//   rhs    : splitting right-hand side f (FP64 stencil, k-marching)  (-> f)
+//   resid  : r = f - L p (FP64 stencil, k-marching)                  (-> r)
+//   xfwd   : real FFT in x of f or r, x->y corner turn              (-> S1)
+//   yfwd   : complex FFT in y, y->z corner turn                  (S1 -> S2)
+//   zsolve : tridiagonal solve per (l, m) line in z, in place        (S2)
+//   yinv   : inverse complex FFT in y, z->y corner turn          (S2 -> S1)
+//   xinv   : inverse real FFT in x, store or accumulate p        (S1 -> p)
+//   corr   : velocity correction with the divergence check (k-marching)
+#pragma once
+
+#include "pcx_dev.hpp"
+
+namespace pcx {
+
+// ------------------------------------------------------------- marching
+// Stencil tiles: TI x TJ cells of a plane (one thread per (i, j) column,
+// TI = min(nx, 64) so a wave holds one row segment when nx >= 64) marching
+// over a chunk of planes.  The planes a cell needs above it are loaded once
+// as the "k+1" neighbour and kept in registers for the next step; x
+// neighbours come from the adjacent lanes, y neighbours through LDS; only
+// tile-edge threads load neighbours from memory.
+struct MTile {
+    int i, j, ti, tj, kb, ke, lane;
+    bool act;
+};
+
+__device__ __forceinline__ MTile march_tile(const Dom &d, int tile)
+{
+    MTile t;
+    const int per = d.cnti * d.cntj;
+    const int kc = tile / per;
+    const int rem = tile - kc * per;
+    const int jt = rem / d.cnti, it = rem - jt * d.cnti;
+    t.tj = (int)fdiv(threadIdx.x, d.dcti);
+    t.ti = threadIdx.x - t.tj * d.cti;
+    const int i = it * d.cti + t.ti, j = jt * d.ctj + t.tj;
+    t.act = t.tj < d.ctj && i < d.nx && j < d.ny;
+    t.i = min(i, d.nx - 1); // clamped so that idle threads load valid cells
+    t.j = min(j, d.ny - 1);
+    t.kb = kc * d.ckc;
+    t.ke = min(d.nz, t.kb + d.ckc);
+    t.lane = threadIdx.x & 63;
+    return t;
+}
+
+struct MNbr {
+    int oe, ow, on, os;   // in-plane offsets of the four neighbours (wrapped)
+    bool we, ww, wn, ws;  // wall faces
+    bool she, shw;        // x neighbour held by the adjacent lane
+    bool lyn, lys;        // y neighbour held in LDS by the tile
+};
+
+__device__ __forceinline__ MNbr march_nbr(const Dom &d, const MTile &t)
+{
+    MNbr n;
+    const int nx = d.nx, ny = d.ny, i = t.i, j = t.j;
+    n.oe = (i == nx - 1) ? -(nx - 1) : 1;
+    n.ow = (i == 0) ? (nx - 1) : -1;
+    n.on = (j == ny - 1) ? -(ny - 1) * nx : nx;
+    n.os = (j == 0) ? (ny - 1) * nx : -nx;
+    n.we = d.bcx == BC_WALL && i == nx - 1;
+    n.ww = d.bcx == BC_WALL && i == 0;
+    n.wn = d.bcy == BC_WALL && j == ny - 1;
+    n.ws = d.bcy == BC_WALL && j == 0;
+    n.she = t.ti < d.cti - 1 && t.lane < 63 && i + 1 < nx;
+    n.shw = t.ti > 0 && t.lane > 0;
+    n.lyn = t.tj < d.ctj - 1 && j + 1 < ny;
+    n.lys = t.tj > 0;
+    return n;
+}
+
+__device__ __forceinline__ double amax_nan(double m, double v)
+{
+    double a = fabs(v);
+    return (a > m || a != a) ? a : m;
+}
+
+// f = (rho0/dt) D u* + D[(1 - rho0/rho_face) G p*], stored in FP64 to d.f.
+// Face fluxes: x from this lane and its west lane, y computed on both faces,
+// z carried from the previous plane.
+__device__ void pass_rhs(const Dom &d, int tile, char *smem)
+{
+    double *red = (double *)smem;
+    double *sP = red + 8, *sR = sP + NT;
+    const MTile t = march_tile(d, tile);
+    const MNbr n = march_nbr(d, t);
+    const int nx = d.nx, nz = d.nz, sz = nx * d.ny, TI = d.cti;
+    const int col = t.j * nx + t.i;
+    const double rr0 = d.rho0, tr0 = 2.0 * d.rho0;
+    const double idx2 = d.idx * d.idx, idy2 = d.idy * d.idy, cdiv = d.rho0 / d.dt;
+    int k = t.kb;
+    double Pc = d.ps[k * sz + col], Rc = d.rho[k * sz + col];
+    double Fb = 0.0, Wb = 0.0; // flux of (1 - rho0/rho) G p* and w* on face k - 1/2
+    if (!(d.bcz == BC_WALL && k == 0)) {
+        const int km = (k == 0) ? nz - 1 : k - 1;
+        const double Pm = d.ps[km * sz + col], Rm = d.rho[km * sz + col];
+        Fb = (1.0 - rr0 * rcp_nr(Rm * d.rzlo[km] + Rc * d.rzhi[km])) * (Pc - Pm) * d.idzc[km];
+        Wb = d.w[km * sz + col];
+    }
+    double amax = 0.0;
+    for (; k < t.ke; ++k) {
+        const int c = k * sz + col;
+        const int kp = (k == nz - 1) ? 0 : k + 1;
+        const bool wt = d.bcz == BC_WALL && k == nz - 1;
+        const double Pp = d.ps[kp * sz + col], Rp = d.rho[kp * sz + col];
+        const double u = d.u[c], v = d.v[c], w = d.w[c];
+        double Pe = __shfl_down(Pc, 1, 64), Re = __shfl_down(Rc, 1, 64);
+        if (!n.she) { Pe = d.ps[c + n.oe]; Re = d.rho[c + n.oe]; }
+        const double Fe = n.we ? 0.0 : (1.0 - tr0 * rcp_nr(Rc + Re)) * (Pe - Pc);
+        double Fw = __shfl_up(Fe, 1, 64), uw = __shfl_up(u, 1, 64);
+        if (!n.shw) {
+            const double Pw = d.ps[c + n.ow], Rw = d.rho[c + n.ow];
+            Fw = n.ww ? 0.0 : (1.0 - tr0 * rcp_nr(Rw + Rc)) * (Pc - Pw);
+            uw = d.u[c + n.ow];
+        }
+        sP[threadIdx.x] = Pc;
+        sR[threadIdx.x] = Rc;
+        __syncthreads();
+        double Pn, Rn, Ps, Rs;
+        if (n.lyn) { Pn = sP[threadIdx.x + TI]; Rn = sR[threadIdx.x + TI]; }
+        else { Pn = d.ps[c + n.on]; Rn = d.rho[c + n.on]; }
+        if (n.lys) { Ps = sP[threadIdx.x - TI]; Rs = sR[threadIdx.x - TI]; }
+        else { Ps = d.ps[c + n.os]; Rs = d.rho[c + n.os]; }
+        __syncthreads();
+        const double vs = n.ws ? 0.0 : d.v[c + n.os];
+        const double Fn = n.wn ? 0.0 : (1.0 - tr0 * rcp_nr(Rc + Rn)) * (Pn - Pc);
+        const double Fs = n.ws ? 0.0 : (1.0 - tr0 * rcp_nr(Rs + Rc)) * (Pc - Ps);
+        const double Ft = wt ? 0.0 : (1.0 - rr0 * rcp_nr(Rc * d.rzlo[k] + Rp * d.rzhi[k])) * (Pp - Pc) * d.idzc[k];
+        const double ue = n.we ? 0.0 : u, uwf = n.ww ? 0.0 : uw;
+        const double vn = n.wn ? 0.0 : v;
+        const double wt_ = wt ? 0.0 : w;
+        const double idzf = d.idzf[k];
+        const double f = cdiv * ((ue - uwf) * d.idx + (vn - vs) * d.idy + (wt_ - Wb) * idzf) + (Fe - Fw) * idx2 +
+                         (Fn - Fs) * idy2 + (Ft - Fb) * idzf;
+        if (t.act) {
+            d.f[c] = f;
+            amax = amax_nan(amax, f);
+        }
+        Fb = Ft;
+        Wb = wt_;
+        Pc = Pp;
+        Rc = Rp;
+    }
+    block_max_to(d.stats + ST_FINF, amax, red);
+    block_max_to(d.stats + ST_SOLVE0, amax, red);
+}
+
+// r = f - L p (FP64, 7-point operator with variable z spacing) -> d.r.
+__device__ void pass_resid(const Dom &d, int tile, char *smem, int solve)
+{
+    double *red = (double *)smem;
+    double *sP = red + 8;
+    const MTile t = march_tile(d, tile);
+    const MNbr n = march_nbr(d, t);
+    const int nx = d.nx, nz = d.nz, sz = nx * d.ny, TI = d.cti;
+    const int col = t.j * nx + t.i;
+    const double idx2 = d.idx * d.idx, idy2 = d.idy * d.idy;
+    int k = t.kb;
+    double Pc = d.po[k * sz + col];
+    double Gb = 0.0;
+    if (!(d.bcz == BC_WALL && k == 0)) {
+        const int km = (k == 0) ? nz - 1 : k - 1;
+        Gb = (Pc - d.po[km * sz + col]) * d.idzc[km];
+    }
+    double amax = 0.0;
+    for (; k < t.ke; ++k) {
+        const int c = k * sz + col;
+        const int kp = (k == nz - 1) ? 0 : k + 1;
+        const bool wt = d.bcz == BC_WALL && k == nz - 1;
+        const double Pp = d.po[kp * sz + col];
+        const double fv = d.f[c];
+        double Pe = __shfl_down(Pc, 1, 64), Pw = __shfl_up(Pc, 1, 64);
+        if (!n.she) Pe = d.po[c + n.oe];
+        if (!n.shw) Pw = d.po[c + n.ow];
+        sP[threadIdx.x] = Pc;
+        __syncthreads();
+        const double Pn = n.lyn ? sP[threadIdx.x + TI] : d.po[c + n.on];
+        const double Ps = n.lys ? sP[threadIdx.x - TI] : d.po[c + n.os];
+        __syncthreads();
+        const double ge = n.we ? 0.0 : Pe - Pc, gw = n.ww ? 0.0 : Pc - Pw;
+        const double gn = n.wn ? 0.0 : Pn - Pc, gs = n.ws ? 0.0 : Pc - Ps;
+        const double Gt = wt ? 0.0 : (Pp - Pc) * d.idzc[k];
+        const double r = fv - ((ge - gw) * idx2 + (gn - gs) * idy2 + (Gt - Gb) * d.idzf[k]);
+        if (t.act) {
+            d.r[c] = r;
+            amax = amax_nan(amax, r);
+        }
+        Gb = Gt;
+        Pc = Pp;
+    }
+    block_max_to(d.stats + ST_SOLVE0 + 4 * solve, amax, red);
+}
+
+// Velocity correction of the +faces of each column, marching in k:
+//   u_out = u* - dt [ (1/rho0) G p + (1/rho_face - 1/rho0) G p* ], 0 on walls.
+// With `divcheck`, also max |D u_out|: the -x face from the west lane, the -y
+// face through LDS, the -z face carried from the previous plane (recomputed
+// with the same arithmetic at tile edges).
+__device__ void pass_corr(const Dom &d, int tile, char *smem, bool divcheck)
+{
+    double *red = (double *)smem;
+    double *sP = red + 8, *sS = sP + NT, *sR = sS + NT, *sF = sR + NT;
+    const MTile t = march_tile(d, tile);
+    const MNbr n = march_nbr(d, t);
+    const int nx = d.nx, ny = d.ny, nz = d.nz, sz = nx * ny, TI = d.cti;
+    const int col = t.j * nx + t.i;
+    const double dt = d.dt, ir0 = d.irho0;
+    int k = t.kb;
+    double Pc = d.po[k * sz + col], Sc = d.ps[k * sz + col], Rc = d.rho[k * sz + col];
+    double fb = 0.0;
+    if (divcheck && !(d.bcz == BC_WALL && k == 0)) fb = corr_face(d, 2, t.i, t.j, (k == 0) ? nz - 1 : k - 1);
+    double dmax = 0.0, omax = 0.0;
+    for (; k < t.ke; ++k) {
+        const int c = k * sz + col;
+        const int kp = (k == nz - 1) ? 0 : k + 1;
+        const bool wt = d.bcz == BC_WALL && k == nz - 1;
+        const double Pp = d.po[kp * sz + col], Sp = d.ps[kp * sz + col], Rp = d.rho[kp * sz + col];
+        const double u = d.u[c], v = d.v[c], w = d.w[c];
+        double Pe = __shfl_down(Pc, 1, 64), Se = __shfl_down(Sc, 1, 64), Re = __shfl_down(Rc, 1, 64);
+        if (!n.she) { Pe = d.po[c + n.oe]; Se = d.ps[c + n.oe]; Re = d.rho[c + n.oe]; }
+        sP[threadIdx.x] = Pc;
+        sS[threadIdx.x] = Sc;
+        sR[threadIdx.x] = Rc;
+        __syncthreads();
+        double Pn, Sn, Rn;
+        if (n.lyn) { Pn = sP[threadIdx.x + TI]; Sn = sS[threadIdx.x + TI]; Rn = sR[threadIdx.x + TI]; }
+        else { Pn = d.po[c + n.on]; Sn = d.ps[c + n.on]; Rn = d.rho[c + n.on]; }
+        const double fe = n.we ? 0.0 : u - dt * (ir0 * (Pe - Pc) * d.idx + (2.0 * rcp_nr(Rc + Re) - ir0) * (Se - Sc) * d.idx);
+        const double fn = n.wn ? 0.0 : v - dt * (ir0 * (Pn - Pc) * d.idy + (2.0 * rcp_nr(Rc + Rn) - ir0) * (Sn - Sc) * d.idy);
+        const double hz = d.idzc[k];
+        const double ft = wt ? 0.0 : w - dt * (ir0 * (Pp - Pc) * hz + (rcp_nr(Rc * d.rzlo[k] + Rp * d.rzhi[k]) - ir0) * (Sp - Sc) * hz);
+        if (t.act) {
+            d.uo[c] = fe;
+            d.vo[c] = fn;
+            d.wo[c] = ft;
+            omax = amax_nan(amax_nan(amax_nan(omax, fe), fn), ft);
+        }
+        if (divcheck) {
+            sF[threadIdx.x] = fn;
+            double fw = __shfl_up(fe, 1, 64);
+            __syncthreads();
+            double fs;
+            if (!n.shw) fw = n.ww ? 0.0 : corr_face(d, 0, (t.i == 0) ? nx - 1 : t.i - 1, t.j, k);
+            if (n.lys) fs = sF[threadIdx.x - TI];
+            else fs = n.ws ? 0.0 : corr_face(d, 1, t.i, (t.j == 0) ? ny - 1 : t.j - 1, k);
+            const double dv = (fe - fw) * d.idx + (fn - fs) * d.idy + (ft - fb) * d.idzf[k];
+            if (t.act) dmax = amax_nan(dmax, dv);
+            fb = ft;
+        }
+        __syncthreads();
+        Pc = Pp;
+        Sc = Sp;
+        Rc = Rp;
+    }
+    if (divcheck) block_max_to(d.stats + ST_DIV, dmax, red);
+    block_max_to(d.stats + ST_NONFIN, omax, red);
+}
+
+// Divergence of the stored output velocity (used when outputs alias inputs);
+// tiles of NT consecutive cells (d.ndiv_tiles of them).
+__device__ __forceinline__ void pass_div(const Dom &d, int tile, char *smem)
+{
+    double *red = (double *)smem;
+    const size_t ncell = (size_t)d.nx * d.ny * d.nz;
+    const size_t c = (size_t)tile * NT + threadIdx.x;
+    double dmax = 0.0;
+    if (c < ncell) {
+        size_t plane = (size_t)d.nx * d.ny;
+        int k = (int)(c / plane);
+        size_t rem = c - (size_t)k * plane;
+        int j = (int)(rem / d.nx);
+        int i = (int)(rem - (size_t)j * d.nx);
+        double fw = (i > 0) ? d.uo[c - 1] : (d.bcx == BC_WALL ? 0.0 : d.uo[c + d.nx - 1]);
+        double fs = (j > 0) ? d.vo[c - d.nx] : (d.bcy == BC_WALL ? 0.0 : d.vo[c + (size_t)(d.ny - 1) * d.nx]);
+        double fb = (k > 0) ? d.wo[c - plane] : (d.bcz == BC_WALL ? 0.0 : d.wo[c + (size_t)(d.nz - 1) * plane]);
+        double dv = (d.uo[c] - fw) * d.idx + (d.vo[c] - fs) * d.idy + (d.wo[c] - fb) * d.idzf[k];
+        dmax = fabs(dv);
+    }
+    block_max_to(d.stats + ST_DIV, dmax, red);
+}
+
+// ------------------------------------------------------------------ xfwd
+// Tile = (j tile, k): rows j0 .. j0+rows-1 of plane k of f (or r).  Real
+// FFT by a half-length complex FFT of z[n] = s[2n] + i s[2n+1] and the split
+// X[l] = E + W^l O, X[M-l] = conj(E - W^l O); then the corner turn into S1.
+template <typename T, int SRC>
+__device__ void pass_xfwd(const Dom &d, int tile, char *smem)
+{
+    using C = c2<T>;
+    C *buf = (C *)smem;
+    const int ldr = lds_line(d.M + 1);
+    const int jt = tile % d.ntj, k = tile / d.ntj;
+    const int j0 = jt * d.tj;
+    const int rows = min(d.tj, d.ny - j0);
+    const int nx = d.nx;
+    const double *src = (SRC == SRC_RHS ? d.f : d.r) + ((size_t)k * d.ny + j0) * nx;
+    for (int idx = threadIdx.x; idx < rows * nx; idx += NT) {
+        int r = (int)fdiv((uint32_t)idx, d.dnx);
+        int i = idx - r * nx;
+        ((T *)(buf + r * ldr + pidx(i >> 1)))[i & 1] = (T)src[idx];
+    }
+    __syncthreads();
+    lds_fft<T, false>(buf, ldr, rows, d.fx);
+    const C *twr = (const C *)d.twr;
+    const int M = d.M, half = M / 2;
+    for (int idx = threadIdx.x; idx < rows * (half + 1); idx += NT) {
+        int r = idx / (half + 1);
+        int l = idx - r * (half + 1);
+        C *row = buf + r * ldr;
+        if (l == 0) {
+            C z0 = row[0];
+            row[0] = C{z0.x + z0.y, T(0)};
+            row[pidx(M)] = C{z0.x - z0.y, T(0)};
+        } else if (2 * l == M) {
+            row[pidx(l)] = cconj(row[pidx(l)]);
+        } else {
+            C zl = row[pidx(l)], zm = row[pidx(M - l)];
+            C e = {T(0.5) * (zl.x + zm.x), T(0.5) * (zl.y - zm.y)};
+            // o = (zl - conj(zm)) / (2i)
+            C o = {T(0.5) * (zl.y + zm.y), T(-0.5) * (zl.x - zm.x)};
+            C wo = cmul(twr[l], o);
+            row[pidx(l)] = cadd(e, wo);
+            row[pidx(M - l)] = cconj(csub(e, wo));
+        }
+    }
+    __syncthreads();
+    C *s1 = (C *)d.s1;
+    const int tj = d.tj, nl = d.nl;
+    for (int idx = threadIdx.x; idx < tj * nl; idx += NT) {
+        int l = (int)fdiv((uint32_t)idx, d.dtj);
+        int r = idx - l * tj;
+        if (r < rows) s1[((size_t)k * nl + l) * d.ny + j0 + r] = buf[r * ldr + pidx(l)];
+    }
+}
+
+// ------------------------------------------------------------------- y pass
+// Tile = (k tile, l): columns k0 .. k0+cols-1 of mode l.
+template <typename T, bool INV>
+__device__ void pass_y(const Dom &d, int tile, char *smem)
+{
+    using C = c2<T>;
+    C *buf = (C *)smem;
+    const int kt = tile % d.ntk, l = tile / d.ntk;
+    const int k0 = kt * d.tk;
+    const int cols = min(d.tk, d.nz - k0);
+    const int ny = d.ny, nz = d.nz, nl = d.nl, tk = d.tk;
+    const int ldc = lds_line(ny);
+    C *s1 = (C *)d.s1;
+    C *s2 = (C *)d.s2;
+    if (!INV) {
+        for (int idx = threadIdx.x; idx < cols * ny; idx += NT) {
+            int c = (int)fdiv((uint32_t)idx, d.dnyc);
+            int j = idx - c * ny;
+            buf[c * ldc + pidx(j)] = s1[((size_t)(k0 + c) * nl + l) * ny + j];
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < tk * ny; idx += NT) {
+            int m = (int)fdiv((uint32_t)idx, d.dtk);
+            int c = idx - m * tk;
+            if (c < cols) buf[c * ldc + pidx(m)] = s2[((size_t)l * ny + m) * nz + k0 + c];
+        }
+    }
+    __syncthreads();
+    lds_fft<T, INV>(buf, ldc, cols, d.fy);
+    if (!INV) {
+        for (int idx = threadIdx.x; idx < tk * ny; idx += NT) {
+            int m = (int)fdiv((uint32_t)idx, d.dtk);
+            int c = idx - m * tk;
+            if (c < cols) s2[((size_t)l * ny + m) * nz + k0 + c] = buf[c * ldc + pidx(m)];
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < cols * ny; idx += NT) {
+            int c = (int)fdiv((uint32_t)idx, d.dnyc);
+            int j = idx - c * ny;
+            s1[((size_t)(k0 + c) * nl + l) * ny + j] = buf[c * ldc + pidx(j)];
+        }
+    }
+}
+
+// --------------------------------------------------------------- z solve
+// Lines (l, m) are contiguous in S2.  G lanes cooperate on one line, lane t
+// owning a contiguous chunk of S_t levels (sizes differ by at most one).  The
+// first S_t - 1 levels of a chunk are eliminated locally (Thomas with two
+// extra right-hand sides giving the response to the neighbouring chunks'
+// last unknowns E_{t-1}, E_t), leaving one equation per lane in the E's:
+//   alpha_t E_{t-1} + beta_t E_t + gamma_t E_{t+1} = rho_t,
+// solved by parallel cyclic reduction across the G lanes (cyclic when z is
+// periodic).  The singular mode (l, m) = (0, 0) is made compatible, pinned
+// (last level = 0), solved without wrap, then shifted to zero dzf-weighted
+// mean.  The right-hand side is scaled by 1/(nx ny) (inverse transforms are
+// unnormalised).
+template <typename T, int SMAX>
+__device__ void pass_z(const Dom &d, int tile, char *smem)
+{
+    using C = c2<T>;
+    C *buf = (C *)smem;
+    const int nz = d.nz, G = d.zg;
+    const int lpw = 64 / G;                      // lines per wave
+    const int lpg = d.zlpw;                      // lines per workgroup
+    const long nlines_tot = (long)d.nl * d.ny;
+    const long q0 = (long)tile * lpg;
+    const int nlin = (int)min((long)lpg, nlines_tot - q0);
+    C *s2 = (C *)d.s2;
+    const size_t gbase = (size_t)q0 * nz;
+    const int nelem = nlin * nz;
+    // padded LDS index: one spare slot per 16 elements
+#define ZP(e) ((e) + ((e) >> 4))
+    for (int e = threadIdx.x; e < nelem; e += NT) buf[ZP(e)] = s2[gbase + e];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int t = lane & (G - 1);
+    const int gl = wv * lpw + (lane / G);        // line within the workgroup
+    const bool active = gl < nlin;
+    const int gls = active ? gl : 0;
+    const long q = q0 + gls;
+    const int l = (int)(q / d.ny), m = (int)(q - (long)l * d.ny);
+    const bool sing = (l == 0 && m == 0);
+    const bool cyc = (d.bcz == BC_PER) && !sing;
+    const T *za = (const T *)d.za, *zb = (const T *)d.zb, *zc = (const T *)d.zc, *dzf = (const T *)d.dzf_s;
+    const T sh = ((const T *)d.lamx)[l] + ((const T *)d.lamy)[m];
+    const T scale = (T)d.scale;
+    const int base = nz / G, rem = nz - base * G;
+    const int S = base + (t < rem ? 1 : 0);
+    const int k0 = t * base + min(t, rem);
+    const int mi = S - 1;                        // interior rows
+    const int lbase = lane & ~(G - 1);
+
+    C y[SMAX];
+    T g[SMAX], cp[SMAX];
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+        if (s < S) {
+            C v = buf[ZP(gls * nz + k0 + s)];
+            y[s] = C{v.x * scale, v.y * scale};
+        }
+    }
+    // compatibility of the singular mode: remove the dzf-weighted mean
+    if (sing) {
+        C acc = {T(0), T(0)};
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s)
+            if (s < S) { T w = dzf[k0 + s]; acc.x += w * y[s].x; acc.y += w * y[s].y; }
+        for (int o = 1; o < G; o <<= 1) { acc.x += __shfl_xor(acc.x, o, 64); acc.y += __shfl_xor(acc.y, o, 64); }
+        T il = T(1) / (T)d.lz;
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s)
+            if (s < S) { y[s].x -= acc.x * il; y[s].y -= acc.y * il; }
+        // the pinned level nz-1 is the identity row x = 0
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s)
+            if (s < S && k0 + s == nz - 1) y[s] = C{T(0), T(0)};
+    }
+    // row coefficients (pinned system for the singular mode)
+    auto coef = [&](int k, T &A, T &B, T &Cc) {
+        A = za[k]; Cc = zc[k]; B = zb[k] + sh;
+        if (sing) {
+            if (k == nz - 1) { A = T(0); Cc = T(0); B = T(1); }
+            if (k == nz - 2) Cc = T(0);
+            if (k == 0) A = T(0);
+        }
+    };
+    // local elimination of the interior rows k0 .. k0+mi-1
+    T hlast = T(0);
+    {
+        T cpp = T(0), gp = T(0);
+        C yp = {T(0), T(0)};
+#pragma unroll
+        for (int s = 0; s < SMAX - 1; ++s) {
+            if (s < mi) {
+                T A, B, Cc;
+                coef(k0 + s, A, B, Cc);
+                T a = (s == 0) ? T(0) : A;
+                T inv = T(1) / (B - a * cpp);
+                cp[s] = Cc * inv;
+                y[s] = C{(y[s].x - a * yp.x) * inv, (y[s].y - a * yp.y) * inv};
+                g[s] = ((s == 0) ? -A : -a * gp) * inv;
+                if (s == mi - 1) hlast = -Cc * inv;
+                cpp = cp[s]; yp = y[s]; gp = g[s];
+            }
+        }
+    }
+    T h0 = hlast;
+#pragma unroll
+    for (int s = SMAX - 3; s >= 0; --s) {
+        if (s < mi - 1) {
+            y[s].x -= cp[s] * y[s + 1].x;
+            y[s].y -= cp[s] * y[s + 1].y;
+            g[s] -= cp[s] * g[s + 1];
+            h0 = -cp[s] * h0;
+        }
+    }
+    // E-row of this lane: row ke = k0 + mi
+    T Ae, Be, Ce;
+    coef(k0 + mi, Ae, Be, Ce);
+    C ye = y[0];
+    T gl_last = T(0), hl_last = hlast;
+    C yl_last = {T(0), T(0)};
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+        if (s == mi) ye = y[s];
+        if (s == mi - 1) { yl_last = y[s]; gl_last = g[s]; }
+    }
+    // first interior unknown of the next lane (wraps for a cyclic line)
+    const int nxt = lbase | ((t + 1) & (G - 1));
+    C y0n = {__shfl(y[0].x, nxt, 64), __shfl(y[0].y, nxt, 64)};
+    T g0n = __shfl(g[0], nxt, 64);
+    T h0n = __shfl(h0, nxt, 64);
+    T al = Ae * gl_last;
+    T be = Be + Ae * hl_last + Ce * g0n;
+    T ga = Ce * h0n;
+    C rh = {ye.x - Ae * yl_last.x - Ce * y0n.x, ye.y - Ae * yl_last.y - Ce * y0n.y};
+    // parallel cyclic reduction over the G lanes of the line
+    for (int dd = 1; dd < G; dd <<= 1) {
+        int lo = t - dd, hi = t + dd;
+        bool vlo = cyc || lo >= 0, vhi = cyc || hi < G;
+        int slo = lbase | (lo & (G - 1)), shi = lbase | (hi & (G - 1));
+        T al_lo = __shfl(al, slo, 64), be_lo = __shfl(be, slo, 64), ga_lo = __shfl(ga, slo, 64);
+        T rx_lo = __shfl(rh.x, slo, 64), ry_lo = __shfl(rh.y, slo, 64);
+        T al_hi = __shfl(al, shi, 64), be_hi = __shfl(be, shi, 64), ga_hi = __shfl(ga, shi, 64);
+        T rx_hi = __shfl(rh.x, shi, 64), ry_hi = __shfl(rh.y, shi, 64);
+        if (!vlo) { al_lo = T(0); be_lo = T(1); ga_lo = T(0); rx_lo = T(0); ry_lo = T(0); }
+        if (!vhi) { al_hi = T(0); be_hi = T(1); ga_hi = T(0); rx_hi = T(0); ry_hi = T(0); }
+        T k1 = al / be_lo, k2 = ga / be_hi;
+        T nal = -k1 * al_lo, nga = -k2 * ga_hi;
+        T nbe = be - k1 * ga_lo - k2 * al_hi;
+        rh = C{rh.x - k1 * rx_lo - k2 * rx_hi, rh.y - k1 * ry_lo - k2 * ry_hi};
+        al = nal; be = nbe; ga = nga;
+    }
+    T den = cyc ? (al + be + ga) : be;
+    C E = {rh.x / den, rh.y / den};
+    const int prv = lbase | ((t - 1) & (G - 1));
+    C Ep = {__shfl(E.x, prv, 64), __shfl(E.y, prv, 64)};
+    // reconstruction x_s = y_s + g_s E_{t-1} + h_s E_t
+    {
+        T h = hlast;
+#pragma unroll
+        for (int s = SMAX - 2; s >= 0; --s) {
+            if (s < mi) {
+                y[s] = C{y[s].x + g[s] * Ep.x + h * E.x, y[s].y + g[s] * Ep.y + h * E.y};
+                if (s > 0) h = -cp[s - 1] * h;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s)
+            if (s == mi) y[s] = E;
+    }
+    // gauge of the singular mode: zero dzf-weighted mean
+    if (sing) {
+        C acc = {T(0), T(0)};
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s)
+            if (s < S) { T w = dzf[k0 + s]; acc.x += w * y[s].x; acc.y += w * y[s].y; }
+        for (int o = 1; o < G; o <<= 1) { acc.x += __shfl_xor(acc.x, o, 64); acc.y += __shfl_xor(acc.y, o, 64); }
+        T il = T(1) / (T)d.lz;
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s)
+            if (s < S) { y[s].x -= acc.x * il; y[s].y -= acc.y * il; }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s)
+            if (s < S) buf[ZP(gl * nz + k0 + s)] = y[s];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nelem; e += NT) s2[gbase + e] = buf[ZP(e)];
+#undef ZP
+}
+
+// ------------------------------------------------------------------ xinv
+// Tile = (j tile, k).  Inverse real FFT of rows j0.. of plane k from S1;
+// MODE store: p = value; accum: p += value (refinement update).
+template <typename T, int MODE>
+__device__ void pass_xinv(const Dom &d, int tile, char *smem, int solve)
+{
+    using C = c2<T>;
+    C *buf = (C *)smem;
+    const int ldr = lds_line(d.M + 1);
+    double *red = (double *)(smem + (size_t)d.tj * ldr * sizeof(C));
+    const int jt = tile % d.ntj, k = tile / d.ntj;
+    const int j0 = jt * d.tj;
+    const int rows = min(d.tj, d.ny - j0);
+    const int nx = d.nx, nl = d.nl, tj = d.tj;
+    const C *s1 = (const C *)d.s1;
+    for (int idx = threadIdx.x; idx < tj * nl; idx += NT) {
+        int l = (int)fdiv((uint32_t)idx, d.dtj);
+        int r = idx - l * tj;
+        if (r < rows) buf[r * ldr + pidx(l)] = s1[((size_t)k * nl + l) * d.ny + j0 + r];
+    }
+    __syncthreads();
+    // Z[l] = E + i O,  E = X[l] + conj(X[M-l]),  O = (X[l] - conj(X[M-l])) conj(W^l)
+    const C *twr = (const C *)d.twr;
+    const int M = d.M, half = M / 2;
+    for (int idx = threadIdx.x; idx < rows * (half + 1); idx += NT) {
+        int r = idx / (half + 1);
+        int l = idx - r * (half + 1);
+        C *row = buf + r * ldr;
+        if (l == 0) {
+            T a = row[0].x, b = row[pidx(M)].x;
+            row[0] = C{a + b, a - b};
+        } else {
+            C xl = row[pidx(l)], xm = row[pidx(M - l)];
+            C e = {xl.x + xm.x, xl.y - xm.y};
+            C df = {xl.x - xm.x, xl.y + xm.y};
+            C o = cmul(df, cconj(twr[l]));
+            C io = {-o.y, o.x};
+            row[pidx(l)] = cadd(e, io);
+            if (2 * l != M) {
+                // Z[M-l] = conj(E) + i conj(O)
+                C ioc = {o.y, o.x};
+                row[pidx(M - l)] = cadd(cconj(e), ioc);
+            }
+        }
+    }
+    __syncthreads();
+    lds_fft<T, true>(buf, ldr, rows, d.fx);
+    // accumulation also removes the FP64 volume mean of the previous p: the
+    // residual cannot see a constant, so the FP32 gauge error of earlier
+    // solves is cancelled here
+    const double shift = (MODE == XOUT_ACCUM) ? d.pmean[0] : 0.0;
+    double emax = 0.0, pmax = 0.0, psum = 0.0;
+    for (int idx = threadIdx.x; idx < rows * nx; idx += NT) {
+        int r = (int)fdiv((uint32_t)idx, d.dnx);
+        int i = idx - r * nx;
+        double val = (double)((const T *)(buf + r * ldr + pidx(i >> 1)))[i & 1];
+        size_t g = ((size_t)k * d.ny + j0 + r) * nx + i;
+        double pv = (MODE == XOUT_STORE) ? val : (d.po[g] - shift) + val;
+        d.po[g] = pv;
+        psum += pv;
+        emax = amax_nan(emax, val);
+        pmax = amax_nan(pmax, pv);
+    }
+    if (d.ppart) {
+        double ts = block_sum(psum, red);
+        if (threadIdx.x == 0) d.ppart[tile] = ts * d.dzf[k];
+    }
+    block_max_to(d.stats + ST_SOLVE0 + 4 * solve + 1, emax, red);
+    block_max_to(d.stats + ST_SOLVE0 + 4 * solve + 2, pmax, red);
+}
+
+// Volume mean of p from the x-tile partial sums, summed in a fixed order by
+// one workgroup: pmean[0] = sum / (nx ny lz).
+__device__ __forceinline__ void pass_pmean(const Dom &d, char *smem)
+{
+    double *red = (double *)smem;
+    const int nt = d.ntj * d.nz;
+    double s = 0.0;
+    for (int t = threadIdx.x; t < nt; t += NT) s += d.ppart[t];
+    double tot = block_sum(s, red);
+    if (threadIdx.x == 0) d.pmean[0] = tot / ((double)d.nx * (double)d.ny * d.lz);
+}
+
+} // namespace pcx

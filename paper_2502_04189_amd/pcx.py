@@ -1,0 +1,240 @@
+"""Python binding of libpcx (ctypes).  Argument marshalling only: every pass
+of the step runs in the HIP library; torch provides device memory and
+streams.  Raises ImportError when the library has not been built."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpcx.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "pcx.h")
+
+PCX_OK, PCX_ERR_INVALID, PCX_ERR_UNSUPPORTED, PCX_ERR_NOMEM, PCX_ERR_HIP = 0, 1, 2, 3, 4
+PCX_ERR_NOT_CONVERGED, PCX_ERR_NONFINITE = 5, 6
+PCX_FP64, PCX_FP32_REFINED = 0, 1
+
+_DP = C.POINTER(C.c_double)
+
+
+class PcxGrid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("lx", C.c_double), ("ly", C.c_double), ("zf", _DP),
+                ("bc_x", C.c_int32), ("bc_y", C.c_int32), ("bc_z", C.c_int32)]
+
+
+class PcxOptions(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("rtol", C.c_double), ("max_iters", C.c_int32),
+                ("fixed_iters", C.c_int32), ("check_finite", C.c_int32), ("autotune", C.c_int32),
+                ("tune_cache", C.c_char_p)]
+
+
+class PcxReport(C.Structure):
+    _fields_ = [("solves", C.c_int32), ("converged", C.c_int32), ("f_inf", C.c_double),
+                ("rel_residual", C.c_double), ("max_div_abs", C.c_double),
+                ("max_div_rel", C.c_double), ("mean_p", C.c_double),
+                ("last_update_inf", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class PcxDomain(C.Structure):
+    _fields_ = [("grid", PcxGrid), ("dt", C.c_double), ("rho0", C.c_double),
+                ("rho", C.c_void_p), ("p_star", C.c_void_p), ("u", C.c_void_p),
+                ("v", C.c_void_p), ("w", C.c_void_p), ("u_out", C.c_void_p),
+                ("v_out", C.c_void_p), ("w_out", C.c_void_p), ("p_out", C.c_void_p)]
+
+
+_lib = None
+
+
+def header_symbols():
+    """Function names declared in include/pcx.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(pcx_[a-z0-9_]+)\s*\(", txt)))
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libpcx.so is not built ({LIB_PATH}); run paper_2502_04189_amd.build.build()")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, dbl = C.c_void_p, C.c_int32, C.c_double
+    st = C.c_int
+    sig = {
+        "pcx_plan_create": (st, [C.POINTER(PcxGrid), C.POINTER(PcxOptions), C.POINTER(vp)]),
+        "pcx_plan_workspace_bytes": (st, [vp, C.POINTER(C.c_size_t)]),
+        "pcx_step": (st, [vp, dbl, dbl] + [vp] * 9 + [vp, C.POINTER(PcxReport)]),
+        "pcx_plan_destroy": (st, [vp]),
+        "pcx_plan_set_timing": (st, [vp, i32]),
+        "pcx_plan_pass_times": (st, [vp, _DP, i32, C.POINTER(i32)]),
+        "pcx_plan_pass_name": (C.c_char_p, [vp, i32]),
+        "pcx_batch_create": (st, [C.POINTER(PcxDomain), i32, C.POINTER(PcxOptions), vp, C.POINTER(vp)]),
+        "pcx_batch_launch": (st, [vp, vp]),
+        "pcx_batch_reports": (st, [vp, C.POINTER(PcxReport)]),
+        "pcx_batch_destroy": (st, [vp]),
+        "pcx_rho_min": (st, [vp, C.c_int64, vp, _DP]),
+        "pcx_refine_should_stop": (i32, [dbl, dbl, dbl, dbl, dbl]),
+        "pcx_status_str": (C.c_char_p, [st]),
+        "pcx_last_error": (C.c_char_p, []),
+        "pcx_abi_version": (i32, []),
+    }
+    for name, (res, args) in sig.items():
+        if hasattr(L, name):
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+    _lib = L
+    return L
+
+
+class PcxError(RuntimeError):
+    def __init__(self, status, where):
+        L = lib()
+        msg = L.pcx_last_error().decode()
+        super().__init__(f"{where}: {L.pcx_status_str(status).decode()}: {msg}")
+        self.status = status
+
+
+def _check(status, where):
+    if status != PCX_OK:
+        raise PcxError(status, where)
+
+
+def make_grid(gs):
+    """pcx_grid from a workloads.GridSpec (keeps zf alive on the struct)."""
+    import numpy as np
+    zf = np.ascontiguousarray(gs.zf, dtype=np.float64)
+    g = PcxGrid(gs.nx, gs.ny, gs.nz, gs.lx, gs.ly, zf.ctypes.data_as(_DP), gs.bcx, gs.bcy, gs.bcz)
+    g._zf_keep = zf
+    return g
+
+
+def make_options(precision="fp64", rtol=1e-10, max_iters=8, fixed_iters=0, check_finite=False,
+                 autotune=False, tune_cache=None):
+    p = PCX_FP64 if precision in ("fp64", PCX_FP64) else PCX_FP32_REFINED
+    return PcxOptions(p, rtol, max_iters, fixed_iters, 1 if check_finite else 0, 1 if autotune else 0,
+                      tune_cache.encode() if tune_cache else None)
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t, shape, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """pcx_plan for one grid.  step() takes torch float64 CUDA tensors of
+    shape (nz, ny, nx)."""
+
+    def __init__(self, grid, precision="fp64", rtol=1e-10, max_iters=8, fixed_iters=0, check_finite=False,
+                 autotune=False, tune_cache=None):
+        L = lib()
+        self.gs = grid
+        self._g = make_grid(grid)
+        self._o = make_options(precision, rtol, max_iters, fixed_iters, check_finite, autotune, tune_cache)
+        h = C.c_void_p()
+        _check(L.pcx_plan_create(C.byref(self._g), C.byref(self._o), C.byref(h)), "pcx_plan_create")
+        self._h = h
+        self.shape = (grid.nz, grid.ny, grid.nx)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pcx_plan_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def workspace_bytes(self):
+        n = C.c_size_t()
+        _check(lib().pcx_plan_workspace_bytes(self._h, C.byref(n)), "pcx_plan_workspace_bytes")
+        return n.value
+
+    def step(self, dt, rho0, rho, pstar, u, v, w, u_out=None, v_out=None, w_out=None, p_out=None,
+             stream=None, report=True, raise_on_status=True):
+        import torch
+        sh = self.shape
+        outs = []
+        for o in (u_out, v_out, w_out, p_out):
+            outs.append(o if o is not None else torch.empty(sh, dtype=torch.float64, device=rho.device))
+        ptrs = [_ptr(t, sh, n) for t, n in zip((rho, pstar, u, v, w) + tuple(outs),
+                                               ("rho", "pstar", "u", "v", "w", "u_out", "v_out", "w_out", "p_out"))]
+        rep = PcxReport()
+        st = lib().pcx_step(self._h, float(dt), float(rho0), *ptrs, _stream_handle(stream),
+                            C.byref(rep) if report else None)
+        self.last_status = st
+        if raise_on_status and st != PCX_OK:
+            raise PcxError(st, "pcx_step")
+        return outs[0], outs[1], outs[2], outs[3], (rep.as_dict() if report else None)
+
+    def set_timing(self, on=True):
+        _check(lib().pcx_plan_set_timing(self._h, 1 if on else 0), "pcx_plan_set_timing")
+
+    def pass_times(self, cap=4096):
+        """(pass name, ms) of every pass of every step since set_timing()."""
+        buf = (C.c_double * cap)()
+        n = C.c_int32()
+        _check(lib().pcx_plan_pass_times(self._h, buf, cap, C.byref(n)), "pcx_plan_pass_times")
+        return [(lib().pcx_plan_pass_name(self._h, i).decode(), buf[i]) for i in range(min(n.value, cap))]
+
+
+class Batch:
+    """pcx_batch over a list of (GridSpec, dt, rho0, tensors...) domains."""
+
+    def __init__(self, domains, precision="fp32_refined", rtol=1e-10, max_iters=8, fixed_iters=0,
+                 stream=None, autotune=False, tune_cache=None):
+        L = lib()
+        self._keep = []
+        arr = (PcxDomain * len(domains))()
+        for i, d in enumerate(domains):
+            g = make_grid(d["grid"])
+            self._keep.append(g)
+            sh = (d["grid"].nz, d["grid"].ny, d["grid"].nx)
+            names = ("rho", "pstar", "u", "v", "w", "u_out", "v_out", "w_out", "p_out")
+            ptrs = [_ptr(d[n], sh, n).value for n in names]
+            arr[i] = PcxDomain(g, float(d["dt"]), float(d["rho0"]), *ptrs)
+        self._arr = arr
+        self._o = make_options(precision, rtol, max_iters, fixed_iters, False, autotune, tune_cache)
+        h = C.c_void_p()
+        _check(L.pcx_batch_create(arr, len(domains), C.byref(self._o), _stream_handle(stream), C.byref(h)),
+               "pcx_batch_create")
+        self._h = h
+        self.n = len(domains)
+
+    def launch(self, stream=None):
+        _check(lib().pcx_batch_launch(self._h, _stream_handle(stream)), "pcx_batch_launch")
+
+    def reports(self, raise_on_status=False):
+        reps = (PcxReport * self.n)()
+        st = lib().pcx_batch_reports(self._h, reps)
+        if raise_on_status or st not in (PCX_OK, PCX_ERR_NOT_CONVERGED):
+            _check(st, "pcx_batch_reports")
+        return [r.as_dict() for r in reps], st
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pcx_batch_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+
+def rho_min(rho, stream=None):
+    out = C.c_double()
+    _check(lib().pcx_rho_min(C.c_void_p(rho.data_ptr()), rho.numel(), _stream_handle(stream), C.byref(out)),
+           "pcx_rho_min")
+    return out.value

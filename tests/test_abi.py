@@ -1,0 +1,86 @@
+"""C-ABI library checks that need no GPU: the library loads, exports every
+function include/pcx.h declares, validates descriptors on the host and
+reports a missing device as PCX_ERR_HIP."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_2502_04189_amd import pcx as P
+from paper_2502_04189_amd import workloads as W
+
+
+@pytest.fixture(scope="module")
+def L():
+    return P.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    syms = P.header_symbols()
+    assert len(syms) >= 15
+    missing = [s for s in syms if not hasattr(L, s)]
+    assert not missing, missing
+    assert L.pcx_abi_version() == 1
+
+
+def test_status_strings(L):
+    for s in range(7):
+        assert L.pcx_status_str(s).decode().startswith("PCX_")
+
+
+def _create(L, gs, opts=None):
+    g = P.make_grid(gs)
+    h = C.c_void_p()
+    st = L.pcx_plan_create(C.byref(g), C.byref(opts) if opts is not None else None, C.byref(h))
+    if st == 0:
+        L.pcx_plan_destroy(h)
+    return st
+
+
+def test_descriptor_validation(L):
+    ok = W.GridSpec(32, 32, 16, 1.0, 1.0, W.zf_uniform(16, 1.0))
+    bad_z = ok.zf.copy()
+    bad_z[5] = bad_z[4]
+    cases = [
+        (W.GridSpec(1, 32, 16, 1.0, 1.0, ok.zf), P.PCX_ERR_INVALID),
+        (W.GridSpec(32, 32, 16, 0.0, 1.0, ok.zf), P.PCX_ERR_INVALID),
+        (W.GridSpec(31, 32, 16, 1.0, 1.0, ok.zf), P.PCX_ERR_INVALID),      # odd periodic nx
+        (W.GridSpec(32, 32, 16, 1.0, 1.0, bad_z), P.PCX_ERR_INVALID),      # non-increasing zf
+        (W.GridSpec(32, 32, 16, 1.0, 1.0, ok.zf, 0, 0, 7), P.PCX_ERR_INVALID),
+        (W.GridSpec(40, 32, 16, 1.0, 1.0, ok.zf), P.PCX_ERR_UNSUPPORTED),  # 40 = 2^3 5
+        (W.GridSpec(8192, 32, 16, 1.0, 1.0, ok.zf), P.PCX_ERR_UNSUPPORTED),
+        (W.GridSpec(32, 32, 2048, 1.0, 1.0, W.zf_uniform(2048, 1.0)), P.PCX_ERR_UNSUPPORTED),
+    ]
+    for gs, want in cases:
+        assert _create(L, gs) == want, (gs.nx, gs.ny, gs.nz)
+    assert "must" in L.pcx_last_error().decode() or "support" in L.pcx_last_error().decode()
+    h = C.c_void_p()
+    assert L.pcx_plan_create(None, None, C.byref(h)) == P.PCX_ERR_INVALID
+    assert L.pcx_step(None, 1.0, 1.0, *([None] * 9), None, None) == P.PCX_ERR_INVALID
+
+
+def test_missing_device_is_hip_error(L):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    gs = W.GridSpec(32, 32, 16, 1.0, 1.0, W.zf_uniform(16, 1.0))
+    assert _create(L, gs) == P.PCX_ERR_HIP
+    assert "device" in L.pcx_last_error().decode()
+
+
+def test_refine_stop_logic(L):
+    """Host stop test on fake residual/update sequences: the residual must be
+    within rtol and the error left after the last update, estimated from the
+    observed contraction q = |e_s|/|e_s-1| as q |e_s| / (1 - q), must be below
+    0.1 rtol |p|."""
+    rtol = 1e-10
+    # (rel_residual, |e_s|, |e_s-1|) with |p| = 1
+    seq = [(4e-6, 1.0, 0.0),        # first solve: no rate yet
+           (2e-11, 1e-4, 1.0),      # residual fine, but q |e| = 1e-8 left
+           (2e-11, 1e-8, 1e-4),     # q = 1e-4: about 1e-12 left -> stop
+           (5e-10, 1e-12, 1e-8),    # residual above rtol
+           (1e-12, 9e-9, 1e-8)]     # q = 0.9: about 8e-8 left
+    got = [L.pcx_refine_should_stop(r, e, ep, 1.0, rtol) for r, e, ep in seq]
+    assert got == [0, 0, 1, 0, 0]
+    assert L.pcx_refine_should_stop(float("nan"), 0.0, 1.0, 1.0, rtol) == 0
+    assert L.pcx_refine_should_stop(1e-12, 2.0, 1.0, 1.0, rtol) == 0     # diverging

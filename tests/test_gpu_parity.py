@@ -1,0 +1,93 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Tolerances (max-norm relative error per field): FP64 path 1e-12; FP32 with
+FP64 refinement 1e-10; relative post-correction divergence likewise.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2502_04189_amd import workloads as W
+from tests import manufactured as M
+from tests.gpu_util import errors, run_plan, to_dev
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+REF_TOL = 1e-10
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pcx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2502_04189_amd import pcx as P
+    P.lib()
+    return P
+
+
+def _oracle(orc, case):
+    g = orc.Grid.from_workload(case.grid)
+    uo, vo, wo, p, d = orc.step(g, case.dt, case.rho0, *case.fields())
+    return [uo, vo, wo, p], d
+
+
+def test_config0_fp64(pcx, orc):
+    case = W.config0()
+    _say("case config0 fp64 32^3")
+    plan = pcx.Plan(case.grid, "fp64")
+    got, rep = run_plan(plan, case)
+    ref, d = _oracle(orc, case)
+    e = errors(got, ref)
+    _say(f"errors {e} report {rep}")
+    assert max(e.values()) <= FP64_TOL
+    assert rep["max_div_rel"] <= FP64_TOL
+    assert abs(rep["mean_p"]) <= 1e-13 * np.abs(ref[3]).max()
+    assert np.all(got[2][-1] == 0.0)
+
+
+SMALL = [
+    ((48, 36, 20), (0, 0, 1), 1.8),
+    ((64, 96, 33), (0, 0, 0), 0.0),
+    ((96, 48, 64), (0, 0, 1), 1.2),
+    ((6, 4, 5), (0, 0, 1), 1.5),
+    ((8, 8, 3), (0, 0, 0), 0.0),
+    ((2, 2, 2), (0, 0, 1), 0.0),
+    ((24, 18, 7), (0, 0, 0), 1.1),
+    ((128, 32, 96), (0, 0, 0), 0.0),
+]
+
+
+@pytest.mark.parametrize("dims,bc,stretch", SMALL)
+def test_small_fp64(pcx, orc, dims, bc, stretch):
+    case = W.random_case(3 + sum(dims), *dims, *bc, stretch=stretch)
+    _say(f"case {case.name} fp64")
+    plan = pcx.Plan(case.grid, "fp64")
+    got, rep = run_plan(plan, case)
+    ref, d = _oracle(orc, case)
+    e = errors(got, ref)
+    _say(f"errors {e} div {rep['max_div_rel']:.3e}")
+    assert max(e.values()) <= FP64_TOL
+    assert rep["max_div_rel"] <= FP64_TOL
+
+
+@pytest.mark.parametrize("dims,bc,stretch", [((32, 32, 32), (0, 0, 1), 0.0), ((48, 36, 20), (0, 0, 1), 1.8),
+                                             ((64, 96, 33), (0, 0, 0), 0.0)])
+def test_small_refined(pcx, orc, dims, bc, stretch):
+    case = W.config0() if dims == (32, 32, 32) else W.random_case(5 + sum(dims), *dims, *bc, stretch=stretch)
+    _say(f"case {case.name} fp32_refined")
+    plan = pcx.Plan(case.grid, "fp32_refined")
+    got, rep = run_plan(plan, case)
+    ref, d = _oracle(orc, case)
+    e = errors(got, ref)
+    _say(f"errors {e} report {rep}")
+    assert rep["converged"] == 1
+    assert max(e.values()) <= REF_TOL
+    assert rep["max_div_rel"] <= REF_TOL
