@@ -90,6 +90,39 @@ def summarize_passes(passes, steps):
     return {k: {"ms_avg": v[0] / v[1], "launches_per_step": v[1] / steps} for k, v in agg.items()}
 
 
+def src_hash():
+    """Hash of the HIP sources (same definition as in the profile summaries)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2502_04189_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+# pass name -> kernel-name prefix in the rocprofv3 summaries
+KERNEL_OF_PASS = {"correct_div": "pcx::k_corr", "rhs_stencil": "pcx::k_rhs", "x_fft_fwd": "void pcx::k_xfwd<double, 0",
+                  "y_fft_fwd": "void pcx::k_y<double, false", "y_fft_inv": "void pcx::k_y<double, true",
+                  "z_solve": "void pcx::k_z<double", "x_fft_inv_store_p": "void pcx::k_xinv<double, 0"}
+
+
+def measured_traffic(pass_name, profile="fp64_512cube_step"):
+    """HBM bytes per launch of the kernel behind a pass, from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, calibrated), or
+    None when the kernel sources changed since the counters were taken."""
+    fn = os.path.join(ROOT, "profiles", profile + "_traffic.json")
+    if not os.path.exists(fn):
+        return None
+    d = json.load(open(fn))
+    if d.get("src_hash") != src_hash():
+        return None
+    pre = KERNEL_OF_PASS.get(pass_name)
+    for k, v in d["kernels"].items():
+        if pre and k.startswith(pre):
+            return int(v["fetch_bytes"] + v["write_bytes"])
+    return None
+
+
 def roofline(pass_summary, gs, csz):
     # dominant kernel = largest total time per step
     best = max(pass_summary.items(), key=lambda kv: kv[1]["ms_avg"] * kv[1]["launches_per_step"])
@@ -97,7 +130,7 @@ def roofline(pass_summary, gs, csz):
     by = kernel_bytes(name, gs, csz)
     gbs = by / (s["ms_avg"] * 1e-3) / 1e9
     return name, {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                  "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name) if csz == 16 else None,
                   "kernel": name, "bytes_per_launch": by, "ms_per_launch": round(s["ms_avg"], 4)}
 
 

@@ -174,7 +174,7 @@ extern "C" pcx_status pcx_batch_create(const pcx_domain *domains, int32_t n, con
             if (st != PCX_OK) { batch_free(B); return st; }
             cache.store(B->grids[i], B->prec, tp, rc);
         }
-        choose_shapes(B->grids[i], B->prec, have || o.autotune ? &tp : nullptr, sh);
+        choose_shapes(B->grids[i], B->prec, have || o.autotune ? &tp : nullptr, sh, true);
         pcx_status st = build_domain(B->grids[i], B->prec, sh, have || o.autotune ? &rc : nullptr, B->tables[i], B->doms[i]);
         if (st != PCX_OK) { batch_free(B); return st; }
         B->smax = std::max(B->smax, sh.smax);
@@ -219,13 +219,36 @@ extern "C" pcx_status pcx_batch_create(const pcx_domain *domains, int32_t n, con
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         return (long)B->grids[a].nx * B->grids[a].ny * B->grids[a].nz > (long)B->grids[b].nx * B->grids[b].ny * B->grids[b].nz;
     });
+    // items: runs of consecutive tiles of one (domain, phase), sized to about
+    // 256 KB of HBM traffic so that the per-item queue and fence cost stays
+    // small next to the work
     std::vector<Item> items;
     std::vector<unsigned> need((size_t)n * tab.nphase);
+    const size_t target = 256 * 1024;
     for (int p = 0; p < tab.nphase; ++p)
         for (int i : order) {
-            long t = tiles_of(B->doms[i], tab.kind[p]);
-            need[(size_t)i * tab.nphase + p] = (unsigned)t;
-            for (long k = 0; k < t; ++k) items.push_back(Item{(uint16_t)i, (uint16_t)p, (uint32_t)k});
+            const Dom &d = B->doms[i];
+            const long t = tiles_of(d, tab.kind[p]);
+            const size_t sp = (size_t)d.nl * d.ny * d.nz * csz;
+            const size_t cells = (size_t)d.nx * d.ny * d.nz;
+            size_t bytes = 0;
+            switch (tab.kind[p]) {
+            case PK_RHS: bytes = 48 * cells; break;
+            case PK_RESID: bytes = 24 * cells; break;
+            case PK_CORR: bytes = 72 * cells; break;
+            case PK_XINV_ACCUM: bytes = sp + 16 * cells; break;
+            case PK_PMEAN: bytes = 0; break;
+            case PK_XFWD_RHS:
+            case PK_XFWD_RESID:
+            case PK_XINV_STORE: bytes = sp + 8 * cells; break;
+            default: bytes = 2 * sp; break;
+            }
+            const size_t per_tile = std::max<size_t>(1, bytes / (size_t)t);
+            const long g = std::max(1L, std::min(t, (long)(target / per_tile)));
+            long cnt = 0;
+            for (long k = 0; k < t; k += g, ++cnt)
+                items.push_back(Item{(uint16_t)i, (uint16_t)p, (uint32_t)k, (uint32_t)std::min(g, t - k), 0u});
+            need[(size_t)i * tab.nphase + p] = (unsigned)cnt;
         }
     B->nitems = (int)items.size();
     BCHK(hipMalloc(&B->items, items.size() * sizeof(Item)));

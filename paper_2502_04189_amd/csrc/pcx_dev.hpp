@@ -21,7 +21,8 @@ namespace pcx {
 
 constexpr int NT = 256;       // threads per workgroup (4 wave64)
 constexpr int MAXST = 16;     // max FFT stages
-constexpr int PPT = 16;       // complex points per thread per FFT stage
+constexpr int PPT = 16;       // complex points per thread per FFT stage (at NT threads)
+constexpr int MAXPTS = PPT * NT; // most complex points one workgroup transforms at once
 constexpr int NSTAT = 64;     // reduction slots per domain
 constexpr int MAXIT = 12;     // max refinement solves tracked
 
@@ -65,7 +66,8 @@ struct Dom {
     int zg, zlpw, nzt;                // z lanes per line, lines per WG, z tiles
     int ncell_tiles;                  // correction tiles (see pass_corr)
     int ndiv_tiles;                   // divergence-only tiles (NT cells each)
-    int cti, ctj, cnti, cntj, ckc, cnk; // correction tile TI x TJ cells, k chunk
+    int cti, ctj, cnti, cntj, ckc, cnk; // marching tile TI x TJ cells, k chunk
+    int mth, yth, xth;                // threads of the marching, y and x workgroups
     FastDiv dnx, dny, dtj, dtk, dnyc, dcti;
     double dx, dy, idx, idy, dt, rho0, irho0, lz, scale;
     // z tables (FP64): dzf, 1/dzf, 1/dzc, rho interpolation weights
@@ -170,11 +172,11 @@ __host__ __device__ constexpr int lds_line(int n) { return (((n - 1) + ((n - 1) 
 //   twiddle W_{ns R}^{(j mod ns) r}
 //   outputs y[line][(j / ns) ns R + (j mod ns) + r ns]
 // Results are held in registers across a barrier, so the stage is in place.
-template <typename T, bool INV, int R>
+template <typename T, bool INV, int R, int NTH>
 __device__ __forceinline__ void fft_stage(c2<T> *buf, int ldb, int nlines, const FftDesc &fd, int s)
 {
     using C = c2<T>;
-    constexpr int K = (PPT + R - 1) / R;
+    constexpr int K = (MAXPTS / NTH + R - 1) / R;
     const int nb = fd.n / R;
     const int total = nlines * nb;
     const int ns = fd.ns[s];
@@ -184,7 +186,7 @@ __device__ __forceinline__ void fft_stage(c2<T> *buf, int ldb, int nlines, const
     int lo[K], oo[K];
 #pragma unroll
     for (int t = 0; t < K; ++t) {
-        int b = threadIdx.x + t * NT;
+        int b = threadIdx.x + t * NTH;
         lo[t] = -1;
         oo[t] = 0;
         if (b < total) {
@@ -222,15 +224,15 @@ __device__ __forceinline__ void fft_stage(c2<T> *buf, int ldb, int nlines, const
 
 // Complex FFT (unnormalised) of nlines LDS lines; all threads participate.
 // Entry and exit are barrier-separated from the caller's LDS traffic.
-template <typename T, bool INV>
+template <typename T, bool INV, int NTH = NT>
 __device__ void lds_fft(c2<T> *buf, int ldb, int nlines, const FftDesc &fd)
 {
     for (int s = 0; s < fd.nst; ++s) {
         switch (fd.rad[s]) {
-        case 2: fft_stage<T, INV, 2>(buf, ldb, nlines, fd, s); break;
-        case 3: fft_stage<T, INV, 3>(buf, ldb, nlines, fd, s); break;
-        case 4: fft_stage<T, INV, 4>(buf, ldb, nlines, fd, s); break;
-        default: fft_stage<T, INV, 8>(buf, ldb, nlines, fd, s); break;
+        case 2: fft_stage<T, INV, 2, NTH>(buf, ldb, nlines, fd, s); break;
+        case 3: fft_stage<T, INV, 3, NTH>(buf, ldb, nlines, fd, s); break;
+        case 4: fft_stage<T, INV, 4, NTH>(buf, ldb, nlines, fd, s); break;
+        default: fft_stage<T, INV, 8, NTH>(buf, ldb, nlines, fd, s); break;
         }
     }
 }
@@ -245,6 +247,7 @@ __device__ __forceinline__ double wave_max(double v)
 
 // Block-wide max of non-negative values (NaN propagates), then one atomicMax
 // on the uint64 bit pattern (order-preserving for non-negative doubles).
+template <int NTH = NT>
 __device__ __forceinline__ void block_max_to(unsigned long long *slot, double v, double *red)
 {
     // keep NaN visible: fmax drops NaN, so map NaN to +Inf-plus pattern
@@ -261,13 +264,14 @@ __device__ __forceinline__ void block_max_to(unsigned long long *slot, double v,
     __syncthreads();
     if (threadIdx.x == 0) {
         double m = red[0];
-        for (int i = 1; i < NT / 64; ++i) m = (red[i] != red[i] || red[i] > m) ? red[i] : m;
+        for (int i = 1; i < NTH / 64; ++i) m = (red[i] != red[i] || red[i] > m) ? red[i] : m;
         atomicMax(slot, (unsigned long long)__double_as_longlong(m));
     }
 }
 
 // Deterministic block-wide sum (fixed shuffle tree, then waves in order);
 // the result is valid in thread 0.
+template <int NTH = NT>
 __device__ __forceinline__ double block_sum(double v, double *red)
 {
 #pragma unroll
@@ -277,7 +281,7 @@ __device__ __forceinline__ double block_sum(double v, double *red)
     __syncthreads();
     double t = 0.0;
     if (threadIdx.x == 0)
-        for (int i = 0; i < NT / 64; ++i) t += red[i];
+        for (int i = 0; i < NTH / 64; ++i) t += red[i];
     return t;
 }
 

@@ -129,18 +129,22 @@ static int pow2_floor(long v)
     return p;
 }
 
-// Tile shapes: rows per x tile, columns per y tile, z lanes per line.
-void choose_shapes(const pcx_grid &g, int prec, const TuneParams *tp, Shapes &sh)
+// Tile shapes: rows per x tile, columns per y tile (with the y workgroup
+// size), z lanes per line, marching workgroup size.  Corner-turn segments are
+// kept at 128 bytes (8 FP64 or 16 FP32 complex values).  The batched form runs
+// every pass in 256-thread workgroups.
+void choose_shapes(const pcx_grid &g, int prec, const TuneParams *tp, Shapes &sh, bool batch)
 {
     const int M = g.nx / 2;
     const size_t csz = prec == PREC_F64 ? 16 : 8;
     const long lds_cap = 80 * 1024;
-    int tj = pow2_floor(std::max(1, (PPT * NT) / std::max(M, 1)));
+    const int seg = prec == PREC_F64 ? 8 : 16;
+    int tj = pow2_floor(std::max(1, MAXPTS / std::max(M, 1)));
     tj = std::min(tj, pow2_floor(lds_cap / (long)(lds_line(M + 1) * csz)));
-    tj = std::min(tj, prec == PREC_F64 ? 8 : 16);
-    int tk = pow2_floor(std::max(1, (PPT * NT) / g.ny));
+    tj = std::min(tj, seg);
+    int tk = pow2_floor(std::max(1, MAXPTS / g.ny));
     tk = std::min(tk, pow2_floor(lds_cap / (long)(lds_line(g.ny) * csz)));
-    tk = std::min(tk, prec == PREC_F64 ? 4 : 8);
+    tk = std::min(tk, seg);
     int G = std::min(64, pow2_floor(std::max(1, g.nz / 2)));
     if (tp) {
         if (tp->tj > 0) tj = tp->tj;
@@ -152,6 +156,11 @@ void choose_shapes(const pcx_grid &g, int prec, const TuneParams *tp, Shapes &sh
     sh.zg = G;
     int smax_need = (g.nz + G - 1) / G;
     sh.smax = smax_need <= 4 ? 4 : (smax_need <= 8 ? 8 : 16);
+    sh.mth = batch ? NT : 512;
+    // wider y workgroups when a tile holds many columns: more waves per CU
+    sh.yth = (!batch && (long)sh.tk * (lds_line(g.ny) * (long)csz) > 48 * 1024) ? 512 : NT;
+    sh.xth = batch ? NT : 512;
+    sh.batch = batch;
 }
 
 pcx_status build_domain(const pcx_grid &g, int prec, const Shapes &sh, const RadixChoice *rc, DomTables &tb, Dom &d)
@@ -167,17 +176,23 @@ pcx_status build_domain(const pcx_grid &g, int prec, const Shapes &sh, const Rad
     long nlines = (long)nl * ny;
     d.nzt = (int)((nlines + d.zlpw - 1) / d.zlpw);
     d.ndiv_tiles = (int)(((long)nx * ny * nz + NT - 1) / NT);
-    // correction: TI x TJ cell tiles marching over chunks of ckc planes
+    // marching stencils: TI x TJ cell tiles over chunks of ckc planes
+    d.mth = sh.mth;
+    d.yth = sh.yth;
+    d.xth = sh.xth;
     d.cti = std::min(nx, 64);
-    d.ctj = std::max(1, std::min(ny, NT / d.cti));
+    d.ctj = std::max(1, std::min(ny, sh.mth / d.cti));
     d.cnti = (nx + d.cti - 1) / d.cti;
     d.cntj = (ny + d.ctj - 1) / d.ctj;
-    {
+    if (sh.batch) {
+        d.ckc = nz; // whole columns: batch items stay large
+    } else {
         long txy = (long)d.cnti * d.cntj;
-        long chunks = std::max(1L, std::min((long)nz, (4096 + txy - 1) / txy));
+        long target = 2048L * 512 / sh.mth;
+        long chunks = std::max(1L, std::min((long)std::max(1, nz / 16), (target + txy - 1) / txy));
         d.ckc = (int)((nz + chunks - 1) / chunks);
-        d.cnk = (nz + d.ckc - 1) / d.ckc;
     }
+    d.cnk = (nz + d.ckc - 1) / d.ckc;
     d.ncell_tiles = d.cnti * d.cntj * d.cnk;
     d.dnx = mkdiv(nx); d.dny = mkdiv(ny); d.dtj = mkdiv(sh.tj); d.dtk = mkdiv(sh.tk); d.dnyc = mkdiv(ny);
     d.dcti = mkdiv(d.cti);
@@ -327,7 +342,7 @@ extern "C" pcx_status pcx_plan_create(const pcx_grid *grid, const pcx_options *o
             cache.save(o.tune_cache);
         }
     }
-    choose_shapes(P->grid, P->prec, have ? &tp : nullptr, P->sh);
+    choose_shapes(P->grid, P->prec, have ? &tp : nullptr, P->sh, false);
     st = build_domain(P->grid, P->prec, P->sh, have ? &rc : nullptr, P->tables, P->dom);
     if (st != PCX_OK) { plan_free(P); return st; }
     const size_t csz = P->prec == PREC_F64 ? 16 : 8;

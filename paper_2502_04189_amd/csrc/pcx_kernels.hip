@@ -18,34 +18,38 @@ __device__ __forceinline__ int xcd_tile(int ntiles)
     return (b & 7) * per + (b >> 3);
 }
 
-__global__ __launch_bounds__(NT) void k_rhs(Dom d)
+// Marching stencil launches of a single domain use 512-thread workgroups
+// (64 x 8 cells per plane) so that fewer threads sit on a tile edge.
+constexpr int MT = 512;
+
+__global__ __launch_bounds__(MT) void k_rhs(Dom d)
 {
-    __shared__ double sm[8 + 2 * NT];
+    __shared__ double sm[8 + 2 * MT];
     const int t = xcd_tile(d.ncell_tiles);
     if (t >= d.ncell_tiles) return;
-    pass_rhs(d, t, (char *)sm);
+    pass_rhs<MT>(d, t, (char *)sm);
 }
 
-__global__ __launch_bounds__(NT) void k_resid(Dom d, int solve)
+__global__ __launch_bounds__(MT) void k_resid(Dom d, int solve)
 {
-    __shared__ double sm[8 + NT];
+    __shared__ double sm[8 + MT];
     const int t = xcd_tile(d.ncell_tiles);
     if (t >= d.ncell_tiles) return;
-    pass_resid(d, t, (char *)sm, solve);
+    pass_resid<MT>(d, t, (char *)sm, solve);
 }
 
-template <typename T, int SRC>
-__global__ __launch_bounds__(NT) void k_xfwd(Dom d)
+template <typename T, int SRC, int NTH>
+__global__ __launch_bounds__(NTH) void k_xfwd(Dom d)
 {
     extern __shared__ __align__(16) char smem[];
-    pass_xfwd<T, SRC>(d, blockIdx.x, smem);
+    pass_xfwd<T, SRC, NTH>(d, blockIdx.x, smem);
 }
 
-template <typename T, bool INV>
-__global__ __launch_bounds__(NT) void k_y(Dom d)
+template <typename T, bool INV, int NTH>
+__global__ __launch_bounds__(NTH) void k_y(Dom d)
 {
     extern __shared__ __align__(16) char smem[];
-    pass_y<T, INV>(d, blockIdx.x, smem);
+    pass_y<T, INV, NTH>(d, blockIdx.x, smem);
 }
 
 template <typename T, int SMAX>
@@ -55,19 +59,19 @@ __global__ __launch_bounds__(NT) void k_z(Dom d)
     pass_z<T, SMAX>(d, blockIdx.x, smem);
 }
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(NT) void k_xinv(Dom d, int solve)
+template <typename T, int MODE, int NTH>
+__global__ __launch_bounds__(NTH) void k_xinv(Dom d, int solve)
 {
     extern __shared__ __align__(16) char smem[];
-    pass_xinv<T, MODE>(d, blockIdx.x, smem, solve);
+    pass_xinv<T, MODE, NTH>(d, blockIdx.x, smem, solve);
 }
 
-__global__ __launch_bounds__(NT) void k_corr(Dom d, int divcheck)
+__global__ __launch_bounds__(MT) void k_corr(Dom d, int divcheck)
 {
-    __shared__ double sm[8 + 4 * NT];
+    __shared__ double sm[8 + 4 * MT];
     const int t = xcd_tile(d.ncell_tiles);
     if (t >= d.ncell_tiles) return;
-    pass_corr(d, t, (char *)sm, divcheck != 0);
+    pass_corr<MT>(d, t, (char *)sm, divcheck != 0);
 }
 
 __global__ __launch_bounds__(NT) void k_div(Dom d)
@@ -141,13 +145,14 @@ static hipError_t lds_attr(const void *fn, size_t lds)
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-#define PCX_LAUNCH(fn, grid, lds, st, ...)                                              \
+#define PCX_LAUNCH_B(fn, grid, block, lds, st, ...)                                     \
     do {                                                                                \
         hipError_t e_ = lds_attr((const void *)(fn), (lds));                            \
         if (e_ != hipSuccess) return e_;                                                \
-        hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), (lds), (st), __VA_ARGS__);         \
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(block), (lds), (st), __VA_ARGS__);      \
         return hipGetLastError();                                                       \
     } while (0)
+#define PCX_LAUNCH(fn, grid, lds, st, ...) PCX_LAUNCH_B(fn, grid, NT, lds, st, __VA_ARGS__)
 
 hipError_t launch_zero(unsigned long long *p, int n, hipStream_t s)
 {
@@ -159,34 +164,47 @@ static int xcd_grid(int ntiles) { return ((ntiles + 7) >> 3) << 3; }
 
 hipError_t launch_rhs(const Dom &d, hipStream_t s)
 {
-    PCX_LAUNCH(k_rhs, xcd_grid(d.ncell_tiles), 0, s, d);
+    PCX_LAUNCH_B(k_rhs, xcd_grid(d.ncell_tiles), MT, 0, s, d);
 }
 
 hipError_t launch_resid(const Dom &d, int solve, hipStream_t s)
 {
-    PCX_LAUNCH(k_resid, xcd_grid(d.ncell_tiles), 0, s, d, solve);
+    PCX_LAUNCH_B(k_resid, xcd_grid(d.ncell_tiles), MT, 0, s, d, solve);
+}
+
+template <int NTH> static hipError_t launch_xfwd_t(const Dom &d, int prec, int src, size_t lds, hipStream_t s)
+{
+    const int grid = d.ntj * d.nz;
+    if (prec == PREC_F64) {
+        if (src == SRC_RHS) PCX_LAUNCH_B((k_xfwd<double, SRC_RHS, NTH>), grid, NTH, lds, s, d);
+        PCX_LAUNCH_B((k_xfwd<double, SRC_RESID, NTH>), grid, NTH, lds, s, d);
+    }
+    if (src == SRC_RHS) PCX_LAUNCH_B((k_xfwd<float, SRC_RHS, NTH>), grid, NTH, lds, s, d);
+    PCX_LAUNCH_B((k_xfwd<float, SRC_RESID, NTH>), grid, NTH, lds, s, d);
 }
 
 hipError_t launch_xfwd(const Dom &d, int prec, int src, size_t lds, hipStream_t s)
 {
-    const int grid = d.ntj * d.nz;
-    if (prec == PREC_F64) {
-        if (src == SRC_RHS) PCX_LAUNCH((k_xfwd<double, SRC_RHS>), grid, lds, s, d);
-        PCX_LAUNCH((k_xfwd<double, SRC_RESID>), grid, lds, s, d);
-    }
-    if (src == SRC_RHS) PCX_LAUNCH((k_xfwd<float, SRC_RHS>), grid, lds, s, d);
-    PCX_LAUNCH((k_xfwd<float, SRC_RESID>), grid, lds, s, d);
+    return d.xth == 512 ? launch_xfwd_t<512>(d, prec, src, lds, s) : launch_xfwd_t<NT>(d, prec, src, lds, s);
 }
 
 hipError_t launch_y(const Dom &d, int prec, bool inv, size_t lds, hipStream_t s)
 {
     const int grid = d.ntk * d.nl;
-    if (prec == PREC_F64) {
-        if (inv) PCX_LAUNCH((k_y<double, true>), grid, lds, s, d);
-        PCX_LAUNCH((k_y<double, false>), grid, lds, s, d);
+    if (d.yth == 512) {
+        if (prec == PREC_F64) {
+            if (inv) PCX_LAUNCH_B((k_y<double, true, 512>), grid, 512, lds, s, d);
+            PCX_LAUNCH_B((k_y<double, false, 512>), grid, 512, lds, s, d);
+        }
+        if (inv) PCX_LAUNCH_B((k_y<float, true, 512>), grid, 512, lds, s, d);
+        PCX_LAUNCH_B((k_y<float, false, 512>), grid, 512, lds, s, d);
     }
-    if (inv) PCX_LAUNCH((k_y<float, true>), grid, lds, s, d);
-    PCX_LAUNCH((k_y<float, false>), grid, lds, s, d);
+    if (prec == PREC_F64) {
+        if (inv) PCX_LAUNCH((k_y<double, true, NT>), grid, lds, s, d);
+        PCX_LAUNCH((k_y<double, false, NT>), grid, lds, s, d);
+    }
+    if (inv) PCX_LAUNCH((k_y<float, true, NT>), grid, lds, s, d);
+    PCX_LAUNCH((k_y<float, false, NT>), grid, lds, s, d);
 }
 
 hipError_t launch_z(const Dom &d, int prec, int smax, size_t lds, hipStream_t s)
@@ -202,17 +220,26 @@ hipError_t launch_z(const Dom &d, int prec, int smax, size_t lds, hipStream_t s)
     PCX_LAUNCH((k_z<float, 16>), grid, lds, s, d);
 }
 
-hipError_t launch_xinv(const Dom &d, int prec, int mode, int solve, size_t lds, hipStream_t s)
+template <int NTH> static hipError_t launch_xinv_t(const Dom &d, int prec, int mode, int solve, size_t lds, hipStream_t s)
 {
     const int grid = d.ntj * d.nz;
-    if (prec == PREC_F64) PCX_LAUNCH((k_xinv<double, XOUT_STORE>), grid, lds, s, d, solve);
-    if (mode == XOUT_STORE) PCX_LAUNCH((k_xinv<float, XOUT_STORE>), grid, lds, s, d, solve);
-    PCX_LAUNCH((k_xinv<float, XOUT_ACCUM>), grid, lds, s, d, solve);
+    if (prec == PREC_F64) {
+        if (mode == XOUT_STORE) PCX_LAUNCH_B((k_xinv<double, XOUT_STORE, NTH>), grid, NTH, lds, s, d, solve);
+        PCX_LAUNCH_B((k_xinv<double, XOUT_ACCUM, NTH>), grid, NTH, lds, s, d, solve);
+    }
+    if (mode == XOUT_STORE) PCX_LAUNCH_B((k_xinv<float, XOUT_STORE, NTH>), grid, NTH, lds, s, d, solve);
+    PCX_LAUNCH_B((k_xinv<float, XOUT_ACCUM, NTH>), grid, NTH, lds, s, d, solve);
+}
+
+hipError_t launch_xinv(const Dom &d, int prec, int mode, int solve, size_t lds, hipStream_t s)
+{
+    return d.xth == 512 ? launch_xinv_t<512>(d, prec, mode, solve, lds, s)
+                        : launch_xinv_t<NT>(d, prec, mode, solve, lds, s);
 }
 
 hipError_t launch_corr(const Dom &d, bool divcheck, hipStream_t s)
 {
-    PCX_LAUNCH(k_corr, xcd_grid(d.ncell_tiles), 0, s, d, divcheck ? 1 : 0);
+    PCX_LAUNCH_B(k_corr, xcd_grid(d.ncell_tiles), MT, 0, s, d, divcheck ? 1 : 0);
 }
 
 hipError_t launch_pmean(const Dom &d, hipStream_t s)
@@ -278,7 +305,8 @@ __global__ __launch_bounds__(NT) void k_persist(PersistArgs a)
         const Item X = a.items[it];
         const int dom = __builtin_amdgcn_readfirstlane((int)X.dom);
         const int ph = __builtin_amdgcn_readfirstlane((int)X.phase);
-        const int tile = __builtin_amdgcn_readfirstlane((int)X.tile);
+        const int tile0 = __builtin_amdgcn_readfirstlane((int)X.tile);
+        const int count = __builtin_amdgcn_readfirstlane((int)X.count);
         const unsigned slot = (unsigned)dom * a.tab.nphase + ph;
         if (ph > 0 && wid == 0) {
             const unsigned want = (unsigned)__builtin_amdgcn_readfirstlane((int)a.need[slot - 1]);
@@ -297,18 +325,22 @@ __global__ __launch_bounds__(NT) void k_persist(PersistArgs a)
         __threadfence();
         const Dom &d = a.doms[dom];
         const int sv = a.tab.solve[ph];
-        switch (a.tab.kind[ph]) {
-        case PK_RHS: pass_rhs(d, tile, smem); break;
-        case PK_RESID: pass_resid(d, tile, smem, sv); break;
-        case PK_XFWD_RHS: pass_xfwd<T, SRC_RHS>(d, tile, smem); break;
-        case PK_XFWD_RESID: pass_xfwd<T, SRC_RESID>(d, tile, smem); break;
-        case PK_YF: pass_y<T, false>(d, tile, smem); break;
-        case PK_Z: pass_z<T, SMAX>(d, tile, smem); break;
-        case PK_YI: pass_y<T, true>(d, tile, smem); break;
-        case PK_XINV_STORE: pass_xinv<T, XOUT_STORE>(d, tile, smem, sv); break;
-        case PK_XINV_ACCUM: pass_xinv<T, XOUT_ACCUM>(d, tile, smem, sv); break;
-        case PK_PMEAN: pass_pmean(d, smem); break;
-        default: pass_corr(d, tile, smem, true); break;
+        const int kind = a.tab.kind[ph];
+        for (int tile = tile0; tile < tile0 + count; ++tile) {
+            switch (kind) {
+            case PK_RHS: pass_rhs(d, tile, smem); break;
+            case PK_RESID: pass_resid(d, tile, smem, sv); break;
+            case PK_XFWD_RHS: pass_xfwd<T, SRC_RHS>(d, tile, smem); break;
+            case PK_XFWD_RESID: pass_xfwd<T, SRC_RESID>(d, tile, smem); break;
+            case PK_YF: pass_y<T, false>(d, tile, smem); break;
+            case PK_Z: pass_z<T, SMAX>(d, tile, smem); break;
+            case PK_YI: pass_y<T, true>(d, tile, smem); break;
+            case PK_XINV_STORE: pass_xinv<T, XOUT_STORE>(d, tile, smem, sv); break;
+            case PK_XINV_ACCUM: pass_xinv<T, XOUT_ACCUM>(d, tile, smem, sv); break;
+            case PK_PMEAN: pass_pmean(d, smem); break;
+            default: pass_corr(d, tile, smem, true); break;
+            }
+            __syncthreads(); // the next tile rewrites LDS the last one read
         }
         __threadfence();
         __syncthreads();

@@ -28,7 +28,9 @@ enum { PK_RHS = 0, PK_RESID, PK_XFWD_RHS, PK_XFWD_RESID, PK_YF, PK_Z, PK_YI, PK_
 
 struct Item {
     uint16_t dom, phase;
-    uint32_t tile;
+    uint32_t tile;   // first tile
+    uint32_t count;  // consecutive tiles in this item
+    uint32_t pad;
 };
 
 // Pass kind and solve index of each phase (the same for every domain).

@@ -83,10 +83,11 @@ __device__ __forceinline__ double amax_nan(double m, double v)
 // f = (rho0/dt) D u* + D[(1 - rho0/rho_face) G p*], stored in FP64 to d.f.
 // Face fluxes: x from this lane and its west lane, y computed on both faces,
 // z carried from the previous plane.
+template <int NTH = NT>
 __device__ void pass_rhs(const Dom &d, int tile, char *smem)
 {
     double *red = (double *)smem;
-    double *sP = red + 8, *sR = sP + NT;
+    double *sP = red + 8, *sR = sP + NTH;
     const MTile t = march_tile(d, tile);
     const MNbr n = march_nbr(d, t);
     const int nx = d.nx, nz = d.nz, sz = nx * d.ny, TI = d.cti;
@@ -146,11 +147,12 @@ __device__ void pass_rhs(const Dom &d, int tile, char *smem)
         Pc = Pp;
         Rc = Rp;
     }
-    block_max_to(d.stats + ST_FINF, amax, red);
-    block_max_to(d.stats + ST_SOLVE0, amax, red);
+    block_max_to<NTH>(d.stats + ST_FINF, amax, red);
+    block_max_to<NTH>(d.stats + ST_SOLVE0, amax, red);
 }
 
 // r = f - L p (FP64, 7-point operator with variable z spacing) -> d.r.
+template <int NTH = NT>
 __device__ void pass_resid(const Dom &d, int tile, char *smem, int solve)
 {
     double *red = (double *)smem;
@@ -193,7 +195,7 @@ __device__ void pass_resid(const Dom &d, int tile, char *smem, int solve)
         Gb = Gt;
         Pc = Pp;
     }
-    block_max_to(d.stats + ST_SOLVE0 + 4 * solve, amax, red);
+    block_max_to<NTH>(d.stats + ST_SOLVE0 + 4 * solve, amax, red);
 }
 
 // Velocity correction of the +faces of each column, marching in k:
@@ -201,10 +203,11 @@ __device__ void pass_resid(const Dom &d, int tile, char *smem, int solve)
 // With `divcheck`, also max |D u_out|: the -x face from the west lane, the -y
 // face through LDS, the -z face carried from the previous plane (recomputed
 // with the same arithmetic at tile edges).
+template <int NTH = NT>
 __device__ void pass_corr(const Dom &d, int tile, char *smem, bool divcheck)
 {
     double *red = (double *)smem;
-    double *sP = red + 8, *sS = sP + NT, *sR = sS + NT, *sF = sR + NT;
+    double *sP = red + 8, *sS = sP + NTH, *sR = sS + NTH, *sF = sR + NTH;
     const MTile t = march_tile(d, tile);
     const MNbr n = march_nbr(d, t);
     const int nx = d.nx, ny = d.ny, nz = d.nz, sz = nx * ny, TI = d.cti;
@@ -257,8 +260,8 @@ __device__ void pass_corr(const Dom &d, int tile, char *smem, bool divcheck)
         Sc = Sp;
         Rc = Rp;
     }
-    if (divcheck) block_max_to(d.stats + ST_DIV, dmax, red);
-    block_max_to(d.stats + ST_NONFIN, omax, red);
+    if (divcheck) block_max_to<NTH>(d.stats + ST_DIV, dmax, red);
+    block_max_to<NTH>(d.stats + ST_NONFIN, omax, red);
 }
 
 // Divergence of the stored output velocity (used when outputs alias inputs);
@@ -288,7 +291,7 @@ __device__ __forceinline__ void pass_div(const Dom &d, int tile, char *smem)
 // Tile = (j tile, k): rows j0 .. j0+rows-1 of plane k of f (or r).  Real
 // FFT by a half-length complex FFT of z[n] = s[2n] + i s[2n+1] and the split
 // X[l] = E + W^l O, X[M-l] = conj(E - W^l O); then the corner turn into S1.
-template <typename T, int SRC>
+template <typename T, int SRC, int NTH = NT>
 __device__ void pass_xfwd(const Dom &d, int tile, char *smem)
 {
     using C = c2<T>;
@@ -299,16 +302,16 @@ __device__ void pass_xfwd(const Dom &d, int tile, char *smem)
     const int rows = min(d.tj, d.ny - j0);
     const int nx = d.nx;
     const double *src = (SRC == SRC_RHS ? d.f : d.r) + ((size_t)k * d.ny + j0) * nx;
-    for (int idx = threadIdx.x; idx < rows * nx; idx += NT) {
+    for (int idx = threadIdx.x; idx < rows * nx; idx += NTH) {
         int r = (int)fdiv((uint32_t)idx, d.dnx);
         int i = idx - r * nx;
         ((T *)(buf + r * ldr + pidx(i >> 1)))[i & 1] = (T)src[idx];
     }
     __syncthreads();
-    lds_fft<T, false>(buf, ldr, rows, d.fx);
+    lds_fft<T, false, NTH>(buf, ldr, rows, d.fx);
     const C *twr = (const C *)d.twr;
     const int M = d.M, half = M / 2;
-    for (int idx = threadIdx.x; idx < rows * (half + 1); idx += NT) {
+    for (int idx = threadIdx.x; idx < rows * (half + 1); idx += NTH) {
         int r = idx / (half + 1);
         int l = idx - r * (half + 1);
         C *row = buf + r * ldr;
@@ -331,7 +334,7 @@ __device__ void pass_xfwd(const Dom &d, int tile, char *smem)
     __syncthreads();
     C *s1 = (C *)d.s1;
     const int tj = d.tj, nl = d.nl;
-    for (int idx = threadIdx.x; idx < tj * nl; idx += NT) {
+    for (int idx = threadIdx.x; idx < tj * nl; idx += NTH) {
         int l = (int)fdiv((uint32_t)idx, d.dtj);
         int r = idx - l * tj;
         if (r < rows) s1[((size_t)k * nl + l) * d.ny + j0 + r] = buf[r * ldr + pidx(l)];
@@ -340,7 +343,7 @@ __device__ void pass_xfwd(const Dom &d, int tile, char *smem)
 
 // ------------------------------------------------------------------- y pass
 // Tile = (k tile, l): columns k0 .. k0+cols-1 of mode l.
-template <typename T, bool INV>
+template <typename T, bool INV, int NTH = NT>
 __device__ void pass_y(const Dom &d, int tile, char *smem)
 {
     using C = c2<T>;
@@ -353,28 +356,28 @@ __device__ void pass_y(const Dom &d, int tile, char *smem)
     C *s1 = (C *)d.s1;
     C *s2 = (C *)d.s2;
     if (!INV) {
-        for (int idx = threadIdx.x; idx < cols * ny; idx += NT) {
+        for (int idx = threadIdx.x; idx < cols * ny; idx += NTH) {
             int c = (int)fdiv((uint32_t)idx, d.dnyc);
             int j = idx - c * ny;
             buf[c * ldc + pidx(j)] = s1[((size_t)(k0 + c) * nl + l) * ny + j];
         }
     } else {
-        for (int idx = threadIdx.x; idx < tk * ny; idx += NT) {
+        for (int idx = threadIdx.x; idx < tk * ny; idx += NTH) {
             int m = (int)fdiv((uint32_t)idx, d.dtk);
             int c = idx - m * tk;
             if (c < cols) buf[c * ldc + pidx(m)] = s2[((size_t)l * ny + m) * nz + k0 + c];
         }
     }
     __syncthreads();
-    lds_fft<T, INV>(buf, ldc, cols, d.fy);
+    lds_fft<T, INV, NTH>(buf, ldc, cols, d.fy);
     if (!INV) {
-        for (int idx = threadIdx.x; idx < tk * ny; idx += NT) {
+        for (int idx = threadIdx.x; idx < tk * ny; idx += NTH) {
             int m = (int)fdiv((uint32_t)idx, d.dtk);
             int c = idx - m * tk;
             if (c < cols) s2[((size_t)l * ny + m) * nz + k0 + c] = buf[c * ldc + pidx(m)];
         }
     } else {
-        for (int idx = threadIdx.x; idx < cols * ny; idx += NT) {
+        for (int idx = threadIdx.x; idx < cols * ny; idx += NTH) {
             int c = (int)fdiv((uint32_t)idx, d.dnyc);
             int j = idx - c * ny;
             s1[((size_t)(k0 + c) * nl + l) * ny + j] = buf[c * ldc + pidx(j)];
@@ -576,7 +579,7 @@ __device__ void pass_z(const Dom &d, int tile, char *smem)
 // ------------------------------------------------------------------ xinv
 // Tile = (j tile, k).  Inverse real FFT of rows j0.. of plane k from S1;
 // MODE store: p = value; accum: p += value (refinement update).
-template <typename T, int MODE>
+template <typename T, int MODE, int NTH = NT>
 __device__ void pass_xinv(const Dom &d, int tile, char *smem, int solve)
 {
     using C = c2<T>;
@@ -588,7 +591,7 @@ __device__ void pass_xinv(const Dom &d, int tile, char *smem, int solve)
     const int rows = min(d.tj, d.ny - j0);
     const int nx = d.nx, nl = d.nl, tj = d.tj;
     const C *s1 = (const C *)d.s1;
-    for (int idx = threadIdx.x; idx < tj * nl; idx += NT) {
+    for (int idx = threadIdx.x; idx < tj * nl; idx += NTH) {
         int l = (int)fdiv((uint32_t)idx, d.dtj);
         int r = idx - l * tj;
         if (r < rows) buf[r * ldr + pidx(l)] = s1[((size_t)k * nl + l) * d.ny + j0 + r];
@@ -597,7 +600,7 @@ __device__ void pass_xinv(const Dom &d, int tile, char *smem, int solve)
     // Z[l] = E + i O,  E = X[l] + conj(X[M-l]),  O = (X[l] - conj(X[M-l])) conj(W^l)
     const C *twr = (const C *)d.twr;
     const int M = d.M, half = M / 2;
-    for (int idx = threadIdx.x; idx < rows * (half + 1); idx += NT) {
+    for (int idx = threadIdx.x; idx < rows * (half + 1); idx += NTH) {
         int r = idx / (half + 1);
         int l = idx - r * (half + 1);
         C *row = buf + r * ldr;
@@ -619,13 +622,13 @@ __device__ void pass_xinv(const Dom &d, int tile, char *smem, int solve)
         }
     }
     __syncthreads();
-    lds_fft<T, true>(buf, ldr, rows, d.fx);
+    lds_fft<T, true, NTH>(buf, ldr, rows, d.fx);
     // accumulation also removes the FP64 volume mean of the previous p: the
     // residual cannot see a constant, so the FP32 gauge error of earlier
     // solves is cancelled here
     const double shift = (MODE == XOUT_ACCUM) ? d.pmean[0] : 0.0;
     double emax = 0.0, pmax = 0.0, psum = 0.0;
-    for (int idx = threadIdx.x; idx < rows * nx; idx += NT) {
+    for (int idx = threadIdx.x; idx < rows * nx; idx += NTH) {
         int r = (int)fdiv((uint32_t)idx, d.dnx);
         int i = idx - r * nx;
         double val = (double)((const T *)(buf + r * ldr + pidx(i >> 1)))[i & 1];
@@ -637,11 +640,11 @@ __device__ void pass_xinv(const Dom &d, int tile, char *smem, int solve)
         pmax = amax_nan(pmax, pv);
     }
     if (d.ppart) {
-        double ts = block_sum(psum, red);
+        double ts = block_sum<NTH>(psum, red);
         if (threadIdx.x == 0) d.ppart[tile] = ts * d.dzf[k];
     }
-    block_max_to(d.stats + ST_SOLVE0 + 4 * solve + 1, emax, red);
-    block_max_to(d.stats + ST_SOLVE0 + 4 * solve + 2, pmax, red);
+    block_max_to<NTH>(d.stats + ST_SOLVE0 + 4 * solve + 1, emax, red);
+    block_max_to<NTH>(d.stats + ST_SOLVE0 + 4 * solve + 2, pmax, red);
 }
 
 // Volume mean of p from the x-tile partial sums, summed in a fixed order by

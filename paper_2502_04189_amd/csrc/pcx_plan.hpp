@@ -12,6 +12,8 @@ namespace pcx {
 
 struct Shapes {
     int tj = 8, tk = 8, zg = 64, smax = 8;
+    int yth = 256, mth = 512, xth = 512;
+    bool batch = false;
 };
 
 // Optional overrides picked by the autotuner (0 / empty = default).
@@ -33,7 +35,7 @@ FastDiv mkdiv(uint32_t d);
 std::vector<int> default_radices(int n);
 void fill_fft(FftDesc &fd, int n, const std::vector<int> &rad);
 pcx_status validate_grid(const pcx_grid *g);
-void choose_shapes(const pcx_grid &g, int prec, const TuneParams *tp, Shapes &sh);
+void choose_shapes(const pcx_grid &g, int prec, const TuneParams *tp, Shapes &sh, bool batch);
 pcx_status build_domain(const pcx_grid &g, int prec, const Shapes &sh, const RadixChoice *rc, DomTables &tb, Dom &d);
 size_t lds_x(const Dom &d, int prec);
 size_t lds_y(const Dom &d, int prec);

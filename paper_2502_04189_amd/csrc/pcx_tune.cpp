@@ -139,7 +139,7 @@ pcx_status autotune_class(const pcx_grid &g, int prec, hipStream_t s, TuneParams
 
     auto make = [&](const TuneParams &tp, const RadixChoice &rc, Dom &d, DomTables &tb, size_t &lx, size_t &ly, size_t &lz, int &smax) {
         Shapes sh;
-        choose_shapes(g, prec, &tp, sh);
+        choose_shapes(g, prec, &tp, sh, false);
         pcx_status st = build_domain(g, prec, sh, &rc, tb, d);
         if (st != PCX_OK) return st;
         d.dt = 1e-3; d.rho0 = 1.0; d.irho0 = 1.0;
@@ -170,7 +170,7 @@ pcx_status autotune_class(const pcx_grid &g, int prec, hipStream_t s, TuneParams
     TuneParams tp0;
     RadixChoice rc0;
     Shapes base;
-    choose_shapes(g, prec, nullptr, base);
+    choose_shapes(g, prec, nullptr, base, false);
     best.tj = base.tj; best.tk = base.tk; best.zg = base.zg;
     brc.x = default_radices(M);
     brc.y = default_radices(g.ny);
@@ -178,7 +178,7 @@ pcx_status autotune_class(const pcx_grid &g, int prec, hipStream_t s, TuneParams
     {
         float bt = 1e30f;
         for (int tj = 1; tj <= 64; tj *= 2) {
-            if ((long)tj * M > PPT * NT || (long)tj * lds_line(M + 1) * (long)csz > cap) continue;
+            if ((long)tj * M > MAXPTS || (long)tj * lds_line(M + 1) * (long)csz > cap) continue;
             if (tj > 2 * g.ny) continue;
             for (auto &rx : radix_variants(M)) {
                 TuneParams tp = best;
@@ -201,7 +201,7 @@ pcx_status autotune_class(const pcx_grid &g, int prec, hipStream_t s, TuneParams
     {
         float bt = 1e30f;
         for (int tk = 1; tk <= 64; tk *= 2) {
-            if ((long)tk * g.ny > PPT * NT || (long)tk * lds_line(g.ny) * (long)csz > cap) continue;
+            if ((long)tk * g.ny > MAXPTS || (long)tk * lds_line(g.ny) * (long)csz > cap) continue;
             if (tk > 2 * g.nz) continue;
             for (auto &ry : radix_variants(g.ny)) {
                 TuneParams tp = best;

@@ -153,3 +153,84 @@ def relerr(a, b):
     b = np.asarray(b)
     den = np.abs(b).max()
     return float(np.abs(a - b).max() / (den if den > 0 else 1.0))
+
+
+# ------------------------------------------------------------ torch (GPU)
+# The same construction on the GPU with torch, for grids too large to build
+# quickly on the host.  Written independently of both the oracle and the HIP
+# library (plain torch elementwise ops).
+
+def _t_shift_minus(a, dim, wall):
+    import torch
+    if wall:
+        out = torch.zeros_like(a)
+        n = a.shape[dim]
+        out.narrow(dim, 1, n - 1).copy_(a.narrow(dim, 0, n - 1))
+        return out
+    return torch.roll(a, 1, dims=dim)
+
+
+def _t_shift_plus(a, dim, wall):
+    import torch
+    if wall:
+        out = torch.zeros_like(a)
+        n = a.shape[dim]
+        out.narrow(dim, 0, n - 1).copy_(a.narrow(dim, 1, n - 1))
+        return out
+    return torch.roll(a, -1, dims=dim)
+
+
+def fixed_point_inputs_torch(seed, g: GridSpec, rho, dt: float):
+    """Torch/GPU version of fixed_point_inputs: returns (pstar, u*, v*, w*,
+    q, u_df, v_df, w_df) as CUDA float64 tensors; rho is a CUDA tensor."""
+    import torch
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    dev = rho.device
+    sh = g.shape
+    dzf, dzc = metrics(g)
+    dzf_t = torch.from_numpy(dzf).to(dev)
+    dzc_t = torch.from_numpy(dzc).to(dev)
+    wx, wy, wz = g.bcx == WALL, g.bcy == WALL, g.bcz == WALL
+    q = torch.randn(sh, generator=gen, device=dev, dtype=torch.float64)
+    q -= float((q.sum(dim=(1, 2)) * dzf_t).sum() / (g.nx * g.ny * float(dzf.sum())))
+    amp = min(g.dx, g.dy)
+    Ax = torch.randn(sh, generator=gen, device=dev, dtype=torch.float64) * amp
+    Ay = torch.randn(sh, generator=gen, device=dev, dtype=torch.float64) * amp
+    Az = torch.randn(sh, generator=gen, device=dev, dtype=torch.float64) * amp
+    if wx:
+        Ay[:, :, -1] = 0.0
+        Az[:, :, -1] = 0.0
+    if wy:
+        Ax[:, -1, :] = 0.0
+        Az[:, -1, :] = 0.0
+    if wz:
+        Ax[-1] = 0.0
+        Ay[-1] = 0.0
+    dz = dzf_t[:, None, None]
+    ud = (Az - _t_shift_minus(Az, 1, wy)) / g.dy - (Ay - _t_shift_minus(Ay, 0, wz)) / dz
+    vd = (Ax - _t_shift_minus(Ax, 0, wz)) / dz - (Az - _t_shift_minus(Az, 2, wx)) / g.dx
+    wd = (Ay - _t_shift_minus(Ay, 2, wx)) / g.dx - (Ax - _t_shift_minus(Ax, 1, wy)) / g.dy
+    del Ax, Ay, Az
+    rx = 0.5 * (rho + _t_shift_plus(rho, 2, wx))
+    us = ud + dt * (_t_shift_plus(q, 2, wx) - q) / g.dx / rx
+    del rx
+    ry = 0.5 * (rho + _t_shift_plus(rho, 1, wy))
+    vs = vd + dt * (_t_shift_plus(q, 1, wy) - q) / g.dy / ry
+    del ry
+    dzf_up = torch.roll(dzf_t, -1)
+    rz = (rho * dzf_up[:, None, None] + _t_shift_plus(rho, 0, wz) * dz) / (2.0 * dzc_t[:, None, None])
+    ws = wd + dt * (_t_shift_plus(q, 0, wz) - q) / dzc_t[:, None, None] / rz
+    del rz
+    if wx:
+        us[:, :, -1] = 0.0
+    if wy:
+        vs[:, -1, :] = 0.0
+    if wz:
+        ws[-1] = 0.0
+    return q.clone(), us, vs, ws, q, ud, vd, wd
+
+
+def relerr_t(a, b):
+    den = float(b.abs().max())
+    return float((a - b).abs().max()) / (den if den > 0 else 1.0)
