@@ -66,7 +66,9 @@ typedef enum { PCX_FP64 = 0, PCX_FP32_REFINED = 1 } pcx_precision;
 /* Grid and boundary descriptor.  x and y are uniform (dx = lx/nx,
  * dy = ly/ny); z is given by its nz+1 strictly increasing face coordinates
  * zf (host memory, copied at plan creation).  Rules: nx, ny, nz >= 2;
- * nx and ny even when periodic; transform lengths nx, ny of the form 2^a 3^b
+ * nx even (its transform is a half-length complex FFT, also for the cosine
+ * transform of a wall x); ny even when periodic (any ny with a wall in y);
+ * transform lengths nx, ny of the form 2^a 3^b
  * and at most 4096 (else UNSUPPORTED); nz <= 1024 (else UNSUPPORTED). */
 typedef struct {
     int32_t nx, ny, nz;

@@ -75,6 +75,7 @@ struct Dom {
     // z tridiagonal coefficients and eigenvalues in the solve precision
     const void *za, *zb, *zc, *dzf_s, *lamx, *lamy;
     const void *twr;                  // post-twiddles exp(-2 pi i l / nx), l in [0, M]
+    const void *dctx, *dcty;          // wall x / wall y: exp(-i pi k / (2N)), else NULL
     FftDesc fx, fy;
     // fields
     const double *rho, *ps, *u, *v, *w;

@@ -110,15 +110,13 @@ pcx_status validate_grid(const pcx_grid *g)
     if (!(g->lx > 0.0) || !(g->ly > 0.0)) return fail(PCX_ERR_INVALID, "lx and ly must be > 0");
     for (int b : {g->bc_x, g->bc_y, g->bc_z})
         if (b != PCX_BC_PERIODIC && b != PCX_BC_WALL) return fail(PCX_ERR_INVALID, "unknown boundary condition");
-    if (g->bc_x == PCX_BC_PERIODIC && (g->nx % 2)) return fail(PCX_ERR_INVALID, "nx must be even in a periodic direction");
+    if (g->nx % 2) return fail(PCX_ERR_INVALID, "nx must be even");
     if (g->bc_y == PCX_BC_PERIODIC && (g->ny % 2)) return fail(PCX_ERR_INVALID, "ny must be even in a periodic direction");
     for (int k = 0; k < g->nz; ++k)
         if (!(g->zf[k + 1] > g->zf[k])) return fail(PCX_ERR_INVALID, "zf must be strictly increasing");
     if (!is_2a3b(g->nx) || !is_2a3b(g->ny) || g->nx > 4096 || g->ny > 4096)
         return fail(PCX_ERR_UNSUPPORTED, "transform lengths must be 2^a 3^b and at most 4096");
     if (g->nz > 1024) return fail(PCX_ERR_UNSUPPORTED, "nz above 1024 is not supported");
-    if (g->bc_x != PCX_BC_PERIODIC || g->bc_y != PCX_BC_PERIODIC)
-        return fail(PCX_ERR_UNSUPPORTED, "wall x or y (cosine transforms) is not built in this version");
     return PCX_OK;
 }
 
@@ -139,8 +137,9 @@ void choose_shapes(const pcx_grid &g, int prec, const TuneParams *tp, Shapes &sh
     const size_t csz = prec == PREC_F64 ? 16 : 8;
     const long lds_cap = 80 * 1024;
     const int seg = prec == PREC_F64 ? 8 : 16;
+    const int nlx = g.bc_x == PCX_BC_WALL ? g.nx : M + 1;
     int tj = pow2_floor(std::max(1, MAXPTS / std::max(M, 1)));
-    tj = std::min(tj, pow2_floor(lds_cap / (long)(lds_line(M + 1) * csz)));
+    tj = std::min(tj, pow2_floor(lds_cap / (long)(lds_line(nlx) * csz)));
     tj = std::min(tj, seg);
     int tk = pow2_floor(std::max(1, MAXPTS / g.ny));
     tk = std::min(tk, pow2_floor(lds_cap / (long)(lds_line(g.ny) * csz)));
@@ -166,7 +165,9 @@ void choose_shapes(const pcx_grid &g, int prec, const TuneParams *tp, Shapes &sh
 pcx_status build_domain(const pcx_grid &g, int prec, const Shapes &sh, const RadixChoice *rc, DomTables &tb, Dom &d)
 {
     const int nx = g.nx, ny = g.ny, nz = g.nz;
-    const int M = nx / 2, nl = M + 1;
+    const int M = nx / 2;
+    // x modes: half spectrum of a real FFT (periodic) or nx cosine modes (wall)
+    const int nl = g.bc_x == PCX_BC_WALL ? nx : M + 1;
     std::memset(&d, 0, sizeof(d));
     d.nx = nx; d.ny = ny; d.nz = nz; d.nl = nl; d.M = M;
     d.bcx = g.bc_x; d.bcy = g.bc_y; d.bcz = g.bc_z;
@@ -224,13 +225,17 @@ pcx_status build_domain(const pcx_grid &g, int prec, const Shapes &sh, const Rad
     }
     const long double pi = 3.141592653589793238462643383279502884L;
     std::vector<long double> lamx(nl), lamy(ny);
+    // eigenvalues of the second difference: periodic -(4/h^2) sin^2(pi l/n)
+    // (folded to min(l, n-l)), cell-centred Neumann -(4/h^2) sin^2(pi l/(2n))
     for (int l = 0; l < nl; ++l) {
-        long double s = sinl(pi * (long double)l / (long double)nx);
+        long double s = g.bc_x == PCX_BC_WALL ? sinl(pi * (long double)l / (2.0L * nx))
+                                              : sinl(pi * (long double)l / (long double)nx);
         lamx[l] = -4.0L / ((long double)d.dx * d.dx) * s * s;
     }
     for (int m = 0; m < ny; ++m) {
-        int mm = std::min(m, ny - m);
-        long double s = sinl(pi * (long double)mm / (long double)ny);
+        long double s;
+        if (g.bc_y == PCX_BC_WALL) s = sinl(pi * (long double)m / (2.0L * ny));
+        else s = sinl(pi * (long double)std::min(m, ny - m) / (long double)ny);
         lamy[m] = -4.0L / ((long double)d.dy * d.dy) * s * s;
     }
 
@@ -252,6 +257,9 @@ pcx_status build_domain(const pcx_grid &g, int prec, const Shapes &sh, const Rad
     size_t o_twr = addr(nx, false); // first M+1 entries of the nx roots are W_nx^l
     size_t o_twx = addr(M, false);
     size_t o_twy = addr(ny, false);
+    // cosine-transform twiddles exp(-i pi k / (2N)) = W_{4N}^k
+    size_t o_dcx = g.bc_x == PCX_BC_WALL ? addr(4 * nx, false) : 0;
+    size_t o_dcy = g.bc_y == PCX_BC_WALL ? addr(4 * ny, false) : 0;
 
     tb.bytes = b.bytes.size();
     hipError_t e = hipMalloc(&tb.dev, tb.bytes);
@@ -267,6 +275,8 @@ pcx_status build_domain(const pcx_grid &g, int prec, const Shapes &sh, const Rad
     d.za = base + o_za; d.zb = base + o_zb; d.zc = base + o_zc; d.dzf_s = base + o_dzfs;
     d.lamx = base + o_lx; d.lamy = base + o_ly;
     d.twr = base + o_twr;
+    d.dctx = g.bc_x == PCX_BC_WALL ? base + o_dcx : nullptr;
+    d.dcty = g.bc_y == PCX_BC_WALL ? base + o_dcy : nullptr;
     fill_fft(d.fx, M, rc && !rc->x.empty() ? rc->x : default_radices(M));
     d.fx.tw = base + o_twx;
     fill_fft(d.fy, ny, rc && !rc->y.empty() ? rc->y : default_radices(ny));
@@ -274,7 +284,7 @@ pcx_status build_domain(const pcx_grid &g, int prec, const Shapes &sh, const Rad
     return PCX_OK;
 }
 
-size_t lds_x(const Dom &d, int prec) { return (size_t)d.tj * lds_line(d.M + 1) * (prec == PREC_F64 ? 16 : 8) + 64; }
+size_t lds_x(const Dom &d, int prec) { return (size_t)d.tj * lds_line(d.nl) * (prec == PREC_F64 ? 16 : 8) + 64; }
 size_t lds_y(const Dom &d, int prec) { return (size_t)d.tk * lds_line(d.ny) * (prec == PREC_F64 ? 16 : 8) + 64; }
 size_t lds_z(const Dom &d, int prec)
 {

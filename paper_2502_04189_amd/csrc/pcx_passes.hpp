@@ -296,16 +296,19 @@ __device__ void pass_xfwd(const Dom &d, int tile, char *smem)
 {
     using C = c2<T>;
     C *buf = (C *)smem;
-    const int ldr = lds_line(d.M + 1);
+    const int ldr = lds_line(d.nl);
     const int jt = tile % d.ntj, k = tile / d.ntj;
     const int j0 = jt * d.tj;
     const int rows = min(d.tj, d.ny - j0);
     const int nx = d.nx;
     const double *src = (SRC == SRC_RHS ? d.f : d.r) + ((size_t)k * d.ny + j0) * nx;
+    const bool wx = d.bcx == BC_WALL;
     for (int idx = threadIdx.x; idx < rows * nx; idx += NTH) {
         int r = (int)fdiv((uint32_t)idx, d.dnx);
         int i = idx - r * nx;
-        ((T *)(buf + r * ldr + pidx(i >> 1)))[i & 1] = (T)src[idx];
+        // wall x: cosine transform by reordering v[n] = s[2n], v[N-1-n] = s[2n+1]
+        int n = wx ? ((i & 1) ? nx - 1 - (i >> 1) : (i >> 1)) : i;
+        ((T *)(buf + r * ldr + pidx(n >> 1)))[n & 1] = (T)src[idx];
     }
     __syncthreads();
     lds_fft<T, false, NTH>(buf, ldr, rows, d.fx);
@@ -332,6 +335,20 @@ __device__ void pass_xfwd(const Dom &d, int tile, char *smem)
         }
     }
     __syncthreads();
+    if (wx) {
+        // DCT-II from the real FFT V of the reordered row: A_k = W_{4N}^k V_k,
+        // X_k = Re A_k, X_{N-k} = -Im A_k (k = 0..M); stored as real modes
+        const C *wd = (const C *)d.dctx;
+        for (int idx = threadIdx.x; idx < rows * (M + 1); idx += NTH) {
+            int r = idx / (M + 1);
+            int kk = idx - r * (M + 1);
+            C *row = buf + r * ldr;
+            C a = cmul(wd[kk], row[pidx(kk)]);
+            row[pidx(kk)] = C{a.x, T(0)};
+            if (kk >= 1 && kk < M) row[pidx(nx - kk)] = C{-a.y, T(0)};
+        }
+        __syncthreads();
+    }
     C *s1 = (C *)d.s1;
     const int tj = d.tj, nl = d.nl;
     for (int idx = threadIdx.x; idx < tj * nl; idx += NTH) {
@@ -353,13 +370,18 @@ __device__ void pass_y(const Dom &d, int tile, char *smem)
     const int cols = min(d.tk, d.nz - k0);
     const int ny = d.ny, nz = d.nz, nl = d.nl, tk = d.tk;
     const int ldc = lds_line(ny);
+    const bool wy = d.bcy == BC_WALL;
+    // wall y: cosine transform by reordering v[n] = c[2n], v[N-1-n] = c[2n+1]
+    auto pos = [&](int j) { return wy ? ((j & 1) ? ny - 1 - (j >> 1) : (j >> 1)) : j; };
     C *s1 = (C *)d.s1;
     C *s2 = (C *)d.s2;
+    const C *wd = (const C *)d.dcty;
+    const int hy = ny / 2;
     if (!INV) {
         for (int idx = threadIdx.x; idx < cols * ny; idx += NTH) {
             int c = (int)fdiv((uint32_t)idx, d.dnyc);
             int j = idx - c * ny;
-            buf[c * ldc + pidx(j)] = s1[((size_t)(k0 + c) * nl + l) * ny + j];
+            buf[c * ldc + pidx(pos(j))] = s1[((size_t)(k0 + c) * nl + l) * ny + j];
         }
     } else {
         for (int idx = threadIdx.x; idx < tk * ny; idx += NTH) {
@@ -367,10 +389,46 @@ __device__ void pass_y(const Dom &d, int tile, char *smem)
             int c = idx - m * tk;
             if (c < cols) buf[c * ldc + pidx(m)] = s2[((size_t)l * ny + m) * nz + k0 + c];
         }
+        if (wy) {
+            // inverse DCT-II of complex columns: V_k = conj(w_k)(X_k - i X_{N-k}),
+            // V_{N-k} = i w_k (X_{N-k} - i X_k), w_k = W_{4N}^k, X_N = 0
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < cols * hy; idx += NTH) {
+                int c = idx / hy;
+                int kk = idx - c * hy + 1;
+                C *col = buf + c * ldc;
+                const int kn = ny - kk;
+                C w = wd[kk];
+                C xk = col[pidx(kk)], xn = col[pidx(kn)];
+                C a = {xk.x + xn.y, xk.y - xn.x};   // X_k - i X_{N-k}
+                col[pidx(kk)] = cmul(cconj(w), a);
+                if (kn != kk) {
+                    C b = {xn.x + xk.y, xn.y - xk.x}; // X_{N-k} - i X_k
+                    C wb = cmul(w, b);
+                    col[pidx(kn)] = C{-wb.y, wb.x};   // i w b
+                }
+            }
+        }
     }
     __syncthreads();
     lds_fft<T, INV, NTH>(buf, ldc, cols, d.fy);
     if (!INV) {
+        if (wy) {
+            // DCT-II of complex columns from the FFT V of the reordered data:
+            // X_k = (w_k V_k + conj(w_k) V_{N-k}) / 2,
+            // X_{N-k} = i (w_k V_k - conj(w_k) V_{N-k}) / 2, X_0 = V_0
+            for (int idx = threadIdx.x; idx < cols * hy; idx += NTH) {
+                int c = idx / hy;
+                int kk = idx - c * hy + 1;
+                C *col = buf + c * ldc;
+                const int kn = ny - kk;
+                C w = wd[kk];
+                C p = cmul(w, col[pidx(kk)]), q = cmul(cconj(w), col[pidx(kn)]);
+                col[pidx(kk)] = C{T(0.5) * (p.x + q.x), T(0.5) * (p.y + q.y)};
+                if (kn != kk) col[pidx(kn)] = C{T(-0.5) * (p.y - q.y), T(0.5) * (p.x - q.x)};
+            }
+            __syncthreads();
+        }
         for (int idx = threadIdx.x; idx < tk * ny; idx += NTH) {
             int m = (int)fdiv((uint32_t)idx, d.dtk);
             int c = idx - m * tk;
@@ -380,7 +438,7 @@ __device__ void pass_y(const Dom &d, int tile, char *smem)
         for (int idx = threadIdx.x; idx < cols * ny; idx += NTH) {
             int c = (int)fdiv((uint32_t)idx, d.dnyc);
             int j = idx - c * ny;
-            s1[((size_t)(k0 + c) * nl + l) * ny + j] = buf[c * ldc + pidx(j)];
+            s1[((size_t)(k0 + c) * nl + l) * ny + j] = buf[c * ldc + pidx(pos(j))];
         }
     }
 }
@@ -584,7 +642,7 @@ __device__ void pass_xinv(const Dom &d, int tile, char *smem, int solve)
 {
     using C = c2<T>;
     C *buf = (C *)smem;
-    const int ldr = lds_line(d.M + 1);
+    const int ldr = lds_line(d.nl);
     double *red = (double *)(smem + (size_t)d.tj * ldr * sizeof(C));
     const int jt = tile % d.ntj, k = tile / d.ntj;
     const int j0 = jt * d.tj;
@@ -597,6 +655,22 @@ __device__ void pass_xinv(const Dom &d, int tile, char *smem, int solve)
         if (r < rows) buf[r * ldr + pidx(l)] = s1[((size_t)k * nl + l) * d.ny + j0 + r];
     }
     __syncthreads();
+    const bool wx = d.bcx == BC_WALL;
+    if (wx) {
+        // inverse DCT-II: half spectrum of the reordered row,
+        // V_k = conj(W_{4N}^k) (X_k - i X_{N-k}), X_N = 0, k = 0..M
+        const C *wd = (const C *)d.dctx;
+        const int Mh = nx / 2;
+        for (int idx = threadIdx.x; idx < rows * (Mh + 1); idx += NTH) {
+            int r = idx / (Mh + 1);
+            int kk = idx - r * (Mh + 1);
+            C *row = buf + r * ldr;
+            T xk = row[pidx(kk)].x;
+            T xn = kk == 0 ? T(0) : row[pidx(nx - kk)].x;
+            row[pidx(kk)] = cmul(cconj(wd[kk]), C{xk, -xn});
+        }
+        __syncthreads();
+    }
     // Z[l] = E + i O,  E = X[l] + conj(X[M-l]),  O = (X[l] - conj(X[M-l])) conj(W^l)
     const C *twr = (const C *)d.twr;
     const int M = d.M, half = M / 2;
@@ -631,7 +705,8 @@ __device__ void pass_xinv(const Dom &d, int tile, char *smem, int solve)
     for (int idx = threadIdx.x; idx < rows * nx; idx += NTH) {
         int r = (int)fdiv((uint32_t)idx, d.dnx);
         int i = idx - r * nx;
-        double val = (double)((const T *)(buf + r * ldr + pidx(i >> 1)))[i & 1];
+        int n = wx ? ((i & 1) ? nx - 1 - (i >> 1) : (i >> 1)) : i;
+        double val = (double)((const T *)(buf + r * ldr + pidx(n >> 1)))[n & 1];
         size_t g = ((size_t)k * d.ny + j0 + r) * nx + i;
         double pv = (MODE == XOUT_STORE) ? val : (d.po[g] - shift) + val;
         d.po[g] = pv;

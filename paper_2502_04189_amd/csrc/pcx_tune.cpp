@@ -118,7 +118,8 @@ pcx_status autotune_class(const pcx_grid &g, int prec, hipStream_t s, TuneParams
     const size_t ncell = (size_t)g.nx * g.ny * g.nz;
     const int M = g.nx / 2;
     const size_t csz = prec == PREC_F64 ? 16 : 8;
-    const size_t nspec = (size_t)(M + 1) * g.ny * g.nz;
+    const int nlx = g.bc_x == PCX_BC_WALL ? g.nx : M + 1;
+    const size_t nspec = (size_t)nlx * g.ny * g.nz;
     Scratch sc;
     std::vector<double> ones(ncell, 1.0);
     double *fld[9];
@@ -178,7 +179,7 @@ pcx_status autotune_class(const pcx_grid &g, int prec, hipStream_t s, TuneParams
     {
         float bt = 1e30f;
         for (int tj = 1; tj <= 64; tj *= 2) {
-            if ((long)tj * M > MAXPTS || (long)tj * lds_line(M + 1) * (long)csz > cap) continue;
+            if ((long)tj * M > MAXPTS || (long)tj * lds_line(nlx) * (long)csz > cap) continue;
             if (tj > 2 * g.ny) continue;
             for (auto &rx : radix_variants(M)) {
                 TuneParams tp = best;

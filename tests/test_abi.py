@@ -45,6 +45,8 @@ def test_descriptor_validation(L):
         (W.GridSpec(1, 32, 16, 1.0, 1.0, ok.zf), P.PCX_ERR_INVALID),
         (W.GridSpec(32, 32, 16, 0.0, 1.0, ok.zf), P.PCX_ERR_INVALID),
         (W.GridSpec(31, 32, 16, 1.0, 1.0, ok.zf), P.PCX_ERR_INVALID),      # odd periodic nx
+        (W.GridSpec(27, 32, 16, 1.0, 1.0, ok.zf, 1, 0, 1), P.PCX_ERR_INVALID),  # odd walled nx
+        (W.GridSpec(32, 27, 16, 1.0, 1.0, ok.zf, 0, 0, 1), P.PCX_ERR_INVALID),  # odd periodic ny
         (W.GridSpec(32, 32, 16, 1.0, 1.0, bad_z), P.PCX_ERR_INVALID),      # non-increasing zf
         (W.GridSpec(32, 32, 16, 1.0, 1.0, ok.zf, 0, 0, 7), P.PCX_ERR_INVALID),
         (W.GridSpec(40, 32, 16, 1.0, 1.0, ok.zf), P.PCX_ERR_UNSUPPORTED),  # 40 = 2^3 5

@@ -123,3 +123,27 @@ def test_batch_autotune_and_cache(pcx, orc, tmp_path):
     torch.cuda.synchronize()
     for d, d2 in zip(doms, doms2):
         assert torch.equal(d["p_out"], d2["p_out"])
+
+
+def test_batch_mixed_walls_vs_oracle(pcx, orc):
+    """Domains with walls in x and/or y (cosine transforms) batched with
+    periodic ones, in both precisions."""
+    import torch
+    specs = [((32, 48, 32), (1, 0, 1), 1.5), ((48, 32, 64), (0, 1, 0), 0.0), ((64, 64, 32), (1, 1, 1), 1.2),
+             ((32, 32, 32), (0, 0, 1), 0.0), ((96, 32, 33), (1, 1, 0), 0.0)]
+    cases = [W.random_case(900 + i, *d, *bc, stretch=s) for i, (d, bc, s) in enumerate(specs)]
+    for prec, tol in (("fp64", 1e-12), ("fp32_refined", REF_TOL)):
+        _say(f"mixed-wall batch {prec}: " + ", ".join(c.name for c in cases))
+        doms = _domains(cases)
+        b = pcx.Batch(doms, prec)
+        b.launch()
+        torch.cuda.synchronize()
+        reps, st = b.reports()
+        assert st == pcx.PCX_OK
+        for c, d, r in zip(cases, doms, reps):
+            g = orc.Grid.from_workload(c.grid)
+            ref = orc.step(g, c.dt, c.rho0, *c.fields())[:4]
+            e = {n: M.relerr(x, y) for n, x, y in zip("uvwp", _outs(d), ref)}
+            _say(f"  {c.name}: errors {e} div {r['max_div_rel']:.2e}")
+            assert max(e.values()) <= tol
+            assert r["max_div_rel"] <= tol

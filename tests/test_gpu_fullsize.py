@@ -80,21 +80,21 @@ def test_determinism_and_inplace_256(pcx, case256):
     _say(f"deterministic; in place identical; div {rep_in['max_div_rel']:.2e}")
 
 
-@pytest.mark.parametrize("bcz,stretch", [(1, 1.8), (0, 0.0)])
-def test_512_manufactured_fixed_point(pcx, bcz, stretch):
+@pytest.mark.parametrize("bc,stretch", [((0, 0, 1), 1.8), ((0, 0, 0), 0.0), ((1, 1, 1), 1.8)])
+def test_512_manufactured_fixed_point(pcx, bc, stretch):
     """p* = q and u* = u_df + dt G q / rho_face on the 512^3 bubble density:
     the exact step returns p = q and u_out = u_df."""
     import torch
     n = 512
     g = W.GridSpec(n, n, n, 2 * np.pi, 2 * np.pi, W.zf_tanh(n, 2.0, 1.8) if stretch else W.zf_uniform(n, 2.0),
-                   0, 0, bcz)
+                   *bc)
     rng = np.random.Generator(np.random.PCG64(77))
     bub = W.place_bubbles(rng, g, [8 * g.dx] * 512)
     rho = torch.from_numpy(1000.0 + (1.0 - 1000.0) * W.phase_field(g, bub)).to("cuda")
     rho0 = float(rho.min())
     dt = (8 / 15) * 0.5 * min(g.dx, float(np.diff(g.zf).min()))
-    _say(f"512^3 fixed point bcz={bcz}: building inputs on the GPU")
-    ps, us, vs, ws, q, ud, vd, wd = M.fixed_point_inputs_torch(1234 + bcz, g, rho, dt)
+    _say(f"512^3 fixed point bc={bc}: building inputs on the GPU")
+    ps, us, vs, ws, q, ud, vd, wd = M.fixed_point_inputs_torch(1234 + bc[0] + 2 * bc[2], g, rho, dt)
     for prec, tol in (("fp64", 1e-12), ("fp32_refined", 1e-10)):
         plan = pcx.Plan(g, prec)
         uo, vo, wo, p, rep = plan.step(dt, rho0, rho, ps, us, vs, ws)

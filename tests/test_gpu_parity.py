@@ -62,6 +62,14 @@ SMALL = [
     ((2, 2, 2), (0, 0, 1), 0.0),
     ((24, 18, 7), (0, 0, 0), 1.1),
     ((128, 32, 96), (0, 0, 0), 0.0),
+    # wall x and/or y: cosine transforms in the walled directions
+    ((48, 36, 20), (1, 0, 1), 1.8),
+    ((32, 48, 17), (0, 1, 0), 0.0),
+    ((64, 54, 24), (1, 1, 1), 1.2),
+    ((96, 64, 33), (1, 1, 0), 0.0),
+    ((6, 9, 5), (1, 1, 1), 0.0),
+    ((2, 3, 2), (1, 1, 0), 0.0),
+    ((24, 27, 7), (0, 1, 1), 1.1),
 ]
 
 
@@ -79,7 +87,8 @@ def test_small_fp64(pcx, orc, dims, bc, stretch):
 
 
 @pytest.mark.parametrize("dims,bc,stretch", [((32, 32, 32), (0, 0, 1), 0.0), ((48, 36, 20), (0, 0, 1), 1.8),
-                                             ((64, 96, 33), (0, 0, 0), 0.0)])
+                                             ((64, 96, 33), (0, 0, 0), 0.0),
+                                             ((64, 48, 40), (1, 1, 1), 1.5)])
 def test_small_refined(pcx, orc, dims, bc, stretch):
     case = W.config0() if dims == (32, 32, 32) else W.random_case(5 + sum(dims), *dims, *bc, stretch=stretch)
     _say(f"case {case.name} fp32_refined")
