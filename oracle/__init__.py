@@ -65,6 +65,9 @@ def lib():
         L.oracle_step.argtypes = [G, C.c_double, C.c_double] + [_DP] * 9 + [C.POINTER(OrDiag)]
         L.oracle_rhs.argtypes = [G, C.c_double, C.c_double] + [_DP] * 6
         L.oracle_poisson.argtypes = [G, _DP, _DP]
+        L.oracle_rhs_at.argtypes = [G, C.c_double, C.c_double] + [_DP] * 5 + [C.c_int64, C.c_void_p, _DP]
+        L.oracle_correct_at.argtypes = ([G, C.c_double, C.c_double] + [_DP] * 6 +
+                                        [C.c_int64, C.c_void_p, C.c_void_p, _DP])
         L.oracle_correct.argtypes = [G, C.c_double, C.c_double] + [_DP] * 9
         L.oracle_grad.argtypes = [G, _DP, _DP, _DP, _DP]
         L.oracle_div.argtypes = [G, _DP, _DP, _DP, _DP]
@@ -139,6 +142,28 @@ def rhs(g, dt, rho0, rho, pstar, u, v, w):
     f = np.empty(g.shape)
     _chk(lib().oracle_rhs(g.cref, float(dt), float(rho0), *[_p(a) for a in ins], _p(f)), "rhs")
     return f
+
+
+def rhs_at(g, dt, rho0, rho, pstar, u, v, w, cells):
+    """f at the given flat cell indices (k ny + j) nx + i."""
+    ins = [_arr(a) for a in (rho, pstar, u, v, w)]
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    out = np.empty(len(cells))
+    _chk(lib().oracle_rhs_at(g.cref, float(dt), float(rho0), *[_p(a) for a in ins], len(cells), cells.ctypes.data,
+                             _p(out)), "rhs_at")
+    return out
+
+
+def correct_at(g, dt, rho0, rho, pstar, u, v, w, p, dirs, cells):
+    """Corrected velocity on the +dir face (0 u, 1 v, 2 w) of the given flat
+    cell indices, from the pressure p."""
+    ins = [_arr(a) for a in (rho, pstar, u, v, w, p)]
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    dirs = np.ascontiguousarray(dirs, dtype=np.int32)
+    out = np.empty(len(cells))
+    _chk(lib().oracle_correct_at(g.cref, float(dt), float(rho0), *[_p(a) for a in ins], len(cells),
+                                 dirs.ctypes.data, cells.ctypes.data, _p(out)), "correct_at")
+    return out
 
 
 def poisson(g, f):

@@ -96,6 +96,23 @@ static double face_val(const double *a, size_t base, size_t stride, int s, int n
     return a[base + (size_t)wrapi(s, n) * stride];
 }
 
+/* G q on the +dir face of cell (i, j, k); 0 on a wall face. */
+static double face_grad(const geo *m, const double *q, int dir, int i, int j, int k)
+{
+    int nx = m->nx, ny = m->ny, nz = m->nz;
+    size_t c = IDX(i, j, k);
+    if (dir == 0) {
+        if (m->bcx == 1 && i == nx - 1) return 0.0;
+        return (q[IDX(wrapi(i + 1, nx), j, k)] - q[c]) / m->dx;
+    }
+    if (dir == 1) {
+        if (m->bcy == 1 && j == ny - 1) return 0.0;
+        return (q[IDX(i, wrapi(j + 1, ny), k)] - q[c]) / m->dy;
+    }
+    if (m->bcz == 1 && k == nz - 1) return 0.0;
+    return (q[IDX(i, j, wrapi(k + 1, nz))] - q[c]) / m->dzc[k];
+}
+
 /* G: cell centres -> faces.  gx on the +x face of each cell, 0 on wall faces. */
 static void grad_impl(const geo *m, const double *q, double *gx, double *gy, double *gz)
 {
@@ -104,18 +121,9 @@ static void grad_impl(const geo *m, const double *q, double *gx, double *gy, dou
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 size_t c = IDX(i, j, k);
-                if (gx) {
-                    if (m->bcx == 1 && i == nx - 1) gx[c] = 0.0;
-                    else gx[c] = (q[IDX(wrapi(i + 1, nx), j, k)] - q[c]) / m->dx;
-                }
-                if (gy) {
-                    if (m->bcy == 1 && j == ny - 1) gy[c] = 0.0;
-                    else gy[c] = (q[IDX(i, wrapi(j + 1, ny), k)] - q[c]) / m->dy;
-                }
-                if (gz) {
-                    if (m->bcz == 1 && k == nz - 1) gz[c] = 0.0;
-                    else gz[c] = (q[IDX(i, j, wrapi(k + 1, nz))] - q[c]) / m->dzc[k];
-                }
+                if (gx) gx[c] = face_grad(m, q, 0, i, j, k);
+                if (gy) gy[c] = face_grad(m, q, 1, i, j, k);
+                if (gz) gz[c] = face_grad(m, q, 2, i, j, k);
             }
 }
 
@@ -482,6 +490,81 @@ int oracle_correct(const or_grid *g, double dt, double rho0, const double *rho, 
                     out[d][c] = in[d][c] - dt * ((1.0 / rho0) * gp[d][c] + (1.0 / rf - 1.0 / rho0) * gs[d][c]);
                 }
     for (int d = 0; d < 3; ++d) { free(gp[d]); free(gs[d]); }
+    geo_free(&m);
+    return 0;
+}
+
+/* ------------------------------------------------------ sampled outputs */
+/* Point evaluations of the RHS and of the corrected velocity, for checking
+ * grids whose full oracle step would not fit a test's time.  Same
+ * expressions, in the same order, as oracle_rhs and oracle_correct. */
+
+/* (1 - rho0/rho_face) G p* on the +dir face of cell (i, j, k); 0 on walls. */
+static double split_flux(const geo *m, double rho0, const double *rho, const double *pstar, int dir, int i, int j,
+                         int k)
+{
+    if (face_is_wall(m, dir, i, j, k)) return 0.0;
+    return (1.0 - rho0 / rho_face(m, rho, dir, i, j, k)) * face_grad(m, pstar, dir, i, j, k);
+}
+
+/* flux on the -dir face of cell (i, j, k): the +dir face of the cell below,
+ * wrapped when periodic, 0 below the first cell of a wall direction */
+static double split_flux_lo(const geo *m, double rho0, const double *rho, const double *pstar, int dir, int i,
+                            int j, int k)
+{
+    int bc = dir == 0 ? m->bcx : (dir == 1 ? m->bcy : m->bcz);
+    int s = dir == 0 ? i : (dir == 1 ? j : k);
+    int n = dir == 0 ? m->nx : (dir == 1 ? m->ny : m->nz);
+    if (s == 0 && bc == 1) return 0.0;
+    s = wrapi(s - 1, n);
+    return split_flux(m, rho0, rho, pstar, dir, dir == 0 ? s : i, dir == 1 ? s : j, dir == 2 ? s : k);
+}
+
+int oracle_rhs_at(const or_grid *g, double dt, double rho0, const double *rho, const double *pstar,
+                  const double *u, const double *v, const double *w, int64_t n, const int64_t *cells, double *out)
+{
+    if (!(dt > 0.0) || !(rho0 > 0.0) || n < 0) return 1;
+    geo m;
+    if (geo_init(g, &m)) return 1;
+    int nx = m.nx, ny = m.ny, nz = m.nz;
+    size_t sx = 1, sy = (size_t)nx, sz = (size_t)nx * ny;
+    for (int64_t s = 0; s < n; ++s) {
+        int64_t c = cells[s];
+        if (c < 0 || c >= (int64_t)nx * ny * nz) { geo_free(&m); return 1; }
+        int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((int64_t)nx * ny));
+        size_t bx = IDX(0, j, k), by = IDX(i, 0, k), bz = IDX(i, j, 0);
+        double ddx = (face_val(u, bx, sx, i, nx, m.bcx) - face_val(u, bx, sx, i - 1, nx, m.bcx)) / m.dx;
+        double ddy = (face_val(v, by, sy, j, ny, m.bcy) - face_val(v, by, sy, j - 1, ny, m.bcy)) / m.dy;
+        double ddz = (face_val(w, bz, sz, k, nz, m.bcz) - face_val(w, bz, sz, k - 1, nz, m.bcz)) / m.dzf[k];
+        double dv = ddx + ddy + ddz;
+        double fx = (split_flux(&m, rho0, rho, pstar, 0, i, j, k) - split_flux_lo(&m, rho0, rho, pstar, 0, i, j, k)) / m.dx;
+        double fy = (split_flux(&m, rho0, rho, pstar, 1, i, j, k) - split_flux_lo(&m, rho0, rho, pstar, 1, i, j, k)) / m.dy;
+        double fz = (split_flux(&m, rho0, rho, pstar, 2, i, j, k) - split_flux_lo(&m, rho0, rho, pstar, 2, i, j, k)) / m.dzf[k];
+        out[s] = (rho0 / dt) * dv + (fx + fy + fz);
+    }
+    geo_free(&m);
+    return 0;
+}
+
+int oracle_correct_at(const or_grid *g, double dt, double rho0, const double *rho, const double *pstar,
+                      const double *u, const double *v, const double *w, const double *p, int64_t n,
+                      const int32_t *dirs, const int64_t *cells, double *out)
+{
+    if (!(dt > 0.0) || !(rho0 > 0.0) || n < 0) return 1;
+    geo m;
+    if (geo_init(g, &m)) return 1;
+    int nx = m.nx, ny = m.ny, nz = m.nz;
+    const double *in[3] = {u, v, w};
+    for (int64_t s = 0; s < n; ++s) {
+        int64_t c = cells[s];
+        int d = dirs[s];
+        if (c < 0 || c >= (int64_t)nx * ny * nz || d < 0 || d > 2) { geo_free(&m); return 1; }
+        int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((int64_t)nx * ny));
+        if (face_is_wall(&m, d, i, j, k)) { out[s] = 0.0; continue; }
+        double rf = rho_face(&m, rho, d, i, j, k);
+        out[s] = in[d][c] - dt * ((1.0 / rho0) * face_grad(&m, p, d, i, j, k) +
+                                  (1.0 / rf - 1.0 / rho0) * face_grad(&m, pstar, d, i, j, k));
+    }
     geo_free(&m);
     return 0;
 }

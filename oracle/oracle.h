@@ -20,6 +20,8 @@
 #ifndef PCX_ORACLE_H
 #define PCX_ORACLE_H
 
+#include <stdint.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -54,6 +56,17 @@ int oracle_rhs(const or_grid *g, double dt, double rho0, const double *rho,
                const double *pstar, const double *u, const double *v,
                const double *w, double *f);
 int oracle_poisson(const or_grid *g, const double *f, double *p);
+
+/* Sampled outputs: f at n flat cell indices; corrected face velocity at n
+ * (dir, flat cell index) faces (dir 0/1/2 = u/v/w, +dir face of the cell)
+ * given a pressure p.  1 on an invalid argument or index. */
+int oracle_rhs_at(const or_grid *g, double dt, double rho0, const double *rho,
+                  const double *pstar, const double *u, const double *v,
+                  const double *w, int64_t n, const int64_t *cells, double *out);
+int oracle_correct_at(const or_grid *g, double dt, double rho0, const double *rho,
+                      const double *pstar, const double *u, const double *v,
+                      const double *w, const double *p, int64_t n,
+                      const int32_t *dirs, const int64_t *cells, double *out);
 int oracle_correct(const or_grid *g, double dt, double rho0, const double *rho,
                    const double *pstar, const double *u, const double *v,
                    const double *w, const double *p, double *uo, double *vo,

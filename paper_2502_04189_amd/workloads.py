@@ -275,6 +275,88 @@ def config3(seed: int = 1003) -> Case:
     return channel_bubbles(512, 512, seed, "config3_512^3_wallz_tanh")
 
 
+def solenoidal_velocity(rng, g: GridSpec, kmax: float = 32.0, kmin: float = 1.0):
+    """Random-phase Fourier velocity with 1 <= |k| <= kmax (physical
+    wavenumbers, multiples of 2 pi / L per axis), |u_k| = |k|^(-11/6) so the
+    shell spectrum goes as k^(-5/3), each mode's complex amplitude drawn
+    N(0,1)+iN(0,1) per component and projected perpendicular to k (solenoidal
+    in the continuum).  The field is the real part of the mode sum (the
+    Hermitian-symmetrised spectrum), sampled at the staggered face positions,
+    so the discrete divergence is not zero.  Scaled to rms 1 over the three
+    components.  Evaluated as a pruned inverse DFT in three stages (x, then
+    y, then z) since only the few modes inside the shell are non-zero.
+    Draws: the amplitudes, in (kz, ky, kx) order, real parts then imaginary."""
+    ax = []
+    for n, L in ((g.nz, g.lz), (g.ny, g.ly), (g.nx, g.lx)):
+        step = 2.0 * math.pi / L
+        m = min(int(math.floor(kmax / step + 1e-12)), n // 2 - 1)
+        ax.append(np.arange(-m, m + 1) * step)
+    kz, ky, kx = ax
+    K = np.stack(np.meshgrid(kz, ky, kx, indexing="ij"), axis=-1)[..., ::-1]  # (kx, ky, kz) per mode
+    kk = np.sqrt((K ** 2).sum(axis=-1))
+    shell = (kk >= kmin - 1e-12) & (kk <= kmax + 1e-12)
+    a = rng.standard_normal(K.shape) + 1j * rng.standard_normal(K.shape)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        kh = np.where(shell[..., None], K / np.where(shell, kk, 1.0)[..., None], 0.0)
+        a = a - kh * (kh * a).sum(axis=-1, keepdims=True)
+        norm = np.sqrt((np.abs(a) ** 2).sum(axis=-1))
+        amp = np.where(shell, np.where(shell, kk, 1.0) ** (-11.0 / 6.0) / np.where(norm > 0, norm, 1.0), 0.0)
+    coef = a * amp[..., None]                        # (nkz, nky, nkx, 3)
+    x, y, zc = _centres(g)
+    xf = (np.arange(g.nx) + 1.0) * g.dx
+    yf = (np.arange(g.ny) + 1.0) * g.dy
+    zfc = g.zf[1:] - g.zf[0]
+    zc = zc - g.zf[0]
+    out = []
+    for comp, (xs, ys, zs) in enumerate(((xf, y, zc), (x, yf, zc), (x, y, zfc))):
+        C = coef[..., comp]
+        A = C.reshape(-1, len(kx)) @ np.exp(1j * np.outer(kx, xs))                 # (nkz*nky, nx)
+        B = np.exp(1j * np.outer(ys, ky))[None] @ A.reshape(len(kz), len(ky), -1)  # (nkz, ny, nx)
+        B = B.reshape(len(kz), -1)
+        Br, Bi = np.ascontiguousarray(B.real), np.ascontiguousarray(B.imag)
+        del A, B
+        Ez = np.exp(1j * np.outer(zs, kz))                                          # (nz, nkz)
+        Er, Ei = np.ascontiguousarray(Ez.real), np.ascontiguousarray(Ez.imag)
+        f = np.empty((g.nz, g.ny * g.nx))
+        step = 1 << 16
+        for c0 in range(0, f.shape[1], step):
+            f[:, c0:c0 + step] = Er @ Br[:, c0:c0 + step]
+            f[:, c0:c0 + step] -= Ei @ Bi[:, c0:c0 + step]
+        del Br, Bi
+        out.append(f.reshape(g.shape))
+    rms = math.sqrt(sum(float(np.square(c).mean()) for c in out) / 3.0)
+    for c in out:
+        c /= rms
+    return out
+
+
+def emulsion(nx: int, ny: int, nz: int, ndrops: int, seed: int, name: str, kmax: float = 32.0,
+             rlo: float = 4.0, rhi: float = 12.0) -> Case:
+    """Triply periodic emulsion in a 2pi x 2pi x pi box (uniform grid when
+    nx = ny = 2 nz): ndrops drops with R ~ U[rlo, rhi] dx at seeded
+    non-overlapping positions; carrier rho = 10, drop rho = 1; solenoidal
+    random-phase velocity with a k^-5/3 shell spectrum for 1 <= |k| <= kmax,
+    rms 1; smooth random p* periodic in z.
+    Draws: radii, centres, velocity amplitudes, p* modes."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    g = GridSpec(nx, ny, nz, 2.0 * math.pi, 2.0 * math.pi, zf_uniform(nz, math.pi), PERIODIC, PERIODIC,
+                 PERIODIC)
+    radii = list(rng.uniform(rlo, rhi, ndrops) * g.dx)
+    bub = place_bubbles(rng, g, radii, max_tries=200000)
+    phi = phase_field(g, bub)
+    rho = 10.0 + (1.0 - 10.0) * phi
+    del phi
+    u, v, w = solenoidal_velocity(rng, g, kmax)
+    pstar = smooth_pstar(rng, g)
+    return _finish(name, g, rho, pstar, u, v, w, {"drops": len(bub)})
+
+
+def config2(seed: int = 1002) -> Case:
+    """1024 x 1024 x 512 triply periodic emulsion: 2000 drops, R ~ U[4, 12] dx,
+    density ratio 10, k^-5/3 solenoidal velocity for 1 <= |k| <= 32."""
+    return emulsion(1024, 1024, 512, 2000, seed, "config2_1024x1024x512_triply_periodic")
+
+
 def random_case(seed, nx, ny, nz, bcx=PERIODIC, bcy=PERIODIC, bcz=WALL, stretch=0.0,
                 nbub=3, ratio=1000.0, lx=None, ly=None, lz=None) -> Case:
     """Small seeded case of any size/BC for parity tests: a few bubbles,

@@ -234,3 +234,47 @@ def fixed_point_inputs_torch(seed, g: GridSpec, rho, dt: float):
 def relerr_t(a, b):
     den = float(b.abs().max())
     return float((a - b).abs().max()) / (den if den > 0 else 1.0)
+
+
+def _t_wall_zero(a, dim, wall):
+    """Copy of a face field with the stored wall face (last index) set to 0."""
+    if not wall:
+        return a
+    out = a.clone()
+    out.narrow(dim, a.shape[dim] - 1, 1).zero_()
+    return out
+
+
+def div_t(g: GridSpec, u, v, w):
+    """D(u, v, w) at cell centres in torch (FP64), wall faces read as 0."""
+    import torch
+    wx, wy, wz = g.bcx == WALL, g.bcy == WALL, g.bcz == WALL
+    dzf, _ = metrics(g)
+    dz = torch.from_numpy(dzf).to(u.device)[:, None, None]
+    u = _t_wall_zero(u, 2, wx)
+    v = _t_wall_zero(v, 1, wy)
+    w = _t_wall_zero(w, 0, wz)
+    out = (u - _t_shift_minus(u, 2, wx)) / g.dx
+    out += (v - _t_shift_minus(v, 1, wy)) / g.dy
+    out += (w - _t_shift_minus(w, 0, wz)) / dz
+    return out
+
+
+def rhs_t(g: GridSpec, dt: float, rho0: float, rho, pstar, u, v, w):
+    """f = (rho0/dt) D u* + D[(1 - rho0/rho_face) G p*] in torch (FP64):
+    face densities by the arithmetic mean in x and y and linear
+    interpolation in z; wall faces carry no flux."""
+    import torch
+    wx, wy, wz = g.bcx == WALL, g.bcy == WALL, g.bcz == WALL
+    dzf, dzc = metrics(g)
+    dzf_t = torch.from_numpy(dzf).to(rho.device)
+    dzc_t = torch.from_numpy(dzc).to(rho.device)[:, None, None]
+    fx = (1.0 - rho0 / (0.5 * (rho + _t_shift_plus(rho, 2, wx)))) * (_t_shift_plus(pstar, 2, wx) - pstar) / g.dx
+    fy = (1.0 - rho0 / (0.5 * (rho + _t_shift_plus(rho, 1, wy)))) * (_t_shift_plus(pstar, 1, wy) - pstar) / g.dy
+    rz = (rho * torch.roll(dzf_t, -1)[:, None, None] + _t_shift_plus(rho, 0, wz) * dzf_t[:, None, None]) / (2.0 * dzc_t)
+    fz = (1.0 - rho0 / rz) * (_t_shift_plus(pstar, 0, wz) - pstar) / dzc_t
+    del rz
+    f = div_t(g, fx, fy, fz)
+    del fx, fy, fz
+    f += (rho0 / dt) * div_t(g, u, v, w)
+    return f

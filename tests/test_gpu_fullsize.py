@@ -1,8 +1,11 @@
 """GPU tests at the workload sizes, in the launch configuration bench.py times:
-256^3 against the oracle element by element; 512^3 (and a triply periodic
-512^3) through the manufactured fixed point, which holds at any size;
-determinism and in-place operation."""
+256^3 against the oracle element by element; 512^3 (wall z, triply periodic,
+closed box) through the manufactured fixed point, which holds at any size;
+the 1024 x 1024 x 512 triply periodic emulsion through the fixed point on its
+density, oracle values at sampled cells and faces, and the divergence
+identity; determinism and in-place operation."""
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -91,10 +94,15 @@ def test_512_manufactured_fixed_point(pcx, bc, stretch):
     rng = np.random.Generator(np.random.PCG64(77))
     bub = W.place_bubbles(rng, g, [8 * g.dx] * 512)
     rho = torch.from_numpy(1000.0 + (1.0 - 1000.0) * W.phase_field(g, bub)).to("cuda")
-    rho0 = float(rho.min())
-    dt = (8 / 15) * 0.5 * min(g.dx, float(np.diff(g.zf).min()))
     _say(f"512^3 fixed point bc={bc}: building inputs on the GPU")
-    ps, us, vs, ws, q, ud, vd, wd = M.fixed_point_inputs_torch(1234 + bc[0] + 2 * bc[2], g, rho, dt)
+    _fixed_point(pcx, g, rho, 1234 + bc[0] + 2 * bc[2])
+
+
+def _fixed_point(pcx, g, rho, seed):
+    import torch
+    rho0 = float(rho.min())
+    dt = (8 / 15) * 0.5 * min(g.dx, g.dy, float(np.diff(g.zf).min()))
+    ps, us, vs, ws, q, ud, vd, wd = M.fixed_point_inputs_torch(seed, g, rho, dt)
     for prec, tol in (("fp64", 1e-12), ("fp32_refined", 1e-10)):
         plan = pcx.Plan(g, prec)
         uo, vo, wo, p, rep = plan.step(dt, rho0, rho, ps, us, vs, ws)
@@ -107,3 +115,81 @@ def test_512_manufactured_fixed_point(pcx, bc, stretch):
         assert ep <= tol and eu <= tol and rep["max_div_rel"] <= tol
         del uo, vo, wo, p
         plan.close()
+
+
+@pytest.fixture(scope="module")
+def case2():
+    _say("1024 x 1024 x 512 emulsion: generating inputs on the host")
+    t0 = time.time()
+    c = W.config2()
+    _say(f"  generated in {time.time() - t0:.0f} s: {c.meta}, dt {c.dt:.3e}, rho0 {c.rho0:.6f}")
+    return c
+
+
+@pytest.mark.timeout(900)
+def test_config2_emulsion_fixed_point(pcx, case2):
+    """Manufactured fixed point on the emulsion's own density (ratio 10,
+    2000 drops), triply periodic, at its full size."""
+    import torch
+    rho = torch.from_numpy(case2.rho).to("cuda")
+    _say("1024 x 1024 x 512 fixed point: building inputs on the GPU")
+    _fixed_point(pcx, case2.grid, rho, 4321)
+
+
+@pytest.mark.timeout(600)
+def test_config2_emulsion_step(pcx, orc, case2):
+    """The emulsion step itself, FP64 and refined: the RHS against a torch
+    RHS and against the oracle at sampled cells, the corrected velocity
+    against the oracle at sampled faces (from the GPU pressure), the
+    divergence identity D u_out = (dt/rho0)(f - L p) through an independent
+    divergence, and the refined result against the FP64 one."""
+    import torch
+    c = case2
+    g = c.grid
+    og = orc.Grid.from_workload(g)
+    rho, ps, u, v, w = [torch.from_numpy(a).to("cuda") for a in c.fields()]
+    plan = pcx.Plan(g, "fp64")
+    uo, vo, wo, p, rep = plan.step(c.dt, c.rho0, rho, ps, u, v, w)
+    torch.cuda.synchronize()
+    plan.close()
+    _say(f"fp64 report {rep}")
+    assert rep["max_div_rel"] <= 1e-12
+    pmax = float(p.abs().max())
+    assert abs(rep["mean_p"]) <= 1e-13 * pmax
+    f = M.rhs_t(g, c.dt, c.rho0, rho, ps, u, v, w)
+    finf = float(f.abs().max())
+    assert abs(finf - rep["f_inf"]) <= 1e-12 * finf
+    rng = np.random.default_rng(2024)
+    cells = rng.integers(0, g.cells, 20000)
+    fo = orc.rhs_at(og, c.dt, c.rho0, *c.fields(), cells)
+    ef = float(np.abs(f.flatten()[torch.from_numpy(cells).to("cuda")].cpu().numpy() - fo).max()) / finf
+    del f
+    dv = float(M.div_t(g, uo, vo, wo).abs().max())
+    _say(f"rhs vs oracle at 20000 cells {ef:.2e}; max|D u_out| {dv:.3e} "
+         f"= {dv / ((c.dt / c.rho0) * finf):.2e} of (dt/rho0)|f|")
+    assert ef <= 1e-12
+    assert dv <= 1e-12 * (c.dt / c.rho0) * finf
+    ph = p.cpu().numpy()
+    dirs = rng.integers(0, 3, 30000)
+    fcells = rng.integers(0, g.cells, 30000)
+    uref = orc.correct_at(og, c.dt, c.rho0, *c.fields(), ph, dirs, fcells)
+    outs = [t.flatten() for t in (uo, vo, wo)]
+    idx = torch.from_numpy(fcells).to("cuda")
+    got = np.empty(len(fcells))
+    for d in range(3):
+        sel = dirs == d
+        got[sel] = outs[d][idx[torch.from_numpy(sel).to("cuda")]].cpu().numpy()
+    umax = max(float(t.abs().max()) for t in (uo, vo, wo))
+    eu = float(np.abs(got - uref).max()) / umax
+    _say(f"u_out vs oracle at 30000 faces {eu:.2e}")
+    assert eu <= 1e-12
+    ref = [t.clone() for t in (uo, vo, wo, p)]
+    del uo, vo, wo, p, outs
+    plan = pcx.Plan(g, "fp32_refined")
+    uo, vo, wo, p, rep = plan.step(c.dt, c.rho0, rho, ps, u, v, w)
+    torch.cuda.synchronize()
+    plan.close()
+    e = {n: M.relerr_t(a, b) for n, a, b in zip("uvwp", (uo, vo, wo, p), ref)}
+    _say(f"refined report {rep}; vs fp64 {e}")
+    assert rep["converged"] == 1
+    assert max(e.values()) <= 1e-10 and rep["max_div_rel"] <= 1e-10

@@ -100,3 +100,19 @@ def test_small_refined(pcx, orc, dims, bc, stretch):
     assert rep["converged"] == 1
     assert max(e.values()) <= REF_TOL
     assert rep["max_div_rel"] <= REF_TOL
+
+
+@pytest.mark.parametrize("dims,ndrops,kmax", [((64, 64, 32), 6, 8.0), ((96, 96, 48), 12, 12.0)])
+def test_emulsion_small(pcx, orc, dims, ndrops, kmax):
+    """The triply periodic emulsion recipe (k^-5/3 solenoidal velocity,
+    density ratio 10) at sizes the oracle runs in seconds, both forms."""
+    case = W.emulsion(*dims, ndrops, 31 + dims[0], f"emulsion_{dims}", kmax=kmax)
+    ref, d = _oracle(orc, case)
+    for prec, tol in (("fp64", FP64_TOL), ("fp32_refined", REF_TOL)):
+        _say(f"case {case.name} {prec}")
+        plan = pcx.Plan(case.grid, prec)
+        got, rep = run_plan(plan, case)
+        e = errors(got, ref)
+        _say(f"errors {e} div {rep['max_div_rel']:.3e} solves {rep['solves']}")
+        assert max(e.values()) <= tol
+        assert rep["max_div_rel"] <= tol
