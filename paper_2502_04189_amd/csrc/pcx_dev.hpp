@@ -68,7 +68,7 @@ struct Dom {
     int ndiv_tiles;                   // divergence-only tiles (NT cells each)
     int cti, ctj, cnti, cntj, ckc, cnk; // marching tile TI x TJ cells, k chunk
     int mth, yth, xth;                // threads of the marching, y and x workgroups
-    FastDiv dnx, dny, dtj, dtk, dnyc, dcti;
+    FastDiv dnx, dny, dtj, dtk, dnyc, dcti, dM;
     double dx, dy, idx, idy, dt, rho0, irho0, lz, scale;
     // z tables (FP64): dzf, 1/dzf, 1/dzc, rho interpolation weights
     const double *dzf, *idzf, *idzc, *rzlo, *rzhi;
@@ -167,14 +167,20 @@ __device__ __forceinline__ int pidx(int e) { return e + (e >> 3); }
 // so consecutive lines start in different banks.
 __host__ __device__ constexpr int lds_line(int n) { return (((n - 1) + ((n - 1) >> 3) + 1 + 15) & ~15) + 1; }
 
+// Twiddle table of a length-n FFT as held in LDS: for even n only the first
+// n/2 roots, since W_n^(e + n/2) = -W_n^e.
+__host__ __device__ constexpr int tw_half(int n) { return (n & 1) ? n : n / 2; }
+
 // One Stockham autosort stage over `nlines` LDS lines of length n (line
 // stride ldb, padded positions): butterfly b = (line, j), j in [0, n/R):
 //   inputs  x[line][j + r n/R], r < R
 //   twiddle W_{ns R}^{(j mod ns) r}
 //   outputs y[line][(j / ns) ns R + (j mod ns) + r ns]
 // Results are held in registers across a barrier, so the stage is in place.
+// Twiddles come from an LDS copy of the first th roots (see stage_twiddles).
 template <typename T, bool INV, int R, int NTH>
-__device__ __forceinline__ void fft_stage(c2<T> *buf, int ldb, int nlines, const FftDesc &fd, int s)
+__device__ __forceinline__ void fft_stage(c2<T> *buf, int ldb, int nlines, const FftDesc &fd, int s,
+                                          const c2<T> *tw, int th)
 {
     using C = c2<T>;
     constexpr int K = (MAXPTS / NTH + R - 1) / R;
@@ -182,7 +188,6 @@ __device__ __forceinline__ void fft_stage(c2<T> *buf, int ldb, int nlines, const
     const int total = nlines * nb;
     const int ns = fd.ns[s];
     const int tws = fd.tws[s];
-    const C *tw = (const C *)fd.tw;
     C v[K][R];
     int lo[K], oo[K];
 #pragma unroll
@@ -201,7 +206,8 @@ __device__ __forceinline__ void fft_stage(c2<T> *buf, int ldb, int nlines, const
             if (ns > 1) {
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    C w = tw[jm * r * tws];
+                    const int e = jm * r * tws;
+                    C w = e < th ? tw[e] : C{-tw[e - th].x, -tw[e - th].y};
                     if (INV) w.y = -w.y;
                     v[t][r] = cmul(v[t][r], w);
                 }
@@ -226,16 +232,57 @@ __device__ __forceinline__ void fft_stage(c2<T> *buf, int ldb, int nlines, const
 // Complex FFT (unnormalised) of nlines LDS lines; all threads participate.
 // Entry and exit are barrier-separated from the caller's LDS traffic.
 template <typename T, bool INV, int NTH = NT>
-__device__ void lds_fft(c2<T> *buf, int ldb, int nlines, const FftDesc &fd)
+__device__ void lds_fft(c2<T> *buf, int ldb, int nlines, const FftDesc &fd, const c2<T> *tw)
 {
+    const int th = tw_half(fd.n);
     for (int s = 0; s < fd.nst; ++s) {
         switch (fd.rad[s]) {
-        case 2: fft_stage<T, INV, 2, NTH>(buf, ldb, nlines, fd, s); break;
-        case 3: fft_stage<T, INV, 3, NTH>(buf, ldb, nlines, fd, s); break;
-        case 4: fft_stage<T, INV, 4, NTH>(buf, ldb, nlines, fd, s); break;
-        default: fft_stage<T, INV, 8, NTH>(buf, ldb, nlines, fd, s); break;
+        case 2: fft_stage<T, INV, 2, NTH>(buf, ldb, nlines, fd, s, tw, th); break;
+        case 3: fft_stage<T, INV, 3, NTH>(buf, ldb, nlines, fd, s, tw, th); break;
+        case 4: fft_stage<T, INV, 4, NTH>(buf, ldb, nlines, fd, s, tw, th); break;
+        default: fft_stage<T, INV, 8, NTH>(buf, ldb, nlines, fd, s, tw, th); break;
         }
     }
+}
+
+// Copies the first tw_half(n) roots of fd into LDS (no barrier: the caller's
+// next barrier publishes them).
+template <typename T, int NTH>
+__device__ __forceinline__ void stage_twiddles(c2<T> *ltw, const FftDesc &fd)
+{
+    const c2<T> *tw = (const c2<T> *)fd.tw;
+    const int th = tw_half(fd.n);
+    for (int e = threadIdx.x; e < th; e += NTH) ltw[e] = tw[e];
+}
+
+// ------------------------------------------------------- staged copies
+// Moves `total` elements with all of a thread's reads of one round issued
+// before its first write, CNT per thread per round: a global -> LDS copy
+// then waits for one memory latency per round instead of one per element.
+// get(e) returns element e, put(e, v) stores it.
+// staged_copy_t: the same for worker `tid` of STRIDE workers (a wave's lanes).
+template <int STRIDE, int CNT, typename V, typename Get, typename Put>
+__device__ __forceinline__ void staged_copy_t(int tid, int total, Get get, Put put)
+{
+    for (int b = 0; b < total; b += CNT * STRIDE) {
+        V v[CNT];
+#pragma unroll
+        for (int t = 0; t < CNT; ++t) {
+            int e = b + tid + t * STRIDE;
+            if (e < total) v[t] = get(e);
+        }
+#pragma unroll
+        for (int t = 0; t < CNT; ++t) {
+            int e = b + tid + t * STRIDE;
+            if (e < total) put(e, v[t]);
+        }
+    }
+}
+
+template <int NTH, int CNT, typename V, typename Get, typename Put>
+__device__ __forceinline__ void staged_copy(int total, Get get, Put put)
+{
+    staged_copy_t<NTH, CNT, V>((int)threadIdx.x, total, get, put);
 }
 
 // ------------------------------------------------------------- reductions

@@ -150,6 +150,10 @@ void choose_shapes(const pcx_grid &g, int prec, const TuneParams *tp, Shapes &sh
         if (tp->tk > 0) tk = tp->tk;
         if (tp->zg > 0) G = tp->zg;
     }
+    // a tile never holds more than MAXPTS points (register staging of the
+    // pipelined passes assumes it), whatever a tune cache says
+    while (tj > 1 && (long)tj * std::max(M, 1) > MAXPTS) tj >>= 1;
+    while (tk > 1 && (long)tk * g.ny > MAXPTS) tk >>= 1;
     sh.tj = std::max(1, tj);
     sh.tk = std::max(1, tk);
     sh.zg = G;
@@ -197,6 +201,7 @@ pcx_status build_domain(const pcx_grid &g, int prec, const Shapes &sh, const Rad
     d.ncell_tiles = d.cnti * d.cntj * d.cnk;
     d.dnx = mkdiv(nx); d.dny = mkdiv(ny); d.dtj = mkdiv(sh.tj); d.dtk = mkdiv(sh.tk); d.dnyc = mkdiv(ny);
     d.dcti = mkdiv(d.cti);
+    d.dM = mkdiv(M);
     d.dx = g.lx / nx; d.dy = g.ly / ny;
     d.idx = 1.0 / d.dx; d.idy = 1.0 / d.dy;
     d.lz = g.zf[nz] - g.zf[0];
@@ -284,8 +289,14 @@ pcx_status build_domain(const pcx_grid &g, int prec, const Shapes &sh, const Rad
     return PCX_OK;
 }
 
-size_t lds_x(const Dom &d, int prec) { return (size_t)d.tj * lds_line(d.nl) * (prec == PREC_F64 ? 16 : 8) + 64; }
-size_t lds_y(const Dom &d, int prec) { return (size_t)d.tk * lds_line(d.ny) * (prec == PREC_F64 ? 16 : 8) + 64; }
+size_t lds_x(const Dom &d, int prec)
+{
+    return ((size_t)d.tj * lds_line(d.nl) + tw_half(d.M)) * (prec == PREC_F64 ? 16 : 8) + 64;
+}
+size_t lds_y(const Dom &d, int prec)
+{
+    return ((size_t)d.tk * lds_line(d.ny) + tw_half(d.ny)) * (prec == PREC_F64 ? 16 : 8) + 64;
+}
 size_t lds_z(const Dom &d, int prec)
 {
     size_t e = (size_t)d.zlpw * d.nz;

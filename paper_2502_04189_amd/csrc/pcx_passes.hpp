@@ -297,27 +297,31 @@ __device__ void pass_xfwd(const Dom &d, int tile, char *smem)
     using C = c2<T>;
     C *buf = (C *)smem;
     const int ldr = lds_line(d.nl);
+    C *ltw = buf + d.tj * ldr;
     const int jt = tile % d.ntj, k = tile / d.ntj;
     const int j0 = jt * d.tj;
     const int rows = min(d.tj, d.ny - j0);
-    const int nx = d.nx;
+    const int nx = d.nx, M = d.M, half = M / 2;
     const double *src = (SRC == SRC_RHS ? d.f : d.r) + ((size_t)k * d.ny + j0) * nx;
+    stage_twiddles<T, NTH>(ltw, d.fx);
     const bool wx = d.bcx == BC_WALL;
-    for (int idx = threadIdx.x; idx < rows * nx; idx += NTH) {
-        int r = (int)fdiv((uint32_t)idx, d.dnx);
-        int i = idx - r * nx;
-        // wall x: cosine transform by reordering v[n] = s[2n], v[N-1-n] = s[2n+1]
-        int n = wx ? ((i & 1) ? nx - 1 - (i >> 1) : (i >> 1)) : i;
-        ((T *)(buf + r * ldr + pidx(n >> 1)))[n & 1] = (T)src[idx];
-    }
-    __syncthreads();
-    lds_fft<T, false, NTH>(buf, ldr, rows, d.fx);
+    const int hx = nx >> 1;
+    const double2 *src2 = (const double2 *)src;
     const C *twr = (const C *)d.twr;
-    const int M = d.M, half = M / 2;
-    for (int idx = threadIdx.x; idx < rows * (half + 1); idx += NTH) {
-        int r = idx / (half + 1);
-        int l = idx - r * (half + 1);
-        C *row = buf + r * ldr;
+    const C *wd = (const C *)d.dctx;
+    // pairs (s[2h], s[2h+1]) form complex point h of the half-length FFT;
+    // wall x: cosine transform by reordering v[h] = s[2h], v[N-1-h] = s[2h+1]
+    auto put_pair = [&](C *row, int h, double2 s) {
+        if (!wx) {
+            row[pidx(h)] = C{(T)s.x, (T)s.y};
+        } else {
+            int n1 = nx - 1 - h;
+            ((T *)(row + pidx(h >> 1)))[h & 1] = (T)s.x;
+            ((T *)(row + pidx(n1 >> 1)))[n1 & 1] = (T)s.y;
+        }
+    };
+    // split of the half-length spectrum, l in [0, M/2]
+    auto split = [&](C *row, int l) {
         if (l == 0) {
             C z0 = row[0];
             row[0] = C{z0.x + z0.y, T(0)};
@@ -333,43 +337,63 @@ __device__ void pass_xfwd(const Dom &d, int tile, char *smem)
             row[pidx(l)] = cadd(e, wo);
             row[pidx(M - l)] = cconj(csub(e, wo));
         }
-    }
-    __syncthreads();
-    if (wx) {
-        // DCT-II from the real FFT V of the reordered row: A_k = W_{4N}^k V_k,
-        // X_k = Re A_k, X_{N-k} = -Im A_k (k = 0..M); stored as real modes
-        const C *wd = (const C *)d.dctx;
-        for (int idx = threadIdx.x; idx < rows * (M + 1); idx += NTH) {
-            int r = idx / (M + 1);
-            int kk = idx - r * (M + 1);
-            C *row = buf + r * ldr;
-            C a = cmul(wd[kk], row[pidx(kk)]);
-            row[pidx(kk)] = C{a.x, T(0)};
-            if (kk >= 1 && kk < M) row[pidx(nx - kk)] = C{-a.y, T(0)};
+    };
+    // DCT-II from the real FFT V of the reordered row: A_k = W_{4N}^k V_k,
+    // X_k = Re A_k, X_{N-k} = -Im A_k (k in [0, M]); stored as real modes
+    auto dct = [&](C *row, int kk) {
+        C a = cmul(wd[kk], row[pidx(kk)]);
+        row[pidx(kk)] = C{a.x, T(0)};
+        if (kk >= 1 && kk < M) row[pidx(nx - kk)] = C{-a.y, T(0)};
+    };
+    {
+        staged_copy<NTH, 8, double2>(
+            rows * hx, [&](int e) { return src2[e]; },
+            [&](int e, double2 s) {
+                int r = (int)fdiv((uint32_t)e, d.dM);
+                put_pair(buf + r * ldr, e - r * hx, s);
+            });
+        __syncthreads();
+        lds_fft<T, false, NTH>(buf, ldr, rows, d.fx, ltw);
+        for (int idx = threadIdx.x; idx < rows * (half + 1); idx += NTH) {
+            int r = idx / (half + 1);
+            split(buf + r * ldr, idx - r * (half + 1));
         }
         __syncthreads();
+        if (wx) {
+            for (int idx = threadIdx.x; idx < rows * (M + 1); idx += NTH) {
+                int r = idx / (M + 1);
+                dct(buf + r * ldr, idx - r * (M + 1));
+            }
+            __syncthreads();
+        }
     }
     C *s1 = (C *)d.s1;
     const int tj = d.tj, nl = d.nl;
-    for (int idx = threadIdx.x; idx < tj * nl; idx += NTH) {
-        int l = (int)fdiv((uint32_t)idx, d.dtj);
-        int r = idx - l * tj;
-        if (r < rows) s1[((size_t)k * nl + l) * d.ny + j0 + r] = buf[r * ldr + pidx(l)];
-    }
+    staged_copy<NTH, 8, C>(
+        tj * nl,
+        [&](int e) {
+            int l = (int)fdiv((uint32_t)e, d.dtj);
+            int r = e - l * tj;
+            return buf[min(r, rows - 1) * ldr + pidx(l)];
+        },
+        [&](int e, C v) {
+            int l = (int)fdiv((uint32_t)e, d.dtj);
+            int r = e - l * tj;
+            if (r < rows) s1[((size_t)k * nl + l) * d.ny + j0 + r] = v;
+        });
 }
 
-// ------------------------------------------------------------------- y pass
-// Tile = (k tile, l): columns k0 .. k0+cols-1 of mode l.
+// Y pass, tile = (k tile, l).  Forward: columns (k, l) of S1 -> LDS -> FFT
+// (DCT-II for a wall) -> corner turn into the z-lines of S2; inverse the
+// reverse.
 template <typename T, bool INV, int NTH = NT>
 __device__ void pass_y(const Dom &d, int tile, char *smem)
 {
     using C = c2<T>;
     C *buf = (C *)smem;
-    const int kt = tile % d.ntk, l = tile / d.ntk;
-    const int k0 = kt * d.tk;
-    const int cols = min(d.tk, d.nz - k0);
     const int ny = d.ny, nz = d.nz, nl = d.nl, tk = d.tk;
     const int ldc = lds_line(ny);
+    C *ltw = buf + tk * ldc;
     const bool wy = d.bcy == BC_WALL;
     // wall y: cosine transform by reordering v[n] = c[2n], v[N-1-n] = c[2n+1]
     auto pos = [&](int j) { return wy ? ((j & 1) ? ny - 1 - (j >> 1) : (j >> 1)) : j; };
@@ -377,25 +401,39 @@ __device__ void pass_y(const Dom &d, int tile, char *smem)
     C *s2 = (C *)d.s2;
     const C *wd = (const C *)d.dcty;
     const int hy = ny / 2;
+    const int kt = tile % d.ntk, l = tile / d.ntk;
+    const int k0 = kt * tk;
+    const int cols = min(tk, nz - k0);
+    stage_twiddles<T, NTH>(ltw, d.fy);
     if (!INV) {
-        for (int idx = threadIdx.x; idx < cols * ny; idx += NTH) {
-            int c = (int)fdiv((uint32_t)idx, d.dnyc);
-            int j = idx - c * ny;
-            buf[c * ldc + pidx(pos(j))] = s1[((size_t)(k0 + c) * nl + l) * ny + j];
-        }
+        staged_copy<NTH, 8, C>(
+            cols * ny,
+            [&](int e) {
+                const int c = (int)fdiv((uint32_t)e, d.dnyc), j = e - c * ny;
+                return s1[((size_t)(k0 + c) * nl + l) * ny + j];
+            },
+            [&](int e, C v) {
+                const int c = (int)fdiv((uint32_t)e, d.dnyc), j = e - c * ny;
+                buf[c * ldc + pidx(pos(j))] = v;
+            });
     } else {
-        for (int idx = threadIdx.x; idx < tk * ny; idx += NTH) {
-            int m = (int)fdiv((uint32_t)idx, d.dtk);
-            int c = idx - m * tk;
-            if (c < cols) buf[c * ldc + pidx(m)] = s2[((size_t)l * ny + m) * nz + k0 + c];
-        }
+        staged_copy<NTH, 8, C>(
+            tk * ny,
+            [&](int e) {
+                const int m = (int)fdiv((uint32_t)e, d.dtk), c = e - m * tk;
+                return s2[((size_t)l * ny + m) * nz + k0 + min(c, cols - 1)];
+            },
+            [&](int e, C v) {
+                const int m = (int)fdiv((uint32_t)e, d.dtk), c = e - m * tk;
+                if (c < cols) buf[c * ldc + pidx(m)] = v;
+            });
         if (wy) {
             // inverse DCT-II of complex columns: V_k = conj(w_k)(X_k - i X_{N-k}),
             // V_{N-k} = i w_k (X_{N-k} - i X_k), w_k = W_{4N}^k, X_N = 0
             __syncthreads();
             for (int idx = threadIdx.x; idx < cols * hy; idx += NTH) {
-                int c = idx / hy;
-                int kk = idx - c * hy + 1;
+                const int c = idx / hy;
+                const int kk = idx - c * hy + 1;
                 C *col = buf + c * ldc;
                 const int kn = ny - kk;
                 C w = wd[kk];
@@ -411,15 +449,15 @@ __device__ void pass_y(const Dom &d, int tile, char *smem)
         }
     }
     __syncthreads();
-    lds_fft<T, INV, NTH>(buf, ldc, cols, d.fy);
+    lds_fft<T, INV, NTH>(buf, ldc, cols, d.fy, ltw);
     if (!INV) {
         if (wy) {
             // DCT-II of complex columns from the FFT V of the reordered data:
             // X_k = (w_k V_k + conj(w_k) V_{N-k}) / 2,
             // X_{N-k} = i (w_k V_k - conj(w_k) V_{N-k}) / 2, X_0 = V_0
             for (int idx = threadIdx.x; idx < cols * hy; idx += NTH) {
-                int c = idx / hy;
-                int kk = idx - c * hy + 1;
+                const int c = idx / hy;
+                const int kk = idx - c * hy + 1;
                 C *col = buf + c * ldc;
                 const int kn = ny - kk;
                 C w = wd[kk];
@@ -429,17 +467,27 @@ __device__ void pass_y(const Dom &d, int tile, char *smem)
             }
             __syncthreads();
         }
-        for (int idx = threadIdx.x; idx < tk * ny; idx += NTH) {
-            int m = (int)fdiv((uint32_t)idx, d.dtk);
-            int c = idx - m * tk;
-            if (c < cols) s2[((size_t)l * ny + m) * nz + k0 + c] = buf[c * ldc + pidx(m)];
-        }
+        staged_copy<NTH, 8, C>(
+            tk * ny,
+            [&](int e) {
+                const int m = (int)fdiv((uint32_t)e, d.dtk), c = e - m * tk;
+                return buf[min(c, cols - 1) * ldc + pidx(m)];
+            },
+            [&](int e, C v) {
+                const int m = (int)fdiv((uint32_t)e, d.dtk), c = e - m * tk;
+                if (c < cols) s2[((size_t)l * ny + m) * nz + k0 + c] = v;
+            });
     } else {
-        for (int idx = threadIdx.x; idx < cols * ny; idx += NTH) {
-            int c = (int)fdiv((uint32_t)idx, d.dnyc);
-            int j = idx - c * ny;
-            s1[((size_t)(k0 + c) * nl + l) * ny + j] = buf[c * ldc + pidx(pos(j))];
-        }
+        staged_copy<NTH, 8, C>(
+            cols * ny,
+            [&](int e) {
+                const int c = (int)fdiv((uint32_t)e, d.dnyc), j = e - c * ny;
+                return buf[c * ldc + pidx(pos(j))];
+            },
+            [&](int e, C v) {
+                const int c = (int)fdiv((uint32_t)e, d.dnyc), j = e - c * ny;
+                s1[((size_t)(k0 + c) * nl + l) * ny + j] = v;
+            });
     }
 }
 
@@ -471,7 +519,7 @@ __device__ void pass_z(const Dom &d, int tile, char *smem)
     const int nelem = nlin * nz;
     // padded LDS index: one spare slot per 16 elements
 #define ZP(e) ((e) + ((e) >> 4))
-    for (int e = threadIdx.x; e < nelem; e += NT) buf[ZP(e)] = s2[gbase + e];
+    staged_copy<NT, 8, C>(nelem, [&](int e) { return s2[gbase + e]; }, [&](int e, C v) { buf[ZP(e)] = v; });
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -630,7 +678,7 @@ __device__ void pass_z(const Dom &d, int tile, char *smem)
             if (s < S) buf[ZP(gl * nz + k0 + s)] = y[s];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < nelem; e += NT) s2[gbase + e] = buf[ZP(e)];
+    staged_copy<NT, 8, C>(nelem, [&](int e) { return buf[ZP(e)]; }, [&](int e, C v) { s2[gbase + e] = v; });
 #undef ZP
 }
 
@@ -643,41 +691,39 @@ __device__ void pass_xinv(const Dom &d, int tile, char *smem, int solve)
     using C = c2<T>;
     C *buf = (C *)smem;
     const int ldr = lds_line(d.nl);
-    double *red = (double *)(smem + (size_t)d.tj * ldr * sizeof(C));
+    C *ltw = buf + d.tj * ldr;
+    double *red = (double *)(ltw + tw_half(d.fx.n));
+    stage_twiddles<T, NTH>(ltw, d.fx);
     const int jt = tile % d.ntj, k = tile / d.ntj;
     const int j0 = jt * d.tj;
     const int rows = min(d.tj, d.ny - j0);
-    const int nx = d.nx, nl = d.nl, tj = d.tj;
+    const int nx = d.nx, nl = d.nl, tj = d.tj, M = d.M, half = M / 2;
     const C *s1 = (const C *)d.s1;
-    for (int idx = threadIdx.x; idx < tj * nl; idx += NTH) {
-        int l = (int)fdiv((uint32_t)idx, d.dtj);
-        int r = idx - l * tj;
-        if (r < rows) buf[r * ldr + pidx(l)] = s1[((size_t)k * nl + l) * d.ny + j0 + r];
-    }
+    staged_copy<NTH, 8, C>(
+        tj * nl,
+        [&](int e) {
+            int l = (int)fdiv((uint32_t)e, d.dtj);
+            int r = e - l * tj;
+            return s1[((size_t)k * nl + l) * d.ny + j0 + min(r, rows - 1)];
+        },
+        [&](int e, C v) {
+            int l = (int)fdiv((uint32_t)e, d.dtj);
+            int r = e - l * tj;
+            if (r < rows) buf[r * ldr + pidx(l)] = v;
+        });
     __syncthreads();
     const bool wx = d.bcx == BC_WALL;
-    if (wx) {
-        // inverse DCT-II: half spectrum of the reordered row,
-        // V_k = conj(W_{4N}^k) (X_k - i X_{N-k}), X_N = 0, k = 0..M
-        const C *wd = (const C *)d.dctx;
-        const int Mh = nx / 2;
-        for (int idx = threadIdx.x; idx < rows * (Mh + 1); idx += NTH) {
-            int r = idx / (Mh + 1);
-            int kk = idx - r * (Mh + 1);
-            C *row = buf + r * ldr;
-            T xk = row[pidx(kk)].x;
-            T xn = kk == 0 ? T(0) : row[pidx(nx - kk)].x;
-            row[pidx(kk)] = cmul(cconj(wd[kk]), C{xk, -xn});
-        }
-        __syncthreads();
-    }
-    // Z[l] = E + i O,  E = X[l] + conj(X[M-l]),  O = (X[l] - conj(X[M-l])) conj(W^l)
+    const C *wd = (const C *)d.dctx;
     const C *twr = (const C *)d.twr;
-    const int M = d.M, half = M / 2;
-    for (int idx = threadIdx.x; idx < rows * (half + 1); idx += NTH) {
-        int r = idx / (half + 1);
-        int l = idx - r * (half + 1);
-        C *row = buf + r * ldr;
+    // inverse DCT-II: half spectrum of the reordered row,
+    // V_k = conj(W_{4N}^k) (X_k - i X_{N-k}), X_N = 0, k in [0, M]
+    auto dct_pre = [&](C *row, int kk) {
+        T xk = row[pidx(kk)].x;
+        T xn = kk == 0 ? T(0) : row[pidx(nx - kk)].x;
+        row[pidx(kk)] = cmul(cconj(wd[kk]), C{xk, -xn});
+    };
+    // Z[l] = E + i O,  E = X[l] + conj(X[M-l]),  O = (X[l] - conj(X[M-l])) conj(W^l)
+    auto c2r_pre = [&](C *row, int l) {
         if (l == 0) {
             T a = row[0].x, b = row[pidx(M)].x;
             row[0] = C{a + b, a - b};
@@ -694,25 +740,60 @@ __device__ void pass_xinv(const Dom &d, int tile, char *smem, int solve)
                 row[pidx(M - l)] = cadd(cconj(e), ioc);
             }
         }
-    }
-    __syncthreads();
-    lds_fft<T, true, NTH>(buf, ldr, rows, d.fx);
+    };
     // accumulation also removes the FP64 volume mean of the previous p: the
     // residual cannot see a constant, so the FP32 gauge error of earlier
     // solves is cancelled here
     const double shift = (MODE == XOUT_ACCUM) ? d.pmean[0] : 0.0;
     double emax = 0.0, pmax = 0.0, psum = 0.0;
-    for (int idx = threadIdx.x; idx < rows * nx; idx += NTH) {
-        int r = (int)fdiv((uint32_t)idx, d.dnx);
-        int i = idx - r * nx;
-        int n = wx ? ((i & 1) ? nx - 1 - (i >> 1) : (i >> 1)) : i;
-        double val = (double)((const T *)(buf + r * ldr + pidx(n >> 1)))[n & 1];
-        size_t g = ((size_t)k * d.ny + j0 + r) * nx + i;
-        double pv = (MODE == XOUT_STORE) ? val : (d.po[g] - shift) + val;
-        d.po[g] = pv;
-        psum += pv;
-        emax = amax_nan(emax, val);
-        pmax = amax_nan(pmax, pv);
+    const int hx = nx >> 1;
+    double2 *po2 = (double2 *)(d.po + ((size_t)k * d.ny + j0) * nx);
+    // output pairs p[2h], p[2h+1] of row r: complex point h of the
+    // half-length FFT, or (wall x) points h and N-1-h of the reordered sequence
+    auto value = [&](const C *row, int h) {
+        if (!wx) {
+            C z = row[pidx(h)];
+            return double2{(double)z.x, (double)z.y};
+        }
+        int n1 = nx - 1 - h;
+        return double2{(double)((const T *)(row + pidx(h >> 1)))[h & 1],
+                       (double)((const T *)(row + pidx(n1 >> 1)))[n1 & 1]};
+    };
+    auto emit = [&](int e, double2 val, double2 old) {
+        double2 pv = (MODE == XOUT_STORE) ? val : double2{(old.x - shift) + val.x, (old.y - shift) + val.y};
+        po2[e] = pv;
+        psum += pv.x + pv.y;
+        emax = amax_nan(amax_nan(emax, val.x), val.y);
+        pmax = amax_nan(amax_nan(pmax, pv.x), pv.y);
+    };
+    {
+        if (wx) {
+            for (int idx = threadIdx.x; idx < rows * (M + 1); idx += NTH) {
+                int r = idx / (M + 1);
+                dct_pre(buf + r * ldr, idx - r * (M + 1));
+            }
+            __syncthreads();
+        }
+        for (int idx = threadIdx.x; idx < rows * (half + 1); idx += NTH) {
+            int r = idx / (half + 1);
+            c2r_pre(buf + r * ldr, idx - r * (half + 1));
+        }
+        __syncthreads();
+        lds_fft<T, true, NTH>(buf, ldr, rows, d.fx, ltw);
+        if (MODE == XOUT_STORE) {
+            for (int e = threadIdx.x; e < rows * hx; e += NTH) {
+                int r = (int)fdiv((uint32_t)e, d.dM);
+                emit(e, value(buf + r * ldr, e - r * hx), double2{0.0, 0.0});
+            }
+        } else {
+            // accumulate: the reads of the old p are issued together first
+            staged_copy<NTH, 8, double2>(
+                rows * hx, [&](int e) { return po2[e]; },
+                [&](int e, double2 old) {
+                    int r = (int)fdiv((uint32_t)e, d.dM);
+                    emit(e, value(buf + r * ldr, e - r * hx), old);
+                });
+        }
     }
     if (d.ppart) {
         double ts = block_sum<NTH>(psum, red);
