@@ -186,7 +186,8 @@ pcx_status build_domain(const pcx_grid &g, int prec, const Shapes &sh, const Rad
     d.yth = sh.yth;
     d.xth = sh.xth;
     d.cti = std::min(nx, 64);
-    d.ctj = std::max(1, std::min(ny, sh.mth / d.cti));
+    // the tile's halo (7 (TI + TJ) items, see pass_corr) fits two items per thread
+    d.ctj = std::max(1, std::min({ny, sh.mth / d.cti, 2 * sh.mth / 7 - d.cti}));
     d.cnti = (nx + d.cti - 1) / d.cti;
     d.cntj = (ny + d.ctj - 1) / d.ctj;
     if (sh.batch) {

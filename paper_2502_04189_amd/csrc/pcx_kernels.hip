@@ -24,7 +24,7 @@ constexpr int MT = 512;
 
 __global__ __launch_bounds__(MT) void k_rhs(Dom d)
 {
-    __shared__ double sm[8 + 2 * MT];
+    __shared__ double sm[8 + 6 * MT];
     const int t = xcd_tile(d.ncell_tiles);
     if (t >= d.ncell_tiles) return;
     pass_rhs<MT>(d, t, (char *)sm);
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(NTH) void k_xinv(Dom d, int solve)
 
 __global__ __launch_bounds__(MT) void k_corr(Dom d, int divcheck)
 {
-    __shared__ double sm[8 + 4 * MT];
+    __shared__ double sm[8 + 7 * MT];
     const int t = xcd_tile(d.ncell_tiles);
     if (t >= d.ncell_tiles) return;
     pass_corr<MT>(d, t, (char *)sm, divcheck != 0);

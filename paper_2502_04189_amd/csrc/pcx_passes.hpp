@@ -80,22 +80,83 @@ __device__ __forceinline__ double amax_nan(double m, double v)
     return (a > m || a != a) ? a : m;
 }
 
+// Halo of an RHS tile (see the correction's halo below for the layout
+// rules), 5 (TI + TJ) items:
+//   north row: p*, rho      items [0, 2 TI)
+//   south row: v*, p*, rho  items [2 TI, 5 TI)
+//   east col:  p*, rho      items [5 TI, 5 TI + 2 TJ)
+//   west col:  u*, p*, rho  items [5 TI + 2 TJ, 5 (TI + TJ))
+struct Halo {
+    const double *fp[2];
+    int off[2];
+};
+
+__device__ __forceinline__ Halo rhs_halo(const Dom &d, int tile, int nth)
+{
+    const int per = d.cnti * d.cntj;
+    const int rem = tile - (tile / per) * per;
+    const int jt = rem / d.cnti, it = rem - jt * d.cnti;
+    const int TI = d.cti, TJ = d.ctj, nx = d.nx, ny = d.ny;
+    const int i0 = it * TI, j0 = jt * TJ;
+    const int w = min(TI, nx - i0), h = min(TJ, ny - j0);
+    const int ie = (i0 + w == nx) ? 0 : i0 + w, je = (j0 + h == ny) ? 0 : j0 + h;
+    const int iw = (i0 == 0) ? nx - 1 : i0 - 1, js = (j0 == 0) ? ny - 1 : j0 - 1;
+    auto pr = [&](int f) { return f == 0 ? d.ps : d.rho; };
+    Halo H;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int q = threadIdx.x + s * nth;
+        int i = 0, j = 0;
+        const double *fp = d.ps;
+        if (q < 2 * TI) {
+            const int f = q / TI, x = min(q - f * TI, w - 1);
+            fp = pr(f); i = i0 + x; j = je;
+        } else if (q < 5 * TI) {
+            const int f = (q - 2 * TI) / TI, x = min(q - 2 * TI - f * TI, w - 1);
+            fp = f == 0 ? d.v : pr(f - 1); i = i0 + x; j = js;
+        } else if (q < 5 * TI + 2 * TJ) {
+            const int f = (q - 5 * TI) / TJ, y = min(q - 5 * TI - f * TJ, h - 1);
+            fp = pr(f); i = ie; j = j0 + y;
+        } else {
+            const int qq = min(q - 5 * TI - 2 * TJ, 3 * TJ - 1);
+            const int f = qq / TJ, y = min(qq - f * TJ, h - 1);
+            fp = f == 0 ? d.u : pr(f - 1); i = iw; j = j0 + y;
+        }
+        H.fp[s] = fp;
+        H.off[s] = j * nx + i;
+    }
+    return H;
+}
+
 // f = (rho0/dt) D u* + D[(1 - rho0/rho_face) G p*], stored in FP64 to d.f.
-// Face fluxes: x from this lane and its west lane, y computed on both faces,
-// z carried from the previous plane.
+// Marching in k; the neighbours in x and y come through LDS (the tile's own
+// plane) or from the halo; the z flux and w* below are carried from the
+// previous plane.  Every global read of plane k+1 is issued while plane k
+// is computed.  LDS: 8 reduction slots, p* / rho / u* / v* of the plane and
+// the halo items.
 template <int NTH = NT>
 __device__ void pass_rhs(const Dom &d, int tile, char *smem)
 {
     double *red = (double *)smem;
-    double *sP = red + 8, *sR = sP + NTH;
+    double *sP = red + 8, *sR = sP + NTH, *sU = sR + NTH, *sV = sU + NTH, *hal = sV + NTH;
     const MTile t = march_tile(d, tile);
     const MNbr n = march_nbr(d, t);
-    const int nx = d.nx, nz = d.nz, sz = nx * d.ny, TI = d.cti;
+    const int nx = d.nx, ny = d.ny, nz = d.nz, sz = nx * ny, TI = d.cti, TJ = d.ctj;
     const int col = t.j * nx + t.i;
     const double rr0 = d.rho0, tr0 = 2.0 * d.rho0;
     const double idx2 = d.idx * d.idx, idy2 = d.idy * d.idy, cdiv = d.rho0 / d.dt;
+    const int nh = 5 * (TI + TJ);
+    const Halo H = rhs_halo(d, tile, NTH);
+    const bool hv0 = threadIdx.x < nh, hv1 = threadIdx.x + NTH < nh;
+    const int i0 = t.i - t.ti, j0 = t.j - t.tj;
+    const bool inE = t.ti + 1 < min(TI, nx - i0), inN = t.tj + 1 < min(TJ, ny - j0);
+    const int me = threadIdx.x;
+    auto kp = [&](int k) { return k == nz - 1 ? 0 : k + 1; };
     int k = t.kb;
     double Pc = d.ps[k * sz + col], Rc = d.rho[k * sz + col];
+    double Pp = d.ps[kp(k) * sz + col], Rp = d.rho[kp(k) * sz + col];
+    double U = d.u[k * sz + col], V = d.v[k * sz + col], W = d.w[k * sz + col];
+    double h0 = hv0 ? H.fp[0][k * sz + H.off[0]] : 0.0, h1 = hv1 ? H.fp[1][k * sz + H.off[1]] : 0.0;
     double Fb = 0.0, Wb = 0.0; // flux of (1 - rho0/rho) G p* and w* on face k - 1/2
     if (!(d.bcz == BC_WALL && k == 0)) {
         const int km = (k == 0) ? nz - 1 : k - 1;
@@ -105,38 +166,42 @@ __device__ void pass_rhs(const Dom &d, int tile, char *smem)
     }
     double amax = 0.0;
     for (; k < t.ke; ++k) {
-        const int c = k * sz + col;
-        const int kp = (k == nz - 1) ? 0 : k + 1;
-        const bool wt = d.bcz == BC_WALL && k == nz - 1;
-        const double Pp = d.ps[kp * sz + col], Rp = d.rho[kp * sz + col];
-        const double u = d.u[c], v = d.v[c], w = d.w[c];
-        double Pe = __shfl_down(Pc, 1, 64), Re = __shfl_down(Rc, 1, 64);
-        if (!n.she) { Pe = d.ps[c + n.oe]; Re = d.rho[c + n.oe]; }
-        const double Fe = n.we ? 0.0 : (1.0 - tr0 * rcp_nr(Rc + Re)) * (Pe - Pc);
-        double Fw = __shfl_up(Fe, 1, 64), uw = __shfl_up(u, 1, 64);
-        if (!n.shw) {
-            const double Pw = d.ps[c + n.ow], Rw = d.rho[c + n.ow];
-            Fw = n.ww ? 0.0 : (1.0 - tr0 * rcp_nr(Rw + Rc)) * (Pc - Pw);
-            uw = d.u[c + n.ow];
+        // prefetch plane k+1
+        const bool more = k + 1 < t.ke;
+        double P2 = 0.0, R2 = 0.0, U1 = 0.0, V1 = 0.0, W1 = 0.0, g0 = 0.0, g1 = 0.0;
+        if (more) {
+            const int k1 = k + 1, k2 = kp(k1);
+            P2 = d.ps[k2 * sz + col]; R2 = d.rho[k2 * sz + col];
+            U1 = d.u[k1 * sz + col]; V1 = d.v[k1 * sz + col]; W1 = d.w[k1 * sz + col];
+            if (hv0) g0 = H.fp[0][k1 * sz + H.off[0]];
+            if (hv1) g1 = H.fp[1][k1 * sz + H.off[1]];
         }
-        sP[threadIdx.x] = Pc;
-        sR[threadIdx.x] = Rc;
+        const int c = k * sz + col;
+        const bool wt = d.bcz == BC_WALL && k == nz - 1;
+        sP[me] = Pc; sR[me] = Rc; sU[me] = U; sV[me] = V;
+        if (hv0) hal[me] = h0;
+        if (hv1) hal[me + NTH] = h1;
         __syncthreads();
-        double Pn, Rn, Ps, Rs;
-        if (n.lyn) { Pn = sP[threadIdx.x + TI]; Rn = sR[threadIdx.x + TI]; }
-        else { Pn = d.ps[c + n.on]; Rn = d.rho[c + n.on]; }
-        if (n.lys) { Ps = sP[threadIdx.x - TI]; Rs = sR[threadIdx.x - TI]; }
-        else { Ps = d.ps[c + n.os]; Rs = d.rho[c + n.os]; }
+        double Pe, Re, Pn, Rn, Pw, Rw, uw, Ps, Rs, vs;
+        if (inE) { Pe = sP[me + 1]; Re = sR[me + 1]; }
+        else { const double *e2 = hal + 5 * TI + t.tj; Pe = e2[0]; Re = e2[TJ]; }
+        if (inN) { Pn = sP[me + TI]; Rn = sR[me + TI]; }
+        else { const double *n2 = hal + t.ti; Pn = n2[0]; Rn = n2[TI]; }
+        if (t.ti > 0) { Pw = sP[me - 1]; Rw = sR[me - 1]; uw = sU[me - 1]; }
+        else { const double *w3 = hal + 5 * TI + 2 * TJ + t.tj; uw = w3[0]; Pw = w3[TJ]; Rw = w3[2 * TJ]; }
+        if (t.tj > 0) { Ps = sP[me - TI]; Rs = sR[me - TI]; vs = sV[me - TI]; }
+        else { const double *s3 = hal + 2 * TI + t.ti; vs = s3[0]; Ps = s3[TI]; Rs = s3[2 * TI]; }
         __syncthreads();
-        const double vs = n.ws ? 0.0 : d.v[c + n.os];
+        const double Fe = n.we ? 0.0 : (1.0 - tr0 * rcp_nr(Rc + Re)) * (Pe - Pc);
+        const double Fw = n.ww ? 0.0 : (1.0 - tr0 * rcp_nr(Rw + Rc)) * (Pc - Pw);
         const double Fn = n.wn ? 0.0 : (1.0 - tr0 * rcp_nr(Rc + Rn)) * (Pn - Pc);
         const double Fs = n.ws ? 0.0 : (1.0 - tr0 * rcp_nr(Rs + Rc)) * (Pc - Ps);
         const double Ft = wt ? 0.0 : (1.0 - rr0 * rcp_nr(Rc * d.rzlo[k] + Rp * d.rzhi[k])) * (Pp - Pc) * d.idzc[k];
-        const double ue = n.we ? 0.0 : u, uwf = n.ww ? 0.0 : uw;
-        const double vn = n.wn ? 0.0 : v;
-        const double wt_ = wt ? 0.0 : w;
+        const double ue = n.we ? 0.0 : U, uwf = n.ww ? 0.0 : uw;
+        const double vn = n.wn ? 0.0 : V, vsf = n.ws ? 0.0 : vs;
+        const double wt_ = wt ? 0.0 : W;
         const double idzf = d.idzf[k];
-        const double f = cdiv * ((ue - uwf) * d.idx + (vn - vs) * d.idy + (wt_ - Wb) * idzf) + (Fe - Fw) * idx2 +
+        const double f = cdiv * ((ue - uwf) * d.idx + (vn - vsf) * d.idy + (wt_ - Wb) * idzf) + (Fe - Fw) * idx2 +
                          (Fn - Fs) * idy2 + (Ft - Fb) * idzf;
         if (t.act) {
             d.f[c] = f;
@@ -144,8 +209,10 @@ __device__ void pass_rhs(const Dom &d, int tile, char *smem)
         }
         Fb = Ft;
         Wb = wt_;
-        Pc = Pp;
-        Rc = Rp;
+        Pc = Pp; Rc = Rp;
+        Pp = P2; Rp = R2;
+        U = U1; V = V1; W = W1;
+        h0 = g0; h1 = g1;
     }
     block_max_to<NTH>(d.stats + ST_FINF, amax, red);
     block_max_to<NTH>(d.stats + ST_SOLVE0, amax, red);
@@ -198,67 +265,151 @@ __device__ void pass_resid(const Dom &d, int tile, char *smem, int solve)
     block_max_to<NTH>(d.stats + ST_SOLVE0 + 4 * solve, amax, red);
 }
 
+// Halo of a marching tile: the cells just outside its TI x TJ extent that
+// its stencil reads, one value per item, 7 (TI + TJ) items:
+//   north row  (je, i0 + x): p, p*, rho          items [0, 3 TI)
+//   south row  (j0 - 1, i0 + x): v*, p, p*, rho  items [3 TI, 7 TI)
+//   east col   (j0 + y, ie): p, p*, rho          items [7 TI, 7 TI + 3 TJ)
+//   west col   (j0 + y, i0 - 1): u*, p, p*, rho  items [7 TI + 3 TJ, 7 (TI + TJ))
+// with je, ie one past the tile's last row/column, wrapped in periodic
+// directions.  Items whose cell is outside a wall, or beyond a partial tile,
+// read a clamped cell and are never used.  Each thread owns at most two
+// items; the host keeps 7 (TI + TJ) <= 2 x threads.
+
+__device__ __forceinline__ Halo corr_halo(const Dom &d, int tile, int nth)
+{
+    const int per = d.cnti * d.cntj;
+    const int rem = tile - (tile / per) * per;
+    const int jt = rem / d.cnti, it = rem - jt * d.cnti;
+    const int TI = d.cti, TJ = d.ctj, nx = d.nx, ny = d.ny;
+    const int i0 = it * TI, j0 = jt * TJ;
+    const int w = min(TI, nx - i0), h = min(TJ, ny - j0);
+    const int ie = (i0 + w == nx) ? 0 : i0 + w, je = (j0 + h == ny) ? 0 : j0 + h;
+    const int iw = (i0 == 0) ? nx - 1 : i0 - 1, js = (j0 == 0) ? ny - 1 : j0 - 1;
+    // p, p*, rho by index (no local array: it would live in scratch)
+    auto psr = [&](int f) { return f == 0 ? d.po : (f == 1 ? d.ps : d.rho); };
+    Halo H;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int q = threadIdx.x + s * nth;
+        int i = 0, j = 0;
+        const double *fp = d.po;
+        if (q < 3 * TI) {
+            const int f = q / TI, x = min(q - f * TI, w - 1);
+            fp = psr(f); i = i0 + x; j = je;
+        } else if (q < 7 * TI) {
+            const int f = (q - 3 * TI) / TI, x = min(q - 3 * TI - f * TI, w - 1);
+            fp = f == 0 ? d.v : psr(f - 1); i = i0 + x; j = js;
+        } else if (q < 7 * TI + 3 * TJ) {
+            const int f = (q - 7 * TI) / TJ, y = min(q - 7 * TI - f * TJ, h - 1);
+            fp = psr(f); i = ie; j = j0 + y;
+        } else {
+            const int qq = min(q - 7 * TI - 3 * TJ, 4 * TJ - 1);
+            const int f = qq / TJ, y = min(qq - f * TJ, h - 1);
+            fp = f == 0 ? d.u : psr(f - 1); i = iw; j = j0 + y;
+        }
+        H.fp[s] = fp;
+        H.off[s] = j * nx + i;
+    }
+    return H;
+}
+
 // Velocity correction of the +faces of each column, marching in k:
 //   u_out = u* - dt [ (1/rho0) G p + (1/rho_face - 1/rho0) G p* ], 0 on walls.
-// With `divcheck`, also max |D u_out|: the -x face from the west lane, the -y
-// face through LDS, the -z face carried from the previous plane (recomputed
-// with the same arithmetic at tile edges).
+// With `divcheck`, also max |D u_out|: the -x and -y faces of a cell are the
+// +faces of its neighbours (through LDS), recomputed from the halo at the
+// tile's west and south edges; the -z face is carried from the plane below.
+// Every global read of plane k+1 (centre values, halo) is issued while
+// plane k is computed, so each workgroup keeps a plane of loads in flight.
+// LDS: 8 reduction slots, p / p* / rho / u_out / v_out of the plane (one per
+// thread), and the halo items.
 template <int NTH = NT>
 __device__ void pass_corr(const Dom &d, int tile, char *smem, bool divcheck)
 {
     double *red = (double *)smem;
-    double *sP = red + 8, *sS = sP + NTH, *sR = sS + NTH, *sF = sR + NTH;
+    double *sP = red + 8, *sS = sP + NTH, *sR = sS + NTH, *sE = sR + NTH, *sF = sE + NTH, *hal = sF + NTH;
     const MTile t = march_tile(d, tile);
     const MNbr n = march_nbr(d, t);
-    const int nx = d.nx, ny = d.ny, nz = d.nz, sz = nx * ny, TI = d.cti;
+    const int nx = d.nx, ny = d.ny, nz = d.nz, sz = nx * ny, TI = d.cti, TJ = d.ctj;
     const int col = t.j * nx + t.i;
     const double dt = d.dt, ir0 = d.irho0;
+    const int nh = 7 * (TI + TJ);
+    const Halo H = corr_halo(d, tile, NTH);
+    const bool hv0 = threadIdx.x < nh, hv1 = threadIdx.x + NTH < nh;
+    // tile extent and where the neighbours of this cell live
+    const int i0 = t.i - t.ti, j0 = t.j - t.tj;
+    const bool inE = t.ti + 1 < min(TI, nx - i0), inN = t.tj + 1 < min(TJ, ny - j0);
+    const int me = threadIdx.x;
+    auto kp = [&](int k) { return k == nz - 1 ? 0 : k + 1; };
     int k = t.kb;
-    double Pc = d.po[k * sz + col], Sc = d.ps[k * sz + col], Rc = d.rho[k * sz + col];
+    // plane k (centre), plane k+1 (centre p, p*, rho), u*, v*, w* and halo of plane k
+    double P0 = d.po[k * sz + col], S0 = d.ps[k * sz + col], R0 = d.rho[k * sz + col];
+    double P1 = d.po[kp(k) * sz + col], S1 = d.ps[kp(k) * sz + col], R1 = d.rho[kp(k) * sz + col];
+    double U = d.u[k * sz + col], V = d.v[k * sz + col], W = d.w[k * sz + col];
+    double h0 = hv0 ? H.fp[0][k * sz + H.off[0]] : 0.0, h1 = hv1 ? H.fp[1][k * sz + H.off[1]] : 0.0;
     double fb = 0.0;
     if (divcheck && !(d.bcz == BC_WALL && k == 0)) fb = corr_face(d, 2, t.i, t.j, (k == 0) ? nz - 1 : k - 1);
     double dmax = 0.0, omax = 0.0;
     for (; k < t.ke; ++k) {
+        // prefetch plane k+1
+        const bool more = k + 1 < t.ke;
+        double P2 = 0.0, S2 = 0.0, R2 = 0.0, U1 = 0.0, V1 = 0.0, W1 = 0.0, g0 = 0.0, g1 = 0.0;
+        if (more) {
+            const int k1 = k + 1, k2 = kp(k1);
+            P2 = d.po[k2 * sz + col]; S2 = d.ps[k2 * sz + col]; R2 = d.rho[k2 * sz + col];
+            U1 = d.u[k1 * sz + col]; V1 = d.v[k1 * sz + col]; W1 = d.w[k1 * sz + col];
+            if (hv0) g0 = H.fp[0][k1 * sz + H.off[0]];
+            if (hv1) g1 = H.fp[1][k1 * sz + H.off[1]];
+        }
         const int c = k * sz + col;
-        const int kp = (k == nz - 1) ? 0 : k + 1;
         const bool wt = d.bcz == BC_WALL && k == nz - 1;
-        const double Pp = d.po[kp * sz + col], Sp = d.ps[kp * sz + col], Rp = d.rho[kp * sz + col];
-        const double u = d.u[c], v = d.v[c], w = d.w[c];
-        double Pe = __shfl_down(Pc, 1, 64), Se = __shfl_down(Sc, 1, 64), Re = __shfl_down(Rc, 1, 64);
-        if (!n.she) { Pe = d.po[c + n.oe]; Se = d.ps[c + n.oe]; Re = d.rho[c + n.oe]; }
-        sP[threadIdx.x] = Pc;
-        sS[threadIdx.x] = Sc;
-        sR[threadIdx.x] = Rc;
+        sP[me] = P0; sS[me] = S0; sR[me] = R0;
+        if (hv0) hal[me] = h0;
+        if (hv1) hal[me + NTH] = h1;
         __syncthreads();
-        double Pn, Sn, Rn;
-        if (n.lyn) { Pn = sP[threadIdx.x + TI]; Sn = sS[threadIdx.x + TI]; Rn = sR[threadIdx.x + TI]; }
-        else { Pn = d.po[c + n.on]; Sn = d.ps[c + n.on]; Rn = d.rho[c + n.on]; }
-        const double fe = n.we ? 0.0 : u - dt * (ir0 * (Pe - Pc) * d.idx + (2.0 * rcp_nr(Rc + Re) - ir0) * (Se - Sc) * d.idx);
-        const double fn = n.wn ? 0.0 : v - dt * (ir0 * (Pn - Pc) * d.idy + (2.0 * rcp_nr(Rc + Rn) - ir0) * (Sn - Sc) * d.idy);
+        double Pe, Se, Re, Pn, Sn, Rn;
+        if (inE) { Pe = sP[me + 1]; Se = sS[me + 1]; Re = sR[me + 1]; }
+        else { const double *e3 = hal + 7 * TI + t.tj; Pe = e3[0]; Se = e3[TJ]; Re = e3[2 * TJ]; }
+        if (inN) { Pn = sP[me + TI]; Sn = sS[me + TI]; Rn = sR[me + TI]; }
+        else { const double *n3 = hal + t.ti; Pn = n3[0]; Sn = n3[TI]; Rn = n3[2 * TI]; }
+        const double fe = n.we ? 0.0 : U - dt * (ir0 * (Pe - P0) * d.idx + (2.0 * rcp_nr(R0 + Re) - ir0) * (Se - S0) * d.idx);
+        const double fn = n.wn ? 0.0 : V - dt * (ir0 * (Pn - P0) * d.idy + (2.0 * rcp_nr(R0 + Rn) - ir0) * (Sn - S0) * d.idy);
         const double hz = d.idzc[k];
-        const double ft = wt ? 0.0 : w - dt * (ir0 * (Pp - Pc) * hz + (rcp_nr(Rc * d.rzlo[k] + Rp * d.rzhi[k]) - ir0) * (Sp - Sc) * hz);
+        const double ft = wt ? 0.0 : W - dt * (ir0 * (P1 - P0) * hz + (rcp_nr(R0 * d.rzlo[k] + R1 * d.rzhi[k]) - ir0) * (S1 - S0) * hz);
         if (t.act) {
             d.uo[c] = fe;
             d.vo[c] = fn;
             d.wo[c] = ft;
             omax = amax_nan(amax_nan(amax_nan(omax, fe), fn), ft);
         }
+        // faces below and west of the tile, from the halo (before the halo is rewritten)
+        double fw = 0.0, fs = 0.0;
         if (divcheck) {
-            sF[threadIdx.x] = fn;
-            double fw = __shfl_up(fe, 1, 64);
-            __syncthreads();
-            double fs;
-            if (!n.shw) fw = n.ww ? 0.0 : corr_face(d, 0, (t.i == 0) ? nx - 1 : t.i - 1, t.j, k);
-            if (n.lys) fs = sF[threadIdx.x - TI];
-            else fs = n.ws ? 0.0 : corr_face(d, 1, t.i, (t.j == 0) ? ny - 1 : t.j - 1, k);
+            if (t.ti == 0 && !n.ww) {
+                const double *w4 = hal + 7 * TI + 3 * TJ + t.tj;
+                const double Uw = w4[0], Pw = w4[TJ], Sw = w4[2 * TJ], Rw = w4[3 * TJ];
+                fw = Uw - dt * (ir0 * (P0 - Pw) * d.idx + (2.0 * rcp_nr(Rw + R0) - ir0) * (S0 - Sw) * d.idx);
+            }
+            if (t.tj == 0 && !n.ws) {
+                const double *s4 = hal + 3 * TI + t.ti;
+                const double Vs = s4[0], Ps = s4[TI], Ss = s4[2 * TI], Rs = s4[3 * TI];
+                fs = Vs - dt * (ir0 * (P0 - Ps) * d.idy + (2.0 * rcp_nr(Rs + R0) - ir0) * (S0 - Ss) * d.idy);
+            }
+            sE[me] = fe;
+            sF[me] = fn;
+        }
+        __syncthreads();
+        if (divcheck) {
+            if (t.ti > 0) fw = sE[me - 1];
+            if (t.tj > 0) fs = sF[me - TI];
             const double dv = (fe - fw) * d.idx + (fn - fs) * d.idy + (ft - fb) * d.idzf[k];
             if (t.act) dmax = amax_nan(dmax, dv);
             fb = ft;
         }
-        __syncthreads();
-        Pc = Pp;
-        Sc = Sp;
-        Rc = Rp;
+        P0 = P1; S0 = S1; R0 = R1;
+        P1 = P2; S1 = S2; R1 = R2;
+        U = U1; V = V1; W = W1;
+        h0 = g0; h1 = g1;
     }
     if (divcheck) block_max_to<NTH>(d.stats + ST_DIV, dmax, red);
     block_max_to<NTH>(d.stats + ST_NONFIN, omax, red);
