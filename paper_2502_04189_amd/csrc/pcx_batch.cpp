@@ -179,7 +179,7 @@ extern "C" pcx_status pcx_batch_create(const pcx_domain *domains, int32_t n, con
         if (st != PCX_OK) { batch_free(B); return st; }
         B->smax = std::max(B->smax, sh.smax);
         B->lds = std::max({B->lds, lds_x(B->doms[i], B->prec), lds_y(B->doms[i], B->prec), lds_z(B->doms[i], B->prec),
-                           (size_t)(8 + 7 * NT) * sizeof(double)});
+                           (size_t)(16 + 7 * NT) * sizeof(double)});
         const size_t nspec = (size_t)B->doms[i].nl * B->grids[i].ny * B->grids[i].nz;
         const size_t ncell = (size_t)B->grids[i].nx * B->grids[i].ny * B->grids[i].nz;
         off_s1[i] = take(nspec * csz);

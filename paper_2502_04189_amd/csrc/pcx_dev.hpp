@@ -68,7 +68,7 @@ struct Dom {
     int ndiv_tiles;                   // divergence-only tiles (NT cells each)
     int cti, ctj, cnti, cntj, ckc, cnk; // marching tile TI x TJ cells, k chunk
     int mth, yth, xth;                // threads of the marching, y and x workgroups
-    FastDiv dnx, dny, dtj, dtk, dnyc, dcti, dM;
+    FastDiv dnx, dny, dtj, dtk, dnyc, dcti, dM, dH1, dM1, dhy; // dH1: M/2+1, dM1: M+1, dhy: ny/2
     double dx, dy, idx, idy, dt, rho0, irho0, lz, scale;
     // z tables (FP64): dzf, 1/dzf, 1/dzc, rho interpolation weights
     const double *dzf, *idzf, *idzc, *rzlo, *rzhi;
@@ -317,6 +317,37 @@ __device__ __forceinline__ void block_max_to(unsigned long long *slot, double v,
     }
 }
 
+// Two block-wide maxima in one pass (one pair of barriers); either slot may
+// be NULL.  Same NaN handling as block_max_to.
+template <int NTH = NT>
+__device__ __forceinline__ void block_max2_to(unsigned long long *sa, double a, unsigned long long *sb, double b,
+                                              double *red)
+{
+    const double qnan = __longlong_as_double(0x7ff8000000000000LL);
+    if (a != a) a = qnan;
+    if (b != b) b = qnan;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        double x = __shfl_xor(a, o, 64), y = __shfl_xor(b, o, 64);
+        a = (x != x || x > a) ? x : a;
+        b = (y != y || y > b) ? y : b;
+    }
+    const int wid = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) { red[wid] = a; red[NTH / 64 + wid] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ma = red[0], mb = red[NTH / 64];
+        for (int i = 1; i < NTH / 64; ++i) {
+            const double x = red[i], y = red[NTH / 64 + i];
+            ma = (x != x || x > ma) ? x : ma;
+            mb = (y != y || y > mb) ? y : mb;
+        }
+        if (sa) atomicMax(sa, (unsigned long long)__double_as_longlong(ma));
+        if (sb) atomicMax(sb, (unsigned long long)__double_as_longlong(mb));
+    }
+}
+
 // Deterministic block-wide sum (fixed shuffle tree, then waves in order);
 // the result is valid in thread 0.
 template <int NTH = NT>
@@ -345,6 +376,11 @@ __device__ __forceinline__ double rcp_nr(double x)
     e = fma(-x, r, 1.0);
     return fma(r, e, r);
 }
+
+// Reciprocal in the solve precision: FP64 as rcp_nr; FP32 correctly rounded
+// (the FP32 solve's accuracy sets how fast the refinement contracts).
+__device__ __forceinline__ float rcp_t(float x) { return 1.0f / x; }
+__device__ __forceinline__ double rcp_t(double x) { return rcp_nr(x); }
 
 // Corrected +x (dir 0), +y (1) or +z (2) face velocity of cell (i,j,k):
 // u* - dt [ (1/rho0) G p + (1/rho_face - 1/rho0) G p* ], 0 on wall faces.

@@ -203,6 +203,9 @@ pcx_status build_domain(const pcx_grid &g, int prec, const Shapes &sh, const Rad
     d.dnx = mkdiv(nx); d.dny = mkdiv(ny); d.dtj = mkdiv(sh.tj); d.dtk = mkdiv(sh.tk); d.dnyc = mkdiv(ny);
     d.dcti = mkdiv(d.cti);
     d.dM = mkdiv(M);
+    d.dH1 = mkdiv(M / 2 + 1);
+    d.dM1 = mkdiv(M + 1);
+    d.dhy = mkdiv(std::max(1, ny / 2));
     d.dx = g.lx / nx; d.dy = g.ly / ny;
     d.idx = 1.0 / d.dx; d.idy = 1.0 / d.dy;
     d.lz = g.zf[nz] - g.zf[0];
@@ -292,7 +295,7 @@ pcx_status build_domain(const pcx_grid &g, int prec, const Shapes &sh, const Rad
 
 size_t lds_x(const Dom &d, int prec)
 {
-    return ((size_t)d.tj * lds_line(d.nl) + tw_half(d.M)) * (prec == PREC_F64 ? 16 : 8) + 64;
+    return ((size_t)d.tj * lds_line(d.nl) + tw_half(d.M)) * (prec == PREC_F64 ? 16 : 8) + 128;
 }
 size_t lds_y(const Dom &d, int prec)
 {

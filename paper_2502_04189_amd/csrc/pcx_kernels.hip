@@ -24,7 +24,7 @@ constexpr int MT = 512;
 
 __global__ __launch_bounds__(MT) void k_rhs(Dom d)
 {
-    __shared__ double sm[8 + 6 * MT];
+    __shared__ double sm[16 + 6 * MT];
     const int t = xcd_tile(d.ncell_tiles);
     if (t >= d.ncell_tiles) return;
     pass_rhs<MT>(d, t, (char *)sm);
@@ -32,7 +32,7 @@ __global__ __launch_bounds__(MT) void k_rhs(Dom d)
 
 __global__ __launch_bounds__(MT) void k_resid(Dom d, int solve)
 {
-    __shared__ double sm[8 + MT];
+    __shared__ double sm[16 + 2 * MT];
     const int t = xcd_tile(d.ncell_tiles);
     if (t >= d.ncell_tiles) return;
     pass_resid<MT>(d, t, (char *)sm, solve);
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(NTH) void k_xinv(Dom d, int solve)
 
 __global__ __launch_bounds__(MT) void k_corr(Dom d, int divcheck)
 {
-    __shared__ double sm[8 + 7 * MT];
+    __shared__ double sm[16 + 7 * MT];
     const int t = xcd_tile(d.ncell_tiles);
     if (t >= d.ncell_tiles) return;
     pass_corr<MT>(d, t, (char *)sm, divcheck != 0);

@@ -132,13 +132,13 @@ __device__ __forceinline__ Halo rhs_halo(const Dom &d, int tile, int nth)
 // Marching in k; the neighbours in x and y come through LDS (the tile's own
 // plane) or from the halo; the z flux and w* below are carried from the
 // previous plane.  Every global read of plane k+1 is issued while plane k
-// is computed.  LDS: 8 reduction slots, p* / rho / u* / v* of the plane and
+// is computed.  LDS: 16 reduction slots, p* / rho / u* / v* of the plane and
 // the halo items.
 template <int NTH = NT>
 __device__ void pass_rhs(const Dom &d, int tile, char *smem)
 {
     double *red = (double *)smem;
-    double *sP = red + 8, *sR = sP + NTH, *sU = sR + NTH, *sV = sU + NTH, *hal = sV + NTH;
+    double *sP = red + 16, *sR = sP + NTH, *sU = sR + NTH, *sV = sU + NTH, *hal = sV + NTH;
     const MTile t = march_tile(d, tile);
     const MNbr n = march_nbr(d, t);
     const int nx = d.nx, ny = d.ny, nz = d.nz, sz = nx * ny, TI = d.cti, TJ = d.ctj;
@@ -148,7 +148,9 @@ __device__ void pass_rhs(const Dom &d, int tile, char *smem)
     const int nh = 5 * (TI + TJ);
     const Halo H = rhs_halo(d, tile, NTH);
     const bool hv0 = threadIdx.x < nh, hv1 = threadIdx.x + NTH < nh;
-    const int i0 = t.i - t.ti, j0 = t.j - t.tj;
+    // tile origin from the tile index (t.i, t.j are clamped for idle threads)
+    const int per = d.cnti * d.cntj, rem = tile - (tile / per) * per;
+    const int i0 = (rem % d.cnti) * TI, j0 = (rem / d.cnti) * TJ;
     const bool inE = t.ti + 1 < min(TI, nx - i0), inN = t.tj + 1 < min(TJ, ny - j0);
     const int me = threadIdx.x;
     auto kp = [&](int k) { return k == nz - 1 ? 0 : k + 1; };
@@ -214,23 +216,48 @@ __device__ void pass_rhs(const Dom &d, int tile, char *smem)
         U = U1; V = V1; W = W1;
         h0 = g0; h1 = g1;
     }
-    block_max_to<NTH>(d.stats + ST_FINF, amax, red);
-    block_max_to<NTH>(d.stats + ST_SOLVE0, amax, red);
+    block_max2_to<NTH>(d.stats + ST_FINF, amax, d.stats + ST_SOLVE0, amax, red);
 }
 
 // r = f - L p (FP64, 7-point operator with variable z spacing) -> d.r.
+// Marching like the RHS: x and y neighbours of p through LDS or from the
+// halo (p on the four sides of the tile, 2 (TI + TJ) items: north row,
+// south row, east column, west column); the z gradient below is carried.
 template <int NTH = NT>
 __device__ void pass_resid(const Dom &d, int tile, char *smem, int solve)
 {
     double *red = (double *)smem;
-    double *sP = red + 8;
+    double *sP = red + 16, *hal = sP + NTH;
     const MTile t = march_tile(d, tile);
     const MNbr n = march_nbr(d, t);
-    const int nx = d.nx, nz = d.nz, sz = nx * d.ny, TI = d.cti;
+    const int nx = d.nx, ny = d.ny, nz = d.nz, sz = nx * ny, TI = d.cti, TJ = d.ctj;
     const int col = t.j * nx + t.i;
     const double idx2 = d.idx * d.idx, idy2 = d.idy * d.idy;
+    // tile origin from the tile index (t.i, t.j are clamped for idle threads)
+    const int per = d.cnti * d.cntj, rem = tile - (tile / per) * per;
+    const int i0 = (rem % d.cnti) * TI, j0 = (rem / d.cnti) * TJ;
+    const int w = min(TI, nx - i0), h = min(TJ, ny - j0);
+    const bool inE = t.ti + 1 < w, inN = t.tj + 1 < h;
+    // halo item of this thread (nh = 2 (TI + TJ) <= NTH)
+    const int nh = 2 * (TI + TJ);
+    const bool hv = threadIdx.x < nh;
+    int hoff;
+    {
+        const int q = min((int)threadIdx.x, nh - 1);
+        const int ie = (i0 + w == nx) ? 0 : i0 + w, je = (j0 + h == ny) ? 0 : j0 + h;
+        const int iw = (i0 == 0) ? nx - 1 : i0 - 1, js = (j0 == 0) ? ny - 1 : j0 - 1;
+        int i, j;
+        if (q < TI) { i = i0 + min(q, w - 1); j = je; }
+        else if (q < 2 * TI) { i = i0 + min(q - TI, w - 1); j = js; }
+        else if (q < 2 * TI + TJ) { i = ie; j = j0 + min(q - 2 * TI, h - 1); }
+        else { i = iw; j = j0 + min(q - 2 * TI - TJ, h - 1); }
+        hoff = j * nx + i;
+    }
+    const int me = threadIdx.x;
+    auto kp = [&](int k) { return k == nz - 1 ? 0 : k + 1; };
     int k = t.kb;
-    double Pc = d.po[k * sz + col];
+    double Pc = d.po[k * sz + col], Pp = d.po[kp(k) * sz + col], F = d.f[k * sz + col];
+    double hc = hv ? d.po[k * sz + hoff] : 0.0;
     double Gb = 0.0;
     if (!(d.bcz == BC_WALL && k == 0)) {
         const int km = (k == 0) ? nz - 1 : k - 1;
@@ -238,29 +265,34 @@ __device__ void pass_resid(const Dom &d, int tile, char *smem, int solve)
     }
     double amax = 0.0;
     for (; k < t.ke; ++k) {
+        const bool more = k + 1 < t.ke;
+        double P2 = 0.0, F1 = 0.0, hn = 0.0;
+        if (more) {
+            const int k1 = k + 1;
+            P2 = d.po[kp(k1) * sz + col];
+            F1 = d.f[k1 * sz + col];
+            if (hv) hn = d.po[k1 * sz + hoff];
+        }
         const int c = k * sz + col;
-        const int kp = (k == nz - 1) ? 0 : k + 1;
         const bool wt = d.bcz == BC_WALL && k == nz - 1;
-        const double Pp = d.po[kp * sz + col];
-        const double fv = d.f[c];
-        double Pe = __shfl_down(Pc, 1, 64), Pw = __shfl_up(Pc, 1, 64);
-        if (!n.she) Pe = d.po[c + n.oe];
-        if (!n.shw) Pw = d.po[c + n.ow];
-        sP[threadIdx.x] = Pc;
+        sP[me] = Pc;
+        if (hv) hal[me] = hc;
         __syncthreads();
-        const double Pn = n.lyn ? sP[threadIdx.x + TI] : d.po[c + n.on];
-        const double Ps = n.lys ? sP[threadIdx.x - TI] : d.po[c + n.os];
+        const double Pe = inE ? sP[me + 1] : hal[2 * TI + t.tj];
+        const double Pn = inN ? sP[me + TI] : hal[t.ti];
+        const double Pw = t.ti > 0 ? sP[me - 1] : hal[2 * TI + TJ + t.tj];
+        const double Ps = t.tj > 0 ? sP[me - TI] : hal[TI + t.ti];
         __syncthreads();
         const double ge = n.we ? 0.0 : Pe - Pc, gw = n.ww ? 0.0 : Pc - Pw;
         const double gn = n.wn ? 0.0 : Pn - Pc, gs = n.ws ? 0.0 : Pc - Ps;
         const double Gt = wt ? 0.0 : (Pp - Pc) * d.idzc[k];
-        const double r = fv - ((ge - gw) * idx2 + (gn - gs) * idy2 + (Gt - Gb) * d.idzf[k]);
+        const double r = F - ((ge - gw) * idx2 + (gn - gs) * idy2 + (Gt - Gb) * d.idzf[k]);
         if (t.act) {
             d.r[c] = r;
             amax = amax_nan(amax, r);
         }
         Gb = Gt;
-        Pc = Pp;
+        Pc = Pp; Pp = P2; F = F1; hc = hn;
     }
     block_max_to<NTH>(d.stats + ST_SOLVE0 + 4 * solve, amax, red);
 }
@@ -321,13 +353,13 @@ __device__ __forceinline__ Halo corr_halo(const Dom &d, int tile, int nth)
 // tile's west and south edges; the -z face is carried from the plane below.
 // Every global read of plane k+1 (centre values, halo) is issued while
 // plane k is computed, so each workgroup keeps a plane of loads in flight.
-// LDS: 8 reduction slots, p / p* / rho / u_out / v_out of the plane (one per
+// LDS: 16 reduction slots, p / p* / rho / u_out / v_out of the plane (one per
 // thread), and the halo items.
 template <int NTH = NT>
 __device__ void pass_corr(const Dom &d, int tile, char *smem, bool divcheck)
 {
     double *red = (double *)smem;
-    double *sP = red + 8, *sS = sP + NTH, *sR = sS + NTH, *sE = sR + NTH, *sF = sE + NTH, *hal = sF + NTH;
+    double *sP = red + 16, *sS = sP + NTH, *sR = sS + NTH, *sE = sR + NTH, *sF = sE + NTH, *hal = sF + NTH;
     const MTile t = march_tile(d, tile);
     const MNbr n = march_nbr(d, t);
     const int nx = d.nx, ny = d.ny, nz = d.nz, sz = nx * ny, TI = d.cti, TJ = d.ctj;
@@ -337,7 +369,9 @@ __device__ void pass_corr(const Dom &d, int tile, char *smem, bool divcheck)
     const Halo H = corr_halo(d, tile, NTH);
     const bool hv0 = threadIdx.x < nh, hv1 = threadIdx.x + NTH < nh;
     // tile extent and where the neighbours of this cell live
-    const int i0 = t.i - t.ti, j0 = t.j - t.tj;
+    // tile origin from the tile index (t.i, t.j are clamped for idle threads)
+    const int per = d.cnti * d.cntj, rem = tile - (tile / per) * per;
+    const int i0 = (rem % d.cnti) * TI, j0 = (rem / d.cnti) * TJ;
     const bool inE = t.ti + 1 < min(TI, nx - i0), inN = t.tj + 1 < min(TJ, ny - j0);
     const int me = threadIdx.x;
     auto kp = [&](int k) { return k == nz - 1 ? 0 : k + 1; };
@@ -411,8 +445,7 @@ __device__ void pass_corr(const Dom &d, int tile, char *smem, bool divcheck)
         U = U1; V = V1; W = W1;
         h0 = g0; h1 = g1;
     }
-    if (divcheck) block_max_to<NTH>(d.stats + ST_DIV, dmax, red);
-    block_max_to<NTH>(d.stats + ST_NONFIN, omax, red);
+    block_max2_to<NTH>(divcheck ? d.stats + ST_DIV : nullptr, dmax, d.stats + ST_NONFIN, omax, red);
 }
 
 // Divergence of the stored output velocity (used when outputs alias inputs);
@@ -506,13 +539,13 @@ __device__ void pass_xfwd(const Dom &d, int tile, char *smem)
         __syncthreads();
         lds_fft<T, false, NTH>(buf, ldr, rows, d.fx, ltw);
         for (int idx = threadIdx.x; idx < rows * (half + 1); idx += NTH) {
-            int r = idx / (half + 1);
+            int r = (int)fdiv((uint32_t)idx, d.dH1);
             split(buf + r * ldr, idx - r * (half + 1));
         }
         __syncthreads();
         if (wx) {
             for (int idx = threadIdx.x; idx < rows * (M + 1); idx += NTH) {
-                int r = idx / (M + 1);
+                int r = (int)fdiv((uint32_t)idx, d.dM1);
                 dct(buf + r * ldr, idx - r * (M + 1));
             }
             __syncthreads();
@@ -583,7 +616,7 @@ __device__ void pass_y(const Dom &d, int tile, char *smem)
             // V_{N-k} = i w_k (X_{N-k} - i X_k), w_k = W_{4N}^k, X_N = 0
             __syncthreads();
             for (int idx = threadIdx.x; idx < cols * hy; idx += NTH) {
-                const int c = idx / hy;
+                const int c = (int)fdiv((uint32_t)idx, d.dhy);
                 const int kk = idx - c * hy + 1;
                 C *col = buf + c * ldc;
                 const int kn = ny - kk;
@@ -607,7 +640,7 @@ __device__ void pass_y(const Dom &d, int tile, char *smem)
             // X_k = (w_k V_k + conj(w_k) V_{N-k}) / 2,
             // X_{N-k} = i (w_k V_k - conj(w_k) V_{N-k}) / 2, X_0 = V_0
             for (int idx = threadIdx.x; idx < cols * hy; idx += NTH) {
-                const int c = idx / hy;
+                const int c = (int)fdiv((uint32_t)idx, d.dhy);
                 const int kk = idx - c * hy + 1;
                 C *col = buf + c * ldc;
                 const int kn = ny - kk;
@@ -736,7 +769,7 @@ __device__ void pass_z(const Dom &d, int tile, char *smem)
                 T A, B, Cc;
                 coef(k0 + s, A, B, Cc);
                 T a = (s == 0) ? T(0) : A;
-                T inv = T(1) / (B - a * cpp);
+                T inv = rcp_t(B - a * cpp);
                 cp[s] = Cc * inv;
                 y[s] = C{(y[s].x - a * yp.x) * inv, (y[s].y - a * yp.y) * inv};
                 g[s] = ((s == 0) ? -A : -a * gp) * inv;
@@ -786,14 +819,15 @@ __device__ void pass_z(const Dom &d, int tile, char *smem)
         T rx_hi = __shfl(rh.x, shi, 64), ry_hi = __shfl(rh.y, shi, 64);
         if (!vlo) { al_lo = T(0); be_lo = T(1); ga_lo = T(0); rx_lo = T(0); ry_lo = T(0); }
         if (!vhi) { al_hi = T(0); be_hi = T(1); ga_hi = T(0); rx_hi = T(0); ry_hi = T(0); }
-        T k1 = al / be_lo, k2 = ga / be_hi;
+        T k1 = al * rcp_t(be_lo), k2 = ga * rcp_t(be_hi);
         T nal = -k1 * al_lo, nga = -k2 * ga_hi;
         T nbe = be - k1 * ga_lo - k2 * al_hi;
         rh = C{rh.x - k1 * rx_lo - k2 * rx_hi, rh.y - k1 * ry_lo - k2 * ry_hi};
         al = nal; be = nbe; ga = nga;
     }
     T den = cyc ? (al + be + ga) : be;
-    C E = {rh.x / den, rh.y / den};
+    const T iden = rcp_t(den);
+    C E = {rh.x * iden, rh.y * iden};
     const int prv = lbase | ((t - 1) & (G - 1));
     C Ep = {__shfl(E.x, prv, 64), __shfl(E.y, prv, 64)};
     // reconstruction x_s = y_s + g_s E_{t-1} + h_s E_t
@@ -920,13 +954,13 @@ __device__ void pass_xinv(const Dom &d, int tile, char *smem, int solve)
     {
         if (wx) {
             for (int idx = threadIdx.x; idx < rows * (M + 1); idx += NTH) {
-                int r = idx / (M + 1);
+                int r = (int)fdiv((uint32_t)idx, d.dM1);
                 dct_pre(buf + r * ldr, idx - r * (M + 1));
             }
             __syncthreads();
         }
         for (int idx = threadIdx.x; idx < rows * (half + 1); idx += NTH) {
-            int r = idx / (half + 1);
+            int r = (int)fdiv((uint32_t)idx, d.dH1);
             c2r_pre(buf + r * ldr, idx - r * (half + 1));
         }
         __syncthreads();
@@ -950,8 +984,7 @@ __device__ void pass_xinv(const Dom &d, int tile, char *smem, int solve)
         double ts = block_sum<NTH>(psum, red);
         if (threadIdx.x == 0) d.ppart[tile] = ts * d.dzf[k];
     }
-    block_max_to<NTH>(d.stats + ST_SOLVE0 + 4 * solve + 1, emax, red);
-    block_max_to<NTH>(d.stats + ST_SOLVE0 + 4 * solve + 2, pmax, red);
+    block_max2_to<NTH>(d.stats + ST_SOLVE0 + 4 * solve + 1, emax, d.stats + ST_SOLVE0 + 4 * solve + 2, pmax, red);
 }
 
 // Volume mean of p from the x-tile partial sums, summed in a fixed order by

@@ -70,6 +70,8 @@ SMALL = [
     ((6, 9, 5), (1, 1, 1), 0.0),
     ((2, 3, 2), (1, 1, 0), 0.0),
     ((24, 27, 7), (0, 1, 1), 1.1),
+    ((96, 162, 5), (1, 1, 0), 0.0),
+    ((96, 18, 9), (0, 0, 1), 1.4),
 ]
 
 
@@ -88,7 +90,9 @@ def test_small_fp64(pcx, orc, dims, bc, stretch):
 
 @pytest.mark.parametrize("dims,bc,stretch", [((32, 32, 32), (0, 0, 1), 0.0), ((48, 36, 20), (0, 0, 1), 1.8),
                                              ((64, 96, 33), (0, 0, 0), 0.0),
-                                             ((64, 48, 40), (1, 1, 1), 1.5)])
+                                             ((64, 48, 40), (1, 1, 1), 1.5),
+                                             # partial stencil tiles in x and y (last tiles of 32 and 2)
+                                             ((64, 18, 12), (0, 0, 1), 1.3), ((96, 162, 5), (1, 1, 0), 0.0)])
 def test_small_refined(pcx, orc, dims, bc, stretch):
     case = W.config0() if dims == (32, 32, 32) else W.random_case(5 + sum(dims), *dims, *bc, stretch=stretch)
     _say(f"case {case.name} fp32_refined")
