@@ -86,6 +86,7 @@ struct Dom {
     unsigned long long *stats;        // NSTAT slots
     double *ppart;                    // per x-tile dzf-weighted sums of p
     double *pmean;                    // [0]: volume mean of p after the last xinv pass
+    double *xpart;                    // per x-tile max |update|, max |p| (NULL: atomics)
 };
 
 // ------------------------------------------------------------ complex math
@@ -317,11 +318,10 @@ __device__ __forceinline__ void block_max_to(unsigned long long *slot, double v,
     }
 }
 
-// Two block-wide maxima in one pass (one pair of barriers); either slot may
-// be NULL.  Same NaN handling as block_max_to.
+// Two block-wide maxima in one pass (one pair of barriers), valid in thread
+// 0.  Same NaN handling as block_max_to.
 template <int NTH = NT>
-__device__ __forceinline__ void block_max2_to(unsigned long long *sa, double a, unsigned long long *sb, double b,
-                                              double *red)
+__device__ __forceinline__ void block_max2(double &a, double &b, double *red)
 {
     const double qnan = __longlong_as_double(0x7ff8000000000000LL);
     if (a != a) a = qnan;
@@ -343,8 +343,20 @@ __device__ __forceinline__ void block_max2_to(unsigned long long *sa, double a, 
             ma = (x != x || x > ma) ? x : ma;
             mb = (y != y || y > mb) ? y : mb;
         }
-        if (sa) atomicMax(sa, (unsigned long long)__double_as_longlong(ma));
-        if (sb) atomicMax(sb, (unsigned long long)__double_as_longlong(mb));
+        a = ma;
+        b = mb;
+    }
+}
+
+// block_max2, then one atomicMax per slot (either slot may be NULL).
+template <int NTH = NT>
+__device__ __forceinline__ void block_max2_to(unsigned long long *sa, double a, unsigned long long *sb, double b,
+                                              double *red)
+{
+    block_max2<NTH>(a, b, red);
+    if (threadIdx.x == 0) {
+        if (sa) atomicMax(sa, (unsigned long long)__double_as_longlong(a));
+        if (sb) atomicMax(sb, (unsigned long long)__double_as_longlong(b));
     }
 }
 

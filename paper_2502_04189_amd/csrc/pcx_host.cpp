@@ -324,6 +324,7 @@ static pcx_status plan_free(pcx_plan P)
     if (P->stats) (void)hipFree(P->stats);
     if (P->psum) (void)hipFree(P->psum);
     if (P->ppart) (void)hipFree(P->ppart);
+    if (P->xpart) (void)hipFree(P->xpart);
     for (auto e : P->ev) (void)hipEventDestroy(e);
     delete P;
     return PCX_OK;
@@ -375,7 +376,8 @@ extern "C" pcx_status pcx_plan_create(const pcx_grid *grid, const pcx_options *o
     const size_t ncell = (size_t)grid->nx * grid->ny * grid->nz;
     if (hipMalloc(&P->s1, nspec * csz) != hipSuccess || hipMalloc(&P->s2, nspec * csz) != hipSuccess ||
         hipMalloc(&P->stats, NSTAT * sizeof(unsigned long long)) != hipSuccess ||
-        hipMalloc(&P->psum, (size_t)grid->nz * sizeof(double)) != hipSuccess) {
+        hipMalloc(&P->psum, (size_t)grid->nz * sizeof(double)) != hipSuccess ||
+        hipMalloc(&P->xpart, (size_t)2 * P->dom.ntj * grid->nz * sizeof(double)) != hipSuccess) {
         plan_free(P);
         return fail(PCX_ERR_NOMEM, "workspace allocation failed");
     }
@@ -387,13 +389,14 @@ extern "C" pcx_status pcx_plan_create(const pcx_grid *grid, const pcx_options *o
         return fail(PCX_ERR_NOMEM, "workspace allocation failed (f, r)");
     }
     P->ws_bytes = 2 * nspec * csz + NSTAT * 8 + grid->nz * 8 + P->tables.bytes + ncell * 8 + (P->r ? ncell * 8 : 0) +
-                  (P->ppart ? ((size_t)P->dom.ntj * grid->nz + 8) * 8 : 0);
+                  (P->ppart ? ((size_t)P->dom.ntj * grid->nz + 8) * 8 : 0) + (size_t)2 * P->dom.ntj * grid->nz * 8;
     P->dom.s1 = P->s1;
     P->dom.s2 = P->s2;
     P->dom.f = P->f;
     P->dom.r = P->r;
     P->dom.stats = P->stats;
     P->dom.ppart = P->ppart;
+    P->dom.xpart = P->xpart;
     P->dom.pmean = P->ppart ? P->ppart + (size_t)P->dom.ntj * grid->nz : nullptr;
     P->lx = lds_x(P->dom, P->prec);
     P->ly = lds_y(P->dom, P->prec);
@@ -486,6 +489,8 @@ static pcx_status solve_tail(pcx_plan P, const Dom &d, int solve, int mode, hipS
     tmark(P, s, "y_fft_inv");
     HIPCHK(launch_xinv(d, P->prec, mode, solve, P->lx, s));
     tmark(P, s, mode == XOUT_STORE ? "x_fft_inv_store_p" : "x_fft_inv_accum_p");
+    HIPCHK(launch_xmax(d, solve, s));
+    tmark(P, s, "x_max");
     if (d.ppart) {
         HIPCHK(launch_pmean(d, s));
         tmark(P, s, "p_mean");

@@ -2,6 +2,8 @@
 // One kernel per pass for a single domain (the descriptor travels by value
 // in the kernel arguments), small reduction helpers, and the persistent
 // multi-domain kernel of the batched form.
+#include <algorithm>
+
 #include "pcx_launch.hpp"
 #include "pcx_passes.hpp"
 
@@ -78,6 +80,12 @@ __global__ __launch_bounds__(NT) void k_div(Dom d)
 {
     __shared__ double red[NT / 64];
     pass_div(d, blockIdx.x, (char *)red);
+}
+
+__global__ __launch_bounds__(NT) void k_xmax(Dom d, int solve)
+{
+    __shared__ double red[2 * NT / 64];
+    pass_xmax(d, solve, blockIdx.x, gridDim.x, (char *)red);
 }
 
 __global__ __launch_bounds__(NT) void k_pmean(Dom d)
@@ -240,6 +248,12 @@ hipError_t launch_xinv(const Dom &d, int prec, int mode, int solve, size_t lds, 
 hipError_t launch_corr(const Dom &d, bool divcheck, hipStream_t s)
 {
     PCX_LAUNCH_B(k_corr, xcd_grid(d.ncell_tiles), MT, 0, s, d, divcheck ? 1 : 0);
+}
+
+hipError_t launch_xmax(const Dom &d, int solve, hipStream_t s)
+{
+    const int nt = d.ntj * d.nz;
+    PCX_LAUNCH(k_xmax, std::max(1, std::min(64, (nt + 4 * NT - 1) / (4 * NT))), 0, s, d, solve);
 }
 
 hipError_t launch_pmean(const Dom &d, hipStream_t s)

@@ -15,6 +15,7 @@ hipError_t launch_xinv(const Dom &d, int prec, int mode, int solve, size_t lds, 
 hipError_t launch_corr(const Dom &d, bool divcheck, hipStream_t s);
 hipError_t launch_div(const Dom &d, hipStream_t s);
 hipError_t launch_pmean(const Dom &d, hipStream_t s);
+hipError_t launch_xmax(const Dom &d, int solve, hipStream_t s);
 hipError_t launch_plane_sums(const double *p, int nxy, int nz, double *out, hipStream_t s);
 hipError_t launch_min(const double *a, long long n, unsigned long long *key, hipStream_t s);
 

@@ -984,7 +984,41 @@ __device__ void pass_xinv(const Dom &d, int tile, char *smem, int solve)
         double ts = block_sum<NTH>(psum, red);
         if (threadIdx.x == 0) d.ppart[tile] = ts * d.dzf[k];
     }
-    block_max2_to<NTH>(d.stats + ST_SOLVE0 + 4 * solve + 1, emax, d.stats + ST_SOLVE0 + 4 * solve + 2, pmax, red);
+    if (d.xpart) {
+        // per-tile maxima, reduced by pass_xmax: one atomic per slot per
+        // launch instead of one per tile
+        block_max2<NTH>(emax, pmax, red);
+        if (threadIdx.x == 0) {
+            d.xpart[2 * tile] = emax;
+            d.xpart[2 * tile + 1] = pmax;
+        }
+    } else {
+        block_max2_to<NTH>(d.stats + ST_SOLVE0 + 4 * solve + 1, emax, d.stats + ST_SOLVE0 + 4 * solve + 2, pmax, red);
+    }
+}
+
+// Maxima of the x-inverse tiles' partials into the solve's statistics slots
+// (workgroup `wg` of `nwg` takes every nwg-th block of NT partials).
+__device__ __forceinline__ void pass_xmax(const Dom &d, int solve, int wg, int nwg, char *smem)
+{
+    double *red = (double *)smem;
+    const int nt = d.ntj * d.nz;
+    double a = 0.0, b = 0.0;
+    const double2 *xp = (const double2 *)d.xpart;
+    for (int q0 = wg * NT; q0 < nt; q0 += 8 * nwg * NT) {
+        double2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = q0 + u * nwg * NT + threadIdx.x;
+            v[u] = q < nt ? xp[q] : double2{0.0, 0.0};
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            a = (v[u].x != v[u].x || v[u].x > a) ? v[u].x : a;
+            b = (v[u].y != v[u].y || v[u].y > b) ? v[u].y : b;
+        }
+    }
+    block_max2_to<NT>(d.stats + ST_SOLVE0 + 4 * solve + 1, a, d.stats + ST_SOLVE0 + 4 * solve + 2, b, red);
 }
 
 // Volume mean of p from the x-tile partial sums, summed in a fixed order by
@@ -994,7 +1028,17 @@ __device__ __forceinline__ void pass_pmean(const Dom &d, char *smem)
     double *red = (double *)smem;
     const int nt = d.ntj * d.nz;
     double s = 0.0;
-    for (int t = threadIdx.x; t < nt; t += NT) s += d.ppart[t];
+    // eight loads in flight per thread; the additions keep one fixed order
+    for (int t0 = 0; t0 < nt; t0 += 8 * NT) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = t0 + u * NT + threadIdx.x;
+            v[u] = t < nt ? d.ppart[t] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
     double tot = block_sum(s, red);
     if (threadIdx.x == 0) d.pmean[0] = tot / ((double)d.nx * (double)d.ny * d.lz);
 }

@@ -57,6 +57,7 @@ struct pcx_plan_s {
     double *r = nullptr;
     double *psum = nullptr;
     double *ppart = nullptr;
+    double *xpart = nullptr;
     unsigned long long *stats = nullptr;
     size_t ws_bytes = 0;
     size_t lx = 0, ly = 0, lzs = 0;
