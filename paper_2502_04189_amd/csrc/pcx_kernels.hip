@@ -337,7 +337,10 @@ __global__ __launch_bounds__(NT) void k_persist(PersistArgs a)
         }
         __syncthreads();
         __threadfence();
-        const Dom &d = a.doms[dom];
+        // the descriptor table is read-only for the kernel's lifetime: read it
+        // through the constant address space, so its fields are scalar loads
+        // that need no registers held across the pass
+        const Dom &d = *(const Dom *)((const __attribute__((address_space(4))) Dom *)a.doms + dom);
         const int sv = a.tab.solve[ph];
         const int kind = a.tab.kind[ph];
         for (int tile = tile0; tile < tile0 + count; ++tile) {
