@@ -143,11 +143,12 @@ extern "C" pcx_status pcx_batch_create(const pcx_domain *domains, int32_t n, con
     PhaseTab &tab = B->tab;
     std::memset(&tab, 0, sizeof(tab));
     auto addph = [&](int kind, int solve) { tab.kind[tab.nphase] = (uint8_t)kind; tab.solve[tab.nphase] = (uint8_t)solve; tab.nphase++; };
-    const bool refined = B->prec == PREC_F32;
     addph(PK_RHS, 0);
     addph(PK_XFWD_RHS, 0);
     addph(PK_YF, 0); addph(PK_Z, 0); addph(PK_YI, 0); addph(PK_XINV_STORE, 0);
-    if (refined) addph(PK_PMEAN, 0);
+    // after every x-inverse phase: the maxima of its tiles (and, refined, the
+    // volume mean of p), one workgroup per domain
+    addph(PK_PMEAN, 0);
     for (int s = 1; s < B->solves; ++s) {
         addph(PK_RESID, s);
         addph(PK_XFWD_RESID, s);
@@ -158,7 +159,7 @@ extern "C" pcx_status pcx_batch_create(const pcx_domain *domains, int32_t n, con
 
     // per-domain tables, shapes and workspace layout
     const size_t csz = B->prec == PREC_F64 ? 16 : 8;
-    std::vector<size_t> off_s1(n), off_s2(n), off_f(n), off_r(n), off_pp(n);
+    std::vector<size_t> off_s1(n), off_s2(n), off_f(n), off_r(n), off_pp(n), off_xp(n);
     size_t total = 0;
     auto take = [&](size_t bytes) { size_t o2 = (total + 255) & ~(size_t)255; total = o2 + bytes; return o2; };
     for (int i = 0; i < n; ++i) {
@@ -187,6 +188,7 @@ extern "C" pcx_status pcx_batch_create(const pcx_domain *domains, int32_t n, con
         off_f[i] = take(ncell * 8);
         off_r[i] = B->prec == PREC_F32 ? take(ncell * 8) : 0;
         off_pp[i] = B->prec == PREC_F32 ? take(((size_t)B->doms[i].ntj * B->grids[i].nz + 8) * 8) : 0;
+        off_xp[i] = take((size_t)2 * B->doms[i].ntj * B->grids[i].nz * 8);
     }
     if (o.tune_cache && o.autotune) cache.save(o.tune_cache);
     if (hipMalloc(&B->ws, std::max<size_t>(total, 256)) != hipSuccess) { batch_free(B); return fail(PCX_ERR_NOMEM, "batch workspace allocation failed"); }
@@ -204,6 +206,7 @@ extern "C" pcx_status pcx_batch_create(const pcx_domain *domains, int32_t n, con
         d.r = B->prec == PREC_F32 ? (double *)((char *)B->ws + off_r[i]) : nullptr;
         d.ppart = B->prec == PREC_F32 ? (double *)((char *)B->ws + off_pp[i]) : nullptr;
         d.pmean = d.ppart ? d.ppart + (size_t)d.ntj * B->grids[i].nz : nullptr;
+        d.xpart = (double *)((char *)B->ws + off_xp[i]);
         d.stats = B->stats + (size_t)i * NSTAT;
         d.dt = dm.dt; d.rho0 = dm.rho0; d.irho0 = 1.0 / dm.rho0;
         d.rho = dm.rho; d.ps = dm.p_star; d.u = dm.u; d.v = dm.v; d.w = dm.w;

@@ -354,7 +354,11 @@ __global__ __launch_bounds__(NT) void k_persist(PersistArgs a)
             case PK_YI: pass_y<T, true>(d, tile, smem); break;
             case PK_XINV_STORE: pass_xinv<T, XOUT_STORE>(d, tile, smem, sv); break;
             case PK_XINV_ACCUM: pass_xinv<T, XOUT_ACCUM>(d, tile, smem, sv); break;
-            case PK_PMEAN: pass_pmean(d, smem); break;
+            case PK_PMEAN:
+                pass_xmax(d, sv, 0, 1, smem);
+                __syncthreads();
+                if (d.ppart) pass_pmean(d, smem);
+                break;
             default: pass_corr(d, tile, smem, true); break;
             }
             __syncthreads(); // the next tile rewrites LDS the last one read

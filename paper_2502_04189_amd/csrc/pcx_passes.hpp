@@ -135,7 +135,7 @@ __device__ __forceinline__ Halo rhs_halo(const Dom &d, int tile, int nth)
 // is computed.  LDS: 16 reduction slots, p* / rho / u* / v* of the plane and
 // the halo items.
 template <int NTH = NT>
-__device__ void pass_rhs(const Dom &d, int tile, char *smem)
+__device__ __forceinline__ void pass_rhs(const Dom &d, int tile, char *smem)
 {
     double *red = (double *)smem;
     double *sP = red + 16, *sR = sP + NTH, *sU = sR + NTH, *sV = sU + NTH, *hal = sV + NTH;
@@ -224,7 +224,7 @@ __device__ void pass_rhs(const Dom &d, int tile, char *smem)
 // halo (p on the four sides of the tile, 2 (TI + TJ) items: north row,
 // south row, east column, west column); the z gradient below is carried.
 template <int NTH = NT>
-__device__ void pass_resid(const Dom &d, int tile, char *smem, int solve)
+__device__ __forceinline__ void pass_resid(const Dom &d, int tile, char *smem, int solve)
 {
     double *red = (double *)smem;
     double *sP = red + 16, *hal = sP + NTH;
@@ -356,7 +356,7 @@ __device__ __forceinline__ Halo corr_halo(const Dom &d, int tile, int nth)
 // LDS: 16 reduction slots, p / p* / rho / u_out / v_out of the plane (one per
 // thread), and the halo items.
 template <int NTH = NT>
-__device__ void pass_corr(const Dom &d, int tile, char *smem, bool divcheck)
+__device__ __forceinline__ void pass_corr(const Dom &d, int tile, char *smem, bool divcheck)
 {
     double *red = (double *)smem;
     double *sP = red + 16, *sS = sP + NTH, *sR = sS + NTH, *sE = sR + NTH, *sF = sE + NTH, *hal = sF + NTH;
@@ -476,7 +476,7 @@ __device__ __forceinline__ void pass_div(const Dom &d, int tile, char *smem)
 // FFT by a half-length complex FFT of z[n] = s[2n] + i s[2n+1] and the split
 // X[l] = E + W^l O, X[M-l] = conj(E - W^l O); then the corner turn into S1.
 template <typename T, int SRC, int NTH = NT>
-__device__ void pass_xfwd(const Dom &d, int tile, char *smem)
+__device__ __forceinline__ void pass_xfwd(const Dom &d, int tile, char *smem)
 {
     using C = c2<T>;
     C *buf = (C *)smem;
@@ -571,7 +571,7 @@ __device__ void pass_xfwd(const Dom &d, int tile, char *smem)
 // (DCT-II for a wall) -> corner turn into the z-lines of S2; inverse the
 // reverse.
 template <typename T, bool INV, int NTH = NT>
-__device__ void pass_y(const Dom &d, int tile, char *smem)
+__device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
 {
     using C = c2<T>;
     C *buf = (C *)smem;
@@ -688,7 +688,7 @@ __device__ void pass_y(const Dom &d, int tile, char *smem)
 // mean.  The right-hand side is scaled by 1/(nx ny) (inverse transforms are
 // unnormalised).
 template <typename T, int SMAX>
-__device__ void pass_z(const Dom &d, int tile, char *smem)
+__device__ __forceinline__ void pass_z(const Dom &d, int tile, char *smem)
 {
     using C = c2<T>;
     C *buf = (C *)smem;
@@ -871,7 +871,7 @@ __device__ void pass_z(const Dom &d, int tile, char *smem)
 // Tile = (j tile, k).  Inverse real FFT of rows j0.. of plane k from S1;
 // MODE store: p = value; accum: p += value (refinement update).
 template <typename T, int MODE, int NTH = NT>
-__device__ void pass_xinv(const Dom &d, int tile, char *smem, int solve)
+__device__ __forceinline__ void pass_xinv(const Dom &d, int tile, char *smem, int solve)
 {
     using C = c2<T>;
     C *buf = (C *)smem;
