@@ -200,12 +200,28 @@ def run_batch(steps, warmup, ndom):
     e1.record(st)
     torch.cuda.synchronize()
     sms = e0.elapsed_time(e1) / steps
-    log(f"batch: {bms:.3f} ms per launch ({cells} cells), sequential fp64 {sms:.3f} ms, create {t_create:.1f} s")
+    # the same domains batched in FP64 (one solve each): the batching gain at
+    # equal arithmetic
+    b64 = pcx.Batch(doms, "fp64", tune_cache=cache)
+    for _ in range(warmup):
+        b64.launch()
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(steps):
+        b64.launch()
+    e1.record(st)
+    torch.cuda.synchronize()
+    b64ms = e0.elapsed_time(e1) / steps
+    _, st64 = b64.reports()
+    log(f"batch: {bms:.3f} ms per launch ({cells} cells), fp64 batch {b64ms:.3f} ms, sequential fp64 {sms:.3f} ms, "
+        f"create {t_create:.1f} s")
     return {"domains": len(doms), "cells": cells, "ms_per_launch": round(bms, 4),
             "value": round(cells / (bms * 1e-3) / 1e6, 1), "unit": "Mpts/s",
             "solves_per_domain": reps[0]["solves"], "worst_rel_residual": worst,
             "domains_converged": nconv, "status": status,
             "sequential_fp64_ms": round(sms, 4), "speedup_vs_sequential_fp64": round(sms / bms, 3),
+            "fp64_batch_ms": round(b64ms, 4), "fp64_batch_status": st64,
+            "fp64_batch_speedup_vs_sequential_fp64": round(sms / b64ms, 3),
             "create_s_incl_autotune": round(t_create, 2)}
 
 

@@ -81,7 +81,7 @@ static long tiles_of(const Dom &d, int kind)
     switch (kind) {
     case PK_RHS:
     case PK_RESID:
-    case PK_CORR: return d.ncell_tiles;
+    case PK_CORR: return d.mg[1].ntiles;
     case PK_XFWD_RHS:
     case PK_XFWD_RESID:
     case PK_XINV_STORE:
@@ -90,7 +90,7 @@ static long tiles_of(const Dom &d, int kind)
     case PK_YI: return (long)d.ntk * d.nl;
     case PK_Z: return d.nzt;
     case PK_PMEAN: return 1;
-    default: return d.ncell_tiles;
+    default: return d.mg[0].ntiles;
     }
 }
 

@@ -57,6 +57,13 @@ struct FftDesc {
     const void *tw;        // n roots exp(-2 pi i e / n), T2
 };
 
+// Tiling of a marching stencil launch: TI x TJ cells of a plane (one thread
+// per column) over chunks of ckc planes; ntiles = cnti cntj cnk.
+struct MGeo {
+    int cti, ctj, cnti, cntj, ckc, cnk, ntiles;
+    FastDiv dcti;
+};
+
 // Everything one domain needs on the device.
 struct Dom {
     int nx, ny, nz, nl, M;            // M = nx/2 (half-length complex FFT)
@@ -64,11 +71,10 @@ struct Dom {
     int tj, ntj;                      // x-pass rows per tile, j tiles
     int tk, ntk;                      // y-pass columns per tile, k tiles
     int zg, zlpw, nzt;                // z lanes per line, lines per WG, z tiles
-    int ncell_tiles;                  // correction tiles (see pass_corr)
+    MGeo mg[2];                       // marching tiles: [0] RHS and residual, [1] correction
     int ndiv_tiles;                   // divergence-only tiles (NT cells each)
-    int cti, ctj, cnti, cntj, ckc, cnk; // marching tile TI x TJ cells, k chunk
     int mth, yth, xth;                // threads of the marching, y and x workgroups
-    FastDiv dnx, dny, dtj, dtk, dnyc, dcti, dM, dH1, dM1, dhy; // dH1: M/2+1, dM1: M+1, dhy: ny/2
+    FastDiv dnx, dny, dtj, dtk, dnyc, dM, dH1, dM1, dhy; // dH1: M/2+1, dM1: M+1, dhy: ny/2
     double dx, dy, idx, idy, dt, rho0, irho0, lz, scale;
     // z tables (FP64): dzf, 1/dzf, 1/dzc, rho interpolation weights
     const double *dzf, *idzf, *idzc, *rzlo, *rzhi;

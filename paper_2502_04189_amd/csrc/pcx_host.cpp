@@ -160,6 +160,7 @@ void choose_shapes(const pcx_grid &g, int prec, const TuneParams *tp, Shapes &sh
     int smax_need = (g.nz + G - 1) / G;
     sh.smax = smax_need <= 4 ? 4 : (smax_need <= 8 ? 8 : 16);
     sh.mth = batch ? NT : 512;
+    sh.mthc = batch ? NT : 1024;
     // wider y workgroups when a tile holds many columns: more waves per CU
     sh.yth = (!batch && (long)sh.tk * (lds_line(g.ny) * (long)csz) > 48 * 1024) ? 512 : NT;
     sh.xth = batch ? NT : 512;
@@ -183,25 +184,31 @@ pcx_status build_domain(const pcx_grid &g, int prec, const Shapes &sh, const Rad
     d.ndiv_tiles = (int)(((long)nx * ny * nz + NT - 1) / NT);
     // marching stencils: TI x TJ cell tiles over chunks of ckc planes
     d.mth = sh.mth;
+    // marching tiles: [0] RHS and residual with sh.mth threads, [1] the
+    // correction with sh.mthc threads; each halo (7 (TI + TJ) items at most)
+    // fits two items per thread
+    for (int q = 0; q < 2; ++q) {
+        MGeo &m = d.mg[q];
+        const int th = q == 0 ? sh.mth : sh.mthc;
+        m.cti = std::min(nx, 64);
+        m.ctj = std::max(1, std::min({ny, th / m.cti, 2 * th / 7 - m.cti}));
+        m.cnti = (nx + m.cti - 1) / m.cti;
+        m.cntj = (ny + m.ctj - 1) / m.ctj;
+        if (sh.batch) {
+            m.ckc = nz; // whole columns: batch items stay large
+        } else {
+            long txy = (long)m.cnti * m.cntj;
+            long target = 2048L * 512 / th;
+            long chunks = std::max(1L, std::min((long)std::max(1, nz / 16), (target + txy - 1) / txy));
+            m.ckc = (int)((nz + chunks - 1) / chunks);
+        }
+        m.cnk = (nz + m.ckc - 1) / m.ckc;
+        m.ntiles = m.cnti * m.cntj * m.cnk;
+        m.dcti = mkdiv(m.cti);
+    }
     d.yth = sh.yth;
     d.xth = sh.xth;
-    d.cti = std::min(nx, 64);
-    // the tile's halo (7 (TI + TJ) items, see pass_corr) fits two items per thread
-    d.ctj = std::max(1, std::min({ny, sh.mth / d.cti, 2 * sh.mth / 7 - d.cti}));
-    d.cnti = (nx + d.cti - 1) / d.cti;
-    d.cntj = (ny + d.ctj - 1) / d.ctj;
-    if (sh.batch) {
-        d.ckc = nz; // whole columns: batch items stay large
-    } else {
-        long txy = (long)d.cnti * d.cntj;
-        long target = 2048L * 512 / sh.mth;
-        long chunks = std::max(1L, std::min((long)std::max(1, nz / 16), (target + txy - 1) / txy));
-        d.ckc = (int)((nz + chunks - 1) / chunks);
-    }
-    d.cnk = (nz + d.ckc - 1) / d.ckc;
-    d.ncell_tiles = d.cnti * d.cntj * d.cnk;
     d.dnx = mkdiv(nx); d.dny = mkdiv(ny); d.dtj = mkdiv(sh.tj); d.dtk = mkdiv(sh.tk); d.dnyc = mkdiv(ny);
-    d.dcti = mkdiv(d.cti);
     d.dM = mkdiv(M);
     d.dH1 = mkdiv(M / 2 + 1);
     d.dM1 = mkdiv(M + 1);

@@ -21,22 +21,24 @@ __device__ __forceinline__ int xcd_tile(int ntiles)
 }
 
 // Marching stencil launches of a single domain use 512-thread workgroups
-// (64 x 8 cells per plane) so that fewer threads sit on a tile edge.
+// (64 x 8 cells per plane) for the RHS and the residual, and 1024 threads
+// (64 x 16) for the correction, whose halo (seven fields) is the largest.
 constexpr int MT = 512;
+constexpr int MTC = 1024;
 
 __global__ __launch_bounds__(MT) void k_rhs(Dom d)
 {
     __shared__ double sm[16 + 6 * MT];
-    const int t = xcd_tile(d.ncell_tiles);
-    if (t >= d.ncell_tiles) return;
+    const int t = xcd_tile(d.mg[0].ntiles);
+    if (t >= d.mg[0].ntiles) return;
     pass_rhs<MT>(d, t, (char *)sm);
 }
 
 __global__ __launch_bounds__(MT) void k_resid(Dom d, int solve)
 {
     __shared__ double sm[16 + 2 * MT];
-    const int t = xcd_tile(d.ncell_tiles);
-    if (t >= d.ncell_tiles) return;
+    const int t = xcd_tile(d.mg[0].ntiles);
+    if (t >= d.mg[0].ntiles) return;
     pass_resid<MT>(d, t, (char *)sm, solve);
 }
 
@@ -68,12 +70,12 @@ __global__ __launch_bounds__(NTH) void k_xinv(Dom d, int solve)
     pass_xinv<T, MODE, NTH>(d, blockIdx.x, smem, solve);
 }
 
-__global__ __launch_bounds__(MT) void k_corr(Dom d, int divcheck)
+__global__ __launch_bounds__(MTC) void k_corr(Dom d, int divcheck)
 {
-    __shared__ double sm[16 + 7 * MT];
-    const int t = xcd_tile(d.ncell_tiles);
-    if (t >= d.ncell_tiles) return;
-    pass_corr<MT>(d, t, (char *)sm, divcheck != 0);
+    __shared__ double sm[16 + 7 * MTC];
+    const int t = xcd_tile(d.mg[1].ntiles);
+    if (t >= d.mg[1].ntiles) return;
+    pass_corr<MTC>(d, t, (char *)sm, divcheck != 0);
 }
 
 __global__ __launch_bounds__(NT) void k_div(Dom d)
@@ -172,12 +174,12 @@ static int xcd_grid(int ntiles) { return ((ntiles + 7) >> 3) << 3; }
 
 hipError_t launch_rhs(const Dom &d, hipStream_t s)
 {
-    PCX_LAUNCH_B(k_rhs, xcd_grid(d.ncell_tiles), MT, 0, s, d);
+    PCX_LAUNCH_B(k_rhs, xcd_grid(d.mg[0].ntiles), MT, 0, s, d);
 }
 
 hipError_t launch_resid(const Dom &d, int solve, hipStream_t s)
 {
-    PCX_LAUNCH_B(k_resid, xcd_grid(d.ncell_tiles), MT, 0, s, d, solve);
+    PCX_LAUNCH_B(k_resid, xcd_grid(d.mg[0].ntiles), MT, 0, s, d, solve);
 }
 
 template <int NTH> static hipError_t launch_xfwd_t(const Dom &d, int prec, int src, size_t lds, hipStream_t s)
@@ -247,7 +249,7 @@ hipError_t launch_xinv(const Dom &d, int prec, int mode, int solve, size_t lds, 
 
 hipError_t launch_corr(const Dom &d, bool divcheck, hipStream_t s)
 {
-    PCX_LAUNCH_B(k_corr, xcd_grid(d.ncell_tiles), MT, 0, s, d, divcheck ? 1 : 0);
+    PCX_LAUNCH_B(k_corr, xcd_grid(d.mg[1].ntiles), MTC, 0, s, d, divcheck ? 1 : 0);
 }
 
 hipError_t launch_xmax(const Dom &d, int solve, hipStream_t s)

@@ -29,21 +29,21 @@ struct MTile {
     bool act;
 };
 
-__device__ __forceinline__ MTile march_tile(const Dom &d, int tile)
+__device__ __forceinline__ MTile march_tile(const Dom &d, const MGeo &g, int tile)
 {
     MTile t;
-    const int per = d.cnti * d.cntj;
+    const int per = g.cnti * g.cntj;
     const int kc = tile / per;
     const int rem = tile - kc * per;
-    const int jt = rem / d.cnti, it = rem - jt * d.cnti;
-    t.tj = (int)fdiv(threadIdx.x, d.dcti);
-    t.ti = threadIdx.x - t.tj * d.cti;
-    const int i = it * d.cti + t.ti, j = jt * d.ctj + t.tj;
-    t.act = t.tj < d.ctj && i < d.nx && j < d.ny;
+    const int jt = rem / g.cnti, it = rem - jt * g.cnti;
+    t.tj = (int)fdiv(threadIdx.x, g.dcti);
+    t.ti = threadIdx.x - t.tj * g.cti;
+    const int i = it * g.cti + t.ti, j = jt * g.ctj + t.tj;
+    t.act = t.tj < g.ctj && i < d.nx && j < d.ny;
     t.i = min(i, d.nx - 1); // clamped so that idle threads load valid cells
     t.j = min(j, d.ny - 1);
-    t.kb = kc * d.ckc;
-    t.ke = min(d.nz, t.kb + d.ckc);
+    t.kb = kc * g.ckc;
+    t.ke = min(d.nz, t.kb + g.ckc);
     t.lane = threadIdx.x & 63;
     return t;
 }
@@ -55,7 +55,7 @@ struct MNbr {
     bool lyn, lys;        // y neighbour held in LDS by the tile
 };
 
-__device__ __forceinline__ MNbr march_nbr(const Dom &d, const MTile &t)
+__device__ __forceinline__ MNbr march_nbr(const Dom &d, const MGeo &g, const MTile &t)
 {
     MNbr n;
     const int nx = d.nx, ny = d.ny, i = t.i, j = t.j;
@@ -67,9 +67,9 @@ __device__ __forceinline__ MNbr march_nbr(const Dom &d, const MTile &t)
     n.ww = d.bcx == BC_WALL && i == 0;
     n.wn = d.bcy == BC_WALL && j == ny - 1;
     n.ws = d.bcy == BC_WALL && j == 0;
-    n.she = t.ti < d.cti - 1 && t.lane < 63 && i + 1 < nx;
+    n.she = t.ti < g.cti - 1 && t.lane < 63 && i + 1 < nx;
     n.shw = t.ti > 0 && t.lane > 0;
-    n.lyn = t.tj < d.ctj - 1 && j + 1 < ny;
+    n.lyn = t.tj < g.ctj - 1 && j + 1 < ny;
     n.lys = t.tj > 0;
     return n;
 }
@@ -91,12 +91,12 @@ struct Halo {
     int off[2];
 };
 
-__device__ __forceinline__ Halo rhs_halo(const Dom &d, int tile, int nth)
+__device__ __forceinline__ Halo rhs_halo(const Dom &d, const MGeo &g, int tile, int nth)
 {
-    const int per = d.cnti * d.cntj;
+    const int per = g.cnti * g.cntj;
     const int rem = tile - (tile / per) * per;
-    const int jt = rem / d.cnti, it = rem - jt * d.cnti;
-    const int TI = d.cti, TJ = d.ctj, nx = d.nx, ny = d.ny;
+    const int jt = rem / g.cnti, it = rem - jt * g.cnti;
+    const int TI = g.cti, TJ = g.ctj, nx = d.nx, ny = d.ny;
     const int i0 = it * TI, j0 = jt * TJ;
     const int w = min(TI, nx - i0), h = min(TJ, ny - j0);
     const int ie = (i0 + w == nx) ? 0 : i0 + w, je = (j0 + h == ny) ? 0 : j0 + h;
@@ -137,20 +137,22 @@ __device__ __forceinline__ Halo rhs_halo(const Dom &d, int tile, int nth)
 template <int NTH = NT>
 __device__ __forceinline__ void pass_rhs(const Dom &d, int tile, char *smem)
 {
+    constexpr int MG = 0;
     double *red = (double *)smem;
     double *sP = red + 16, *sR = sP + NTH, *sU = sR + NTH, *sV = sU + NTH, *hal = sV + NTH;
-    const MTile t = march_tile(d, tile);
-    const MNbr n = march_nbr(d, t);
-    const int nx = d.nx, ny = d.ny, nz = d.nz, sz = nx * ny, TI = d.cti, TJ = d.ctj;
+    const MGeo &g = d.mg[MG];
+    const MTile t = march_tile(d, g, tile);
+    const MNbr n = march_nbr(d, g, t);
+    const int nx = d.nx, ny = d.ny, nz = d.nz, sz = nx * ny, TI = g.cti, TJ = g.ctj;
     const int col = t.j * nx + t.i;
     const double rr0 = d.rho0, tr0 = 2.0 * d.rho0;
     const double idx2 = d.idx * d.idx, idy2 = d.idy * d.idy, cdiv = d.rho0 / d.dt;
     const int nh = 5 * (TI + TJ);
-    const Halo H = rhs_halo(d, tile, NTH);
+    const Halo H = rhs_halo(d, g, tile, NTH);
     const bool hv0 = threadIdx.x < nh, hv1 = threadIdx.x + NTH < nh;
     // tile origin from the tile index (t.i, t.j are clamped for idle threads)
-    const int per = d.cnti * d.cntj, rem = tile - (tile / per) * per;
-    const int i0 = (rem % d.cnti) * TI, j0 = (rem / d.cnti) * TJ;
+    const int per = g.cnti * g.cntj, rem = tile - (tile / per) * per;
+    const int i0 = (rem % g.cnti) * TI, j0 = (rem / g.cnti) * TJ;
     const bool inE = t.ti + 1 < min(TI, nx - i0), inN = t.tj + 1 < min(TJ, ny - j0);
     const int me = threadIdx.x;
     auto kp = [&](int k) { return k == nz - 1 ? 0 : k + 1; };
@@ -226,16 +228,18 @@ __device__ __forceinline__ void pass_rhs(const Dom &d, int tile, char *smem)
 template <int NTH = NT>
 __device__ __forceinline__ void pass_resid(const Dom &d, int tile, char *smem, int solve)
 {
+    constexpr int MG = 0;
     double *red = (double *)smem;
     double *sP = red + 16, *hal = sP + NTH;
-    const MTile t = march_tile(d, tile);
-    const MNbr n = march_nbr(d, t);
-    const int nx = d.nx, ny = d.ny, nz = d.nz, sz = nx * ny, TI = d.cti, TJ = d.ctj;
+    const MGeo &g = d.mg[MG];
+    const MTile t = march_tile(d, g, tile);
+    const MNbr n = march_nbr(d, g, t);
+    const int nx = d.nx, ny = d.ny, nz = d.nz, sz = nx * ny, TI = g.cti, TJ = g.ctj;
     const int col = t.j * nx + t.i;
     const double idx2 = d.idx * d.idx, idy2 = d.idy * d.idy;
     // tile origin from the tile index (t.i, t.j are clamped for idle threads)
-    const int per = d.cnti * d.cntj, rem = tile - (tile / per) * per;
-    const int i0 = (rem % d.cnti) * TI, j0 = (rem / d.cnti) * TJ;
+    const int per = g.cnti * g.cntj, rem = tile - (tile / per) * per;
+    const int i0 = (rem % g.cnti) * TI, j0 = (rem / g.cnti) * TJ;
     const int w = min(TI, nx - i0), h = min(TJ, ny - j0);
     const bool inE = t.ti + 1 < w, inN = t.tj + 1 < h;
     // halo item of this thread (nh = 2 (TI + TJ) <= NTH)
@@ -308,12 +312,12 @@ __device__ __forceinline__ void pass_resid(const Dom &d, int tile, char *smem, i
 // read a clamped cell and are never used.  Each thread owns at most two
 // items; the host keeps 7 (TI + TJ) <= 2 x threads.
 
-__device__ __forceinline__ Halo corr_halo(const Dom &d, int tile, int nth)
+__device__ __forceinline__ Halo corr_halo(const Dom &d, const MGeo &g, int tile, int nth)
 {
-    const int per = d.cnti * d.cntj;
+    const int per = g.cnti * g.cntj;
     const int rem = tile - (tile / per) * per;
-    const int jt = rem / d.cnti, it = rem - jt * d.cnti;
-    const int TI = d.cti, TJ = d.ctj, nx = d.nx, ny = d.ny;
+    const int jt = rem / g.cnti, it = rem - jt * g.cnti;
+    const int TI = g.cti, TJ = g.ctj, nx = d.nx, ny = d.ny;
     const int i0 = it * TI, j0 = jt * TJ;
     const int w = min(TI, nx - i0), h = min(TJ, ny - j0);
     const int ie = (i0 + w == nx) ? 0 : i0 + w, je = (j0 + h == ny) ? 0 : j0 + h;
@@ -358,20 +362,22 @@ __device__ __forceinline__ Halo corr_halo(const Dom &d, int tile, int nth)
 template <int NTH = NT>
 __device__ __forceinline__ void pass_corr(const Dom &d, int tile, char *smem, bool divcheck)
 {
+    constexpr int MG = 1;
     double *red = (double *)smem;
     double *sP = red + 16, *sS = sP + NTH, *sR = sS + NTH, *sE = sR + NTH, *sF = sE + NTH, *hal = sF + NTH;
-    const MTile t = march_tile(d, tile);
-    const MNbr n = march_nbr(d, t);
-    const int nx = d.nx, ny = d.ny, nz = d.nz, sz = nx * ny, TI = d.cti, TJ = d.ctj;
+    const MGeo &g = d.mg[MG];
+    const MTile t = march_tile(d, g, tile);
+    const MNbr n = march_nbr(d, g, t);
+    const int nx = d.nx, ny = d.ny, nz = d.nz, sz = nx * ny, TI = g.cti, TJ = g.ctj;
     const int col = t.j * nx + t.i;
     const double dt = d.dt, ir0 = d.irho0;
     const int nh = 7 * (TI + TJ);
-    const Halo H = corr_halo(d, tile, NTH);
+    const Halo H = corr_halo(d, g, tile, NTH);
     const bool hv0 = threadIdx.x < nh, hv1 = threadIdx.x + NTH < nh;
     // tile extent and where the neighbours of this cell live
     // tile origin from the tile index (t.i, t.j are clamped for idle threads)
-    const int per = d.cnti * d.cntj, rem = tile - (tile / per) * per;
-    const int i0 = (rem % d.cnti) * TI, j0 = (rem / d.cnti) * TJ;
+    const int per = g.cnti * g.cntj, rem = tile - (tile / per) * per;
+    const int i0 = (rem % g.cnti) * TI, j0 = (rem / g.cnti) * TJ;
     const bool inE = t.ti + 1 < min(TI, nx - i0), inN = t.tj + 1 < min(TJ, ny - j0);
     const int me = threadIdx.x;
     auto kp = [&](int k) { return k == nz - 1 ? 0 : k + 1; };

@@ -12,7 +12,7 @@ namespace pcx {
 
 struct Shapes {
     int tj = 8, tk = 8, zg = 64, smax = 8;
-    int yth = 256, mth = 512, xth = 512;
+    int yth = 256, mth = 512, mthc = 1024, xth = 512;
     bool batch = false;
 };
 
