@@ -55,11 +55,14 @@ def build(force: bool = True) -> str:
 
 
 def lib():
+    """The compiled oracle; PCX_ORACLE_LIB names another build of the same
+    source (the mutation tests load deliberately broken copies that way)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
+        path = os.environ.get("PCX_ORACLE_LIB") or _LIB_PATH
+        if path == _LIB_PATH and not os.path.exists(_LIB_PATH):
             build()
-        L = C.CDLL(_LIB_PATH)
+        L = C.CDLL(path)
         G = C.POINTER(OrGrid)
         L.oracle_check_grid.argtypes = [G]
         L.oracle_step.argtypes = [G, C.c_double, C.c_double] + [_DP] * 9 + [C.POINTER(OrDiag)]
