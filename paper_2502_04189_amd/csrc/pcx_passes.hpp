@@ -581,7 +581,9 @@ __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
 {
     using C = c2<T>;
     C *buf = (C *)smem;
-    const int ny = d.ny, nz = d.nz, nl = d.nl, tk = d.tk;
+    // the forward and the inverse pass may use different column counts
+    const int ny = d.ny, nz = d.nz, nl = d.nl, tk = INV ? d.tk : d.tkf, ntk = INV ? d.ntk : d.ntkf;
+    const FastDiv dtk = INV ? d.dtk : d.dtkf;
     const int ldc = lds_line(ny);
     C *ltw = buf + tk * ldc;
     const bool wy = d.bcy == BC_WALL;
@@ -591,7 +593,7 @@ __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
     C *s2 = (C *)d.s2;
     const C *wd = (const C *)d.dcty;
     const int hy = ny / 2;
-    const int kt = tile % d.ntk, l = tile / d.ntk;
+    const int kt = tile % ntk, l = tile / ntk;
     const int k0 = kt * tk;
     const int cols = min(tk, nz - k0);
     stage_twiddles<T, NTH>(ltw, d.fy);
@@ -610,11 +612,11 @@ __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
         staged_copy<NTH, 8, C>(
             tk * ny,
             [&](int e) {
-                const int m = (int)fdiv((uint32_t)e, d.dtk), c = e - m * tk;
+                const int m = (int)fdiv((uint32_t)e, dtk), c = e - m * tk;
                 return s2[((size_t)l * ny + m) * nz + k0 + min(c, cols - 1)];
             },
             [&](int e, C v) {
-                const int m = (int)fdiv((uint32_t)e, d.dtk), c = e - m * tk;
+                const int m = (int)fdiv((uint32_t)e, dtk), c = e - m * tk;
                 if (c < cols) buf[c * ldc + pidx(m)] = v;
             });
         if (wy) {
@@ -660,11 +662,11 @@ __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
         staged_copy<NTH, 8, C>(
             tk * ny,
             [&](int e) {
-                const int m = (int)fdiv((uint32_t)e, d.dtk), c = e - m * tk;
+                const int m = (int)fdiv((uint32_t)e, dtk), c = e - m * tk;
                 return buf[min(c, cols - 1) * ldc + pidx(m)];
             },
             [&](int e, C v) {
-                const int m = (int)fdiv((uint32_t)e, d.dtk), c = e - m * tk;
+                const int m = (int)fdiv((uint32_t)e, dtk), c = e - m * tk;
                 if (c < cols) s2[((size_t)l * ny + m) * nz + k0 + c] = v;
             });
     } else {
