@@ -60,7 +60,9 @@ template <typename T, int SMAX>
 __global__ __launch_bounds__(NT) void k_z(Dom d)
 {
     extern __shared__ __align__(16) char smem[];
-    pass_z<T, SMAX>(d, blockIdx.x, smem);
+    // lines in the reverse of the order the forward y pass wrote them, so the
+    // first tiles read what the device-side cache still holds
+    pass_z<T, SMAX>(d, d.nzt - 1 - (int)blockIdx.x, smem);
 }
 
 template <typename T, int MODE, int NTH>
