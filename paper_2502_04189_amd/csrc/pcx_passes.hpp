@@ -904,6 +904,20 @@ __device__ __forceinline__ void pass_xinv(const Dom &d, int tile, char *smem, in
             int r = e - l * tj;
             if (r < rows) buf[r * ldr + pidx(l)] = v;
         });
+    // accumulate: the old p of this thread's first output pairs is fetched
+    // now, so the loads are in flight during the transform (fewer in the
+    // 256-thread batch kernel, whose register budget is tighter)
+    constexpr int PF = NTH >= 512 ? 8 : 2;
+    const int npair = rows * (d.nx >> 1);
+    double2 oldv[PF];
+    double2 *po2 = (double2 *)(d.po + ((size_t)k * d.ny + j0) * d.nx);
+    if (MODE == XOUT_ACCUM) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int e = threadIdx.x + q * NTH;
+            oldv[q] = e < npair ? po2[e] : double2{0.0, 0.0};
+        }
+    }
     __syncthreads();
     const bool wx = d.bcx == BC_WALL;
     const C *wd = (const C *)d.dctx;
@@ -940,7 +954,6 @@ __device__ __forceinline__ void pass_xinv(const Dom &d, int tile, char *smem, in
     const double shift = (MODE == XOUT_ACCUM) ? d.pmean[0] : 0.0;
     double emax = 0.0, pmax = 0.0, psum = 0.0;
     const int hx = nx >> 1;
-    double2 *po2 = (double2 *)(d.po + ((size_t)k * d.ny + j0) * nx);
     // output pairs p[2h], p[2h+1] of row r: complex point h of the
     // half-length FFT, or (wall x) points h and N-1-h of the reordered sequence
     auto value = [&](const C *row, int h) {
@@ -979,13 +992,19 @@ __device__ __forceinline__ void pass_xinv(const Dom &d, int tile, char *smem, in
                 emit(e, value(buf + r * ldr, e - r * hx), double2{0.0, 0.0});
             }
         } else {
-            // accumulate: the reads of the old p are issued together first
-            staged_copy<NTH, 8, double2>(
-                rows * hx, [&](int e) { return po2[e]; },
-                [&](int e, double2 old) {
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                const int e = threadIdx.x + q * NTH;
+                if (e < npair) {
                     int r = (int)fdiv((uint32_t)e, d.dM);
-                    emit(e, value(buf + r * ldr, e - r * hx), old);
-                });
+                    emit(e, value(buf + r * ldr, e - r * hx), oldv[q]);
+                }
+            }
+            // pairs beyond the prefetched ones (tiles of more than PF x NTH pairs)
+            for (int e = threadIdx.x + PF * NTH; e < npair; e += NTH) {
+                int r = (int)fdiv((uint32_t)e, d.dM);
+                emit(e, value(buf + r * ldr, e - r * hx), po2[e]);
+            }
         }
     }
     if (d.ppart) {
