@@ -263,6 +263,81 @@ __device__ __forceinline__ void stage_twiddles(c2<T> *ltw, const FftDesc &fd)
     for (int e = threadIdx.x; e < th; e += NTH) ltw[e] = tw[e];
 }
 
+// ------------------------------------------------------ wave-level FFT
+// Lengths 256 and 512 (the default radix plans 8.8.4 and 8.8.8) can also be
+// transformed by one wave per line: butterfly j of a stage is lane j mod 64,
+// every index is a compile-time shift or mask, and no workgroup barrier is
+// needed between stages (the LDS operations of one wave execute in order;
+// the fences keep the compiler from moving them across a stage boundary).
+// Same arithmetic, in the same order, as fft_stage with the same radices.
+__host__ __device__ constexpr bool wave_len(int n) { return n == 256 || n == 512; }
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// LDS position of element e + r S: for S a multiple of 8 the padding adds
+// exactly S/8 per step, so the offsets are constants.
+template <int S> __device__ __forceinline__ int pstep(int pe, int e, int r)
+{
+    if constexpr (S % 8 == 0) return pe + r * (S + S / 8);
+    else return pidx(e + r * S);
+}
+
+template <typename T, bool INV, int N, int R, int NS>
+__device__ __forceinline__ void wstage(c2<T> *ln, const c2<T> *tw, int lane)
+{
+    using C = c2<T>;
+    constexpr int NB = N / R, TS = N / (NS * R);
+    static_assert(NB <= 64, "one butterfly per lane");
+    const int j = lane;
+    const bool on = NB == 64 || j < NB;
+    C v[R];
+    if (on) {
+        const int pj = pidx(j);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = ln[pstep<NB>(pj, j, r)];
+        if constexpr (NS > 1) {
+            const int jm = j & (NS - 1);
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const int e = jm * r * TS;
+                C w = e < N / 2 ? tw[e] : C{-tw[e - N / 2].x, -tw[e - N / 2].y};
+                if (INV) w.y = -w.y;
+                v[r] = cmul(v[r], w);
+            }
+        }
+    }
+    wave_sync();
+    if (on) {
+        bfly<INV, R, C, T>(v);
+        const int o = (j / NS) * NS * R + (j & (NS - 1));
+        const int po = pidx(o);
+#pragma unroll
+        for (int r = 0; r < R; ++r) ln[pstep<NS>(po, o, r)] = v[r];
+    }
+    wave_sync();
+}
+
+// Whole line of length n (wave_len(n)) by the calling wave.
+template <typename T, bool INV>
+__device__ __forceinline__ void wave_fft(c2<T> *ln, const c2<T> *tw, int n, int lane)
+{
+    wave_sync();
+    if (n == 256) {
+        wstage<T, INV, 256, 8, 1>(ln, tw, lane);
+        wstage<T, INV, 256, 8, 8>(ln, tw, lane);
+        wstage<T, INV, 256, 4, 64>(ln, tw, lane);
+    } else {
+        wstage<T, INV, 512, 8, 1>(ln, tw, lane);
+        wstage<T, INV, 512, 8, 8>(ln, tw, lane);
+        wstage<T, INV, 512, 8, 64>(ln, tw, lane);
+    }
+}
+
 // ------------------------------------------------------- staged copies
 // Moves `total` elements with all of a thread's reads of one round issued
 // before its first write, CNT per thread per round: a global -> LDS copy

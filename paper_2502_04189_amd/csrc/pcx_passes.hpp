@@ -576,7 +576,7 @@ __device__ __forceinline__ void pass_xfwd(const Dom &d, int tile, char *smem)
 // Y pass, tile = (k tile, l).  Forward: columns (k, l) of S1 -> LDS -> FFT
 // (DCT-II for a wall) -> corner turn into the z-lines of S2; inverse the
 // reverse.
-template <typename T, bool INV, int NTH = NT>
+template <typename T, bool INV, int NTH = NT, bool WV = true>
 __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
 {
     using C = c2<T>;
@@ -597,7 +597,20 @@ __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
     const int k0 = kt * tk;
     const int cols = min(tk, nz - k0);
     stage_twiddles<T, NTH>(ltw, d.fy);
-    if (!INV) {
+    // one wave per column when the tile has at most one column per wave and
+    // the length has the fixed wave plan (which must be the descriptor's)
+    constexpr int NW = NTH / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const bool wv = WV && tk <= NW && wave_len(ny) && d.fy.nst == 3 && d.fy.rad[0] == 8 && d.fy.rad[1] == 8 &&
+                    d.fy.rad[2] == (ny == 512 ? 8 : 4);
+    if (!INV && wv) {
+        if (wid < cols) {
+            const C *src = s1 + ((size_t)(k0 + wid) * nl + l) * ny;
+            C *col = buf + wid * ldc;
+            staged_copy_t<64, 8, C>(
+                lane, ny, [&](int j) { return src[j]; }, [&](int j, C v) { col[pidx(pos(j))] = v; });
+        }
+    } else if (!INV) {
         staged_copy<NTH, 8, C>(
             cols * ny,
             [&](int e) {
@@ -619,7 +632,7 @@ __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
                 const int m = (int)fdiv((uint32_t)e, dtk), c = e - m * tk;
                 if (c < cols) buf[c * ldc + pidx(m)] = v;
             });
-        if (wy) {
+        if (wy && !wv) {
             // inverse DCT-II of complex columns: V_k = conj(w_k)(X_k - i X_{N-k}),
             // V_{N-k} = i w_k (X_{N-k} - i X_k), w_k = W_{4N}^k, X_N = 0
             __syncthreads();
@@ -641,9 +654,48 @@ __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
         }
     }
     __syncthreads();
-    lds_fft<T, INV, NTH>(buf, ldc, cols, d.fy, ltw);
+    if (wv) {
+        if (wid < cols) {
+            C *col = buf + wid * ldc;
+            if (INV && wy) {
+                // inverse DCT-II pre-step of this column (as in the workgroup path below)
+                for (int kk = 1 + lane; kk <= hy; kk += 64) {
+                    const int kn = ny - kk;
+                    C w = wd[kk];
+                    C xk = col[pidx(kk)], xn = col[pidx(kn)];
+                    C a = {xk.x + xn.y, xk.y - xn.x};
+                    col[pidx(kk)] = cmul(cconj(w), a);
+                    if (kn != kk) {
+                        C b = {xn.x + xk.y, xn.y - xk.x};
+                        C wb = cmul(w, b);
+                        col[pidx(kn)] = C{-wb.y, wb.x};
+                    }
+                }
+            }
+            wave_fft<T, INV>(col, ltw, ny, lane);
+            if (!INV && wy) {
+                for (int kk = 1 + lane; kk <= hy; kk += 64) {
+                    const int kn = ny - kk;
+                    C w = wd[kk];
+                    C p = cmul(w, col[pidx(kk)]), q = cmul(cconj(w), col[pidx(kn)]);
+                    col[pidx(kk)] = C{T(0.5) * (p.x + q.x), T(0.5) * (p.y + q.y)};
+                    if (kn != kk) col[pidx(kn)] = C{T(-0.5) * (p.y - q.y), T(0.5) * (p.x - q.x)};
+                }
+            }
+            if (INV) {
+                // the column goes back to S1 by its own wave
+                wave_sync();
+                C *dst = s1 + ((size_t)(k0 + wid) * nl + l) * ny;
+                for (int j = lane; j < ny; j += 64) dst[j] = col[pidx(pos(j))];
+            }
+        }
+        if (INV) return;
+        __syncthreads();
+    } else {
+        lds_fft<T, INV, NTH>(buf, ldc, cols, d.fy, ltw);
+    }
     if (!INV) {
-        if (wy) {
+        if (wy && !wv) {
             // DCT-II of complex columns from the FFT V of the reordered data:
             // X_k = (w_k V_k + conj(w_k) V_{N-k}) / 2,
             // X_{N-k} = i (w_k V_k - conj(w_k) V_{N-k}) / 2, X_0 = V_0
