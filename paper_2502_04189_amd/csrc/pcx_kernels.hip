@@ -351,13 +351,13 @@ __global__ __launch_bounds__(NT) void k_persist(PersistArgs a)
             switch (kind) {
             case PK_RHS: pass_rhs(d, tile, smem); break;
             case PK_RESID: pass_resid(d, tile, smem, sv); break;
-            case PK_XFWD_RHS: pass_xfwd<T, SRC_RHS>(d, tile, smem); break;
-            case PK_XFWD_RESID: pass_xfwd<T, SRC_RESID>(d, tile, smem); break;
+            case PK_XFWD_RHS: pass_xfwd<T, SRC_RHS, NT, false>(d, tile, smem); break;
+            case PK_XFWD_RESID: pass_xfwd<T, SRC_RESID, NT, false>(d, tile, smem); break;
             case PK_YF: pass_y<T, false, NT, false>(d, tile, smem); break;
             case PK_Z: pass_z<T, SMAX>(d, tile, smem); break;
             case PK_YI: pass_y<T, true, NT, false>(d, tile, smem); break;
-            case PK_XINV_STORE: pass_xinv<T, XOUT_STORE>(d, tile, smem, sv); break;
-            case PK_XINV_ACCUM: pass_xinv<T, XOUT_ACCUM>(d, tile, smem, sv); break;
+            case PK_XINV_STORE: pass_xinv<T, XOUT_STORE, NT, false>(d, tile, smem, sv); break;
+            case PK_XINV_ACCUM: pass_xinv<T, XOUT_ACCUM, NT, false>(d, tile, smem, sv); break;
             case PK_PMEAN:
                 pass_xmax(d, sv, 0, 1, smem);
                 __syncthreads();

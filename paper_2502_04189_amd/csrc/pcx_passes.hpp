@@ -481,7 +481,7 @@ __device__ __forceinline__ void pass_div(const Dom &d, int tile, char *smem)
 // Tile = (j tile, k): rows j0 .. j0+rows-1 of plane k of f (or r).  Real
 // FFT by a half-length complex FFT of z[n] = s[2n] + i s[2n+1] and the split
 // X[l] = E + W^l O, X[M-l] = conj(E - W^l O); then the corner turn into S1.
-template <typename T, int SRC, int NTH = NT>
+template <typename T, int SRC, int NTH = NT, bool WV = true>
 __device__ __forceinline__ void pass_xfwd(const Dom &d, int tile, char *smem)
 {
     using C = c2<T>;
@@ -535,7 +535,31 @@ __device__ __forceinline__ void pass_xfwd(const Dom &d, int tile, char *smem)
         row[pidx(kk)] = C{a.x, T(0)};
         if (kk >= 1 && kk < M) row[pidx(nx - kk)] = C{-a.y, T(0)};
     };
-    {
+    // one wave per row when the tile has at most one row per wave and the
+    // half length has the fixed wave plan (which must be the descriptor's)
+    constexpr int NW = NTH / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const bool wv = WV && d.tj <= NW && wave_len(M) && d.fx.nst == 3 && d.fx.rad[0] == 8 && d.fx.rad[1] == 8 &&
+                    d.fx.rad[2] == (M == 512 ? 8 : 4);
+    if (wv) {
+        if (wid < rows) {
+            C *row = buf + wid * ldr;
+            const double2 *sr = src2 + (size_t)wid * hx;
+            staged_copy_t<64, 8, double2>(
+                lane, hx, [&](int h) { return sr[h]; }, [&](int h, double2 s) { put_pair(row, h, s); });
+        }
+        __syncthreads(); // the twiddles
+        if (wid < rows) {
+            C *row = buf + wid * ldr;
+            wave_fft<T, false>(row, ltw, M, lane);
+            for (int l = lane; l <= half; l += 64) split(row, l);
+            if (wx) {
+                wave_sync();
+                for (int kk = lane; kk <= M; kk += 64) dct(row, kk);
+            }
+        }
+        __syncthreads();
+    } else {
         staged_copy<NTH, 8, double2>(
             rows * hx, [&](int e) { return src2[e]; },
             [&](int e, double2 s) {
@@ -930,7 +954,7 @@ __device__ __forceinline__ void pass_z(const Dom &d, int tile, char *smem)
 // ------------------------------------------------------------------ xinv
 // Tile = (j tile, k).  Inverse real FFT of rows j0.. of plane k from S1;
 // MODE store: p = value; accum: p += value (refinement update).
-template <typename T, int MODE, int NTH = NT>
+template <typename T, int MODE, int NTH = NT, bool WV = true>
 __device__ __forceinline__ void pass_xinv(const Dom &d, int tile, char *smem, int solve)
 {
     using C = c2<T>;
@@ -963,10 +987,18 @@ __device__ __forceinline__ void pass_xinv(const Dom &d, int tile, char *smem, in
     const int npair = rows * (d.nx >> 1);
     double2 oldv[PF];
     double2 *po2 = (double2 *)(d.po + ((size_t)k * d.ny + j0) * d.nx);
+    // one wave per row (see below) when the tile has at most one row per
+    // wave and the half length has the fixed wave plan
+    constexpr int NW = NTH / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const bool wv = WV && d.tj <= NW && wave_len(M) && d.fx.nst == 3 && d.fx.rad[0] == 8 && d.fx.rad[1] == 8 &&
+                    d.fx.rad[2] == (M == 512 ? 8 : 4) && (M >> 6) <= PF;
     if (MODE == XOUT_ACCUM) {
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
-            const int e = threadIdx.x + q * NTH;
+            // pair of this thread: (row wid, lane + 64 q) on the wave path
+            const int e = wv ? (wid < rows && lane + 64 * q < (M) ? wid * M + lane + 64 * q : npair)
+                             : threadIdx.x + q * NTH;
             oldv[q] = e < npair ? po2[e] : double2{0.0, 0.0};
         }
     }
@@ -1024,7 +1056,23 @@ __device__ __forceinline__ void pass_xinv(const Dom &d, int tile, char *smem, in
         emax = amax_nan(amax_nan(emax, val.x), val.y);
         pmax = amax_nan(amax_nan(pmax, pv.x), pv.y);
     };
-    {
+    if (wv) {
+        // one wave per row: pre-steps, transform and output of its row
+        if (wid < rows) {
+            C *row = buf + wid * ldr;
+            if (wx) {
+                for (int kk = lane; kk <= M; kk += 64) dct_pre(row, kk);
+                wave_sync();
+            }
+            for (int l = lane; l <= half; l += 64) c2r_pre(row, l);
+            wave_fft<T, true>(row, ltw, M, lane);
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                const int h = lane + 64 * q;
+                if (h < hx) emit(wid * hx + h, value(row, h), MODE == XOUT_STORE ? double2{0.0, 0.0} : oldv[q]);
+            }
+        }
+    } else {
         if (wx) {
             for (int idx = threadIdx.x; idx < rows * (M + 1); idx += NTH) {
                 int r = (int)fdiv((uint32_t)idx, d.dM1);
