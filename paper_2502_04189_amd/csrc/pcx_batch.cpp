@@ -86,7 +86,7 @@ static long tiles_of(const Dom &d, int kind)
     case PK_XFWD_RESID:
     case PK_XINV_STORE:
     case PK_XINV_ACCUM: return (long)d.ntj * d.nz;
-    case PK_YF: return (long)d.ntkf * d.nl;
+    case PK_YF:
     case PK_YI: return (long)d.ntk * d.nl;
     case PK_Z: return d.nzt;
     case PK_PMEAN: return 1;

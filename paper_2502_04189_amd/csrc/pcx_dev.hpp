@@ -69,13 +69,12 @@ struct Dom {
     int nx, ny, nz, nl, M;            // M = nx/2 (half-length complex FFT)
     int bcx, bcy, bcz;
     int tj, ntj;                      // x-pass rows per tile, j tiles
-    int tk, ntk;                      // y-pass columns per tile, k tiles (inverse)
-    int tkf, ntkf;                    // the same for the forward y pass
+    int tk, ntk;                      // y-pass columns per tile, k tiles
     int zg, zlpw, nzt;                // z lanes per line, lines per WG, z tiles
     MGeo mg[2];                       // marching tiles: [0] RHS and residual, [1] correction
     int ndiv_tiles;                   // divergence-only tiles (NT cells each)
-    int mth, yth, ythf, xth;          // threads of the marching, y (inverse, forward) and x workgroups
-    FastDiv dnx, dny, dtj, dtk, dtkf, dnyc, dM, dH1, dM1, dhy; // dH1: M/2+1, dM1: M+1, dhy: ny/2
+    int mth, yth, xth;                // threads of the marching, y and x workgroups
+    FastDiv dnx, dny, dtj, dtk, dnyc, dM, dH1, dM1, dhy; // dH1: M/2+1, dM1: M+1, dhy: ny/2
     double dx, dy, idx, idy, dt, rho0, irho0, lz, scale;
     // z tables (FP64): dzf, 1/dzf, 1/dzc, rho interpolation weights
     const double *dzf, *idzf, *idzc, *rzlo, *rzhi;

@@ -162,13 +162,12 @@ void choose_shapes(const pcx_grid &g, int prec, const TuneParams *tp, Shapes &sh
     sh.mth = batch ? NT : 512;
     sh.mthc = batch ? NT : 1024;
     // wider y workgroups when a tile holds many columns: more waves per CU
-    sh.yth = (!batch && (long)sh.tk * (lds_line(g.ny) * (long)csz) > 48 * 1024) ? 512 : NT;
-    // the forward y pass writes the z-lines in segments of tkf points: at
-    // FP64, half the inverse pass's columns (64-byte segments) keeps twice the
-    // workgroups per CU and measured faster; the inverse pass reads whole
-    // 128-byte segments
-    sh.tkf = (prec == PREC_F64 && !batch && sh.tk >= 8) ? sh.tk / 2 : sh.tk;
-    sh.ythf = (!batch && (long)sh.tkf * (lds_line(g.ny) * (long)csz) > 48 * 1024) ? 512 : NT;
+    // 512-thread y workgroups when a tile holds many columns (more waves per
+    // CU), and when its columns fit one per wave on the wave-level FFT path
+    sh.yth = (!batch && ((long)sh.tk * (lds_line(g.ny) * (long)csz) > 48 * 1024 ||
+                         (wave_len(g.ny) && sh.tk > NT / 64 && sh.tk <= 8)))
+                 ? 512
+                 : NT;
     sh.xth = batch ? NT : 512;
     sh.batch = batch;
 }
@@ -184,7 +183,6 @@ pcx_status build_domain(const pcx_grid &g, int prec, const Shapes &sh, const Rad
     d.bcx = g.bc_x; d.bcy = g.bc_y; d.bcz = g.bc_z;
     d.tj = sh.tj; d.ntj = (ny + sh.tj - 1) / sh.tj;
     d.tk = sh.tk; d.ntk = (nz + sh.tk - 1) / sh.tk;
-    d.tkf = sh.tkf; d.ntkf = (nz + sh.tkf - 1) / sh.tkf;
     d.zg = sh.zg; d.zlpw = (NT / 64) * (64 / sh.zg);
     long nlines = (long)nl * ny;
     d.nzt = (int)((nlines + d.zlpw - 1) / d.zlpw);
@@ -214,9 +212,8 @@ pcx_status build_domain(const pcx_grid &g, int prec, const Shapes &sh, const Rad
         m.dcti = mkdiv(m.cti);
     }
     d.yth = sh.yth;
-    d.ythf = sh.ythf;
     d.xth = sh.xth;
-    d.dnx = mkdiv(nx); d.dny = mkdiv(ny); d.dtj = mkdiv(sh.tj); d.dtk = mkdiv(sh.tk); d.dtkf = mkdiv(sh.tkf); d.dnyc = mkdiv(ny);
+    d.dnx = mkdiv(nx); d.dny = mkdiv(ny); d.dtj = mkdiv(sh.tj); d.dtk = mkdiv(sh.tk); d.dnyc = mkdiv(ny);
     d.dM = mkdiv(M);
     d.dH1 = mkdiv(M / 2 + 1);
     d.dM1 = mkdiv(M + 1);
@@ -312,11 +309,10 @@ size_t lds_x(const Dom &d, int prec)
 {
     return ((size_t)d.tj * lds_line(d.nl) + tw_half(d.M)) * (prec == PREC_F64 ? 16 : 8) + 128;
 }
-size_t lds_y(const Dom &d, int prec, bool inv)
+size_t lds_y(const Dom &d, int prec)
 {
-    return ((size_t)(inv ? d.tk : d.tkf) * lds_line(d.ny) + tw_half(d.ny)) * (prec == PREC_F64 ? 16 : 8) + 64;
+    return ((size_t)d.tk * lds_line(d.ny) + tw_half(d.ny)) * (prec == PREC_F64 ? 16 : 8) + 64;
 }
-size_t lds_y(const Dom &d, int prec) { return std::max(lds_y(d, prec, true), lds_y(d, prec, false)); }
 size_t lds_z(const Dom &d, int prec)
 {
     size_t e = (size_t)d.zlpw * d.nz;
@@ -415,8 +411,7 @@ extern "C" pcx_status pcx_plan_create(const pcx_grid *grid, const pcx_options *o
     P->dom.xpart = P->xpart;
     P->dom.pmean = P->ppart ? P->ppart + (size_t)P->dom.ntj * grid->nz : nullptr;
     P->lx = lds_x(P->dom, P->prec);
-    P->ly = lds_y(P->dom, P->prec, true);
-    P->lyf = lds_y(P->dom, P->prec, false);
+    P->ly = lds_y(P->dom, P->prec);
     P->lzs = lds_z(P->dom, P->prec);
     *out = P;
     return PCX_OK;
@@ -498,7 +493,7 @@ extern "C" const char *pcx_plan_pass_name(pcx_plan P, int32_t i)
 // side already placed (x-transformed) in S1, ending with p stored/accumulated.
 static pcx_status solve_tail(pcx_plan P, const Dom &d, int solve, int mode, hipStream_t s)
 {
-    HIPCHK(launch_y(d, P->prec, false, P->lyf, s));
+    HIPCHK(launch_y(d, P->prec, false, P->ly, s));
     tmark(P, s, "y_fft_fwd");
     HIPCHK(launch_z(d, P->prec, P->sh.smax, P->lzs, s));
     tmark(P, s, "z_solve");

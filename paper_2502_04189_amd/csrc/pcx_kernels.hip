@@ -202,8 +202,8 @@ hipError_t launch_xfwd(const Dom &d, int prec, int src, size_t lds, hipStream_t 
 
 hipError_t launch_y(const Dom &d, int prec, bool inv, size_t lds, hipStream_t s)
 {
-    const int grid = (inv ? d.ntk : d.ntkf) * d.nl;
-    if ((inv ? d.yth : d.ythf) == 512) {
+    const int grid = d.ntk * d.nl;
+    if (d.yth == 512) {
         if (prec == PREC_F64) {
             if (inv) PCX_LAUNCH_B((k_y<double, true, 512>), grid, 512, lds, s, d);
             PCX_LAUNCH_B((k_y<double, false, 512>), grid, 512, lds, s, d);

@@ -605,9 +605,8 @@ __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
 {
     using C = c2<T>;
     C *buf = (C *)smem;
-    // the forward and the inverse pass may use different column counts
-    const int ny = d.ny, nz = d.nz, nl = d.nl, tk = INV ? d.tk : d.tkf, ntk = INV ? d.ntk : d.ntkf;
-    const FastDiv dtk = INV ? d.dtk : d.dtkf;
+    const int ny = d.ny, nz = d.nz, nl = d.nl, tk = d.tk, ntk = d.ntk;
+    const FastDiv dtk = d.dtk;
     const int ldc = lds_line(ny);
     C *ltw = buf + tk * ldc;
     const bool wy = d.bcy == BC_WALL;

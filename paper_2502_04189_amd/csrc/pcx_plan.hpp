@@ -12,8 +12,7 @@ namespace pcx {
 
 struct Shapes {
     int tj = 8, tk = 8, zg = 64, smax = 8;
-    int yth = 256, ythf = 256, mth = 512, mthc = 1024, xth = 512;
-    int tkf = 1;
+    int yth = 256, mth = 512, mthc = 1024, xth = 512;
     bool batch = false;
 };
 
@@ -40,7 +39,6 @@ void choose_shapes(const pcx_grid &g, int prec, const TuneParams *tp, Shapes &sh
 pcx_status build_domain(const pcx_grid &g, int prec, const Shapes &sh, const RadixChoice *rc, DomTables &tb, Dom &d);
 size_t lds_x(const Dom &d, int prec);
 size_t lds_y(const Dom &d, int prec);
-size_t lds_y(const Dom &d, int prec, bool inv);
 size_t lds_z(const Dom &d, int prec);
 
 } // namespace pcx
@@ -62,7 +60,7 @@ struct pcx_plan_s {
     double *xpart = nullptr;
     unsigned long long *stats = nullptr;
     size_t ws_bytes = 0;
-    size_t lx = 0, ly = 0, lyf = 0, lzs = 0;
+    size_t lx = 0, ly = 0, lzs = 0;
     bool timing = false;
     std::vector<hipEvent_t> ev;
     std::vector<std::string> names, pass_names;
