@@ -783,17 +783,24 @@ __device__ __forceinline__ void pass_z(const Dom &d, int tile, char *smem)
     const int nlin = (int)min((long)lpg, nlines_tot - q0);
     C *s2 = (C *)d.s2;
     const size_t gbase = (size_t)q0 * nz;
-    const int nelem = nlin * nz;
+    // Each wave stages, solves and writes back its own lines through its own
+    // LDS region, with no workgroup barrier: the waves of a workgroup drift
+    // apart, so one wave's loads overlap another's arithmetic.
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int wl0 = wv * lpw;                    // first line of this wave
+    const int wlines = min(lpw, nlin - wl0);
+    if (wlines <= 0) return;
+    const int wb = wl0 * nz, wn = wlines * nz;   // element range of the wave
     // padded LDS index: one spare slot per 16 elements
 #define ZP(e) ((e) + ((e) >> 4))
-    staged_copy<NT, 8, C>(nelem, [&](int e) { return s2[gbase + e]; }, [&](int e, C v) { buf[ZP(e)] = v; });
-    __syncthreads();
+    staged_copy_t<64, 8, C>(lane, wn, [&](int e) { return s2[gbase + wb + e]; },
+                            [&](int e, C v) { buf[ZP(wb + e)] = v; });
+    wave_sync();
 
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int t = lane & (G - 1);
-    const int gl = wv * lpw + (lane / G);        // line within the workgroup
+    const int gl = wl0 + (lane / G);             // line within the workgroup
     const bool active = gl < nlin;
-    const int gls = active ? gl : 0;
+    const int gls = active ? gl : wl0;
     const long q = q0 + gls;
     const int l = (int)(q / d.ny), m = (int)(q - (long)l * d.ny);
     const bool sing = (l == 0 && m == 0);
@@ -939,14 +946,15 @@ __device__ __forceinline__ void pass_z(const Dom &d, int tile, char *smem)
         for (int s = 0; s < SMAX; ++s)
             if (s < S) { y[s].x -= acc.x * il; y[s].y -= acc.y * il; }
     }
-    __syncthreads();
+    wave_sync();
     if (active) {
 #pragma unroll
         for (int s = 0; s < SMAX; ++s)
             if (s < S) buf[ZP(gl * nz + k0 + s)] = y[s];
     }
-    __syncthreads();
-    staged_copy<NT, 8, C>(nelem, [&](int e) { return buf[ZP(e)]; }, [&](int e, C v) { s2[gbase + e] = v; });
+    wave_sync();
+    staged_copy_t<64, 8, C>(lane, wn, [&](int e) { return buf[ZP(wb + e)]; },
+                            [&](int e, C v) { s2[gbase + wb + e] = v; });
 #undef ZP
 }
 
@@ -1053,7 +1061,8 @@ __device__ __forceinline__ void pass_xinv(const Dom &d, int tile, char *smem, in
         po2[e] = pv;
         psum += pv.x + pv.y;
         emax = amax_nan(amax_nan(emax, val.x), val.y);
-        pmax = amax_nan(amax_nan(pmax, pv.x), pv.y);
+        // a stored p is the update itself: its maximum is emax
+        if (MODE != XOUT_STORE) pmax = amax_nan(amax_nan(pmax, pv.x), pv.y);
     };
     if (wv) {
         // one wave per row: pre-steps, transform and output of its row
@@ -1106,6 +1115,7 @@ __device__ __forceinline__ void pass_xinv(const Dom &d, int tile, char *smem, in
             }
         }
     }
+    if (MODE == XOUT_STORE) pmax = emax;
     if (d.ppart) {
         double ts = block_sum<NTH>(psum, red);
         if (threadIdx.x == 0) d.ppart[tile] = ts * d.dzf[k];
