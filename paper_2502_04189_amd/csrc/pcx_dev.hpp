@@ -253,14 +253,25 @@ __device__ void lds_fft(c2<T> *buf, int ldb, int nlines, const FftDesc &fd, cons
 }
 
 // Copies the first tw_half(n) roots of fd into LDS (no barrier: the caller's
-// next barrier publishes them).
+// next barrier publishes them), in two halves: fetch() reads this thread's
+// root into a register, put() stores it, so a pass can issue the read ahead
+// of its tile's reads and store it after them (one memory latency instead of
+// two).  Roots beyond the first NTH are copied by put() directly.
 template <typename T, int NTH>
-__device__ __forceinline__ void stage_twiddles(c2<T> *ltw, const FftDesc &fd)
-{
-    const c2<T> *tw = (const c2<T> *)fd.tw;
-    const int th = tw_half(fd.n);
-    for (int e = threadIdx.x; e < th; e += NTH) ltw[e] = tw[e];
-}
+struct TwStage {
+    c2<T> v;
+    __device__ __forceinline__ void fetch(const FftDesc &fd)
+    {
+        v = ((const c2<T> *)fd.tw)[min((int)threadIdx.x, tw_half(fd.n) - 1)];
+    }
+    __device__ __forceinline__ void put(c2<T> *ltw, const FftDesc &fd) const
+    {
+        const c2<T> *tw = (const c2<T> *)fd.tw;
+        const int th = tw_half(fd.n);
+        if ((int)threadIdx.x < th) ltw[threadIdx.x] = v;
+        for (int e = threadIdx.x + NTH; e < th; e += NTH) ltw[e] = tw[e];
+    }
+};
 
 // ------------------------------------------------------ wave-level FFT
 // Lengths 256 and 512 (the default radix plans 8.8.4 and 8.8.8) can also be
@@ -341,24 +352,33 @@ __device__ __forceinline__ void wave_fft(c2<T> *ln, const c2<T> *tw, int n, int 
 // Moves `total` elements with all of a thread's reads of one round issued
 // before its first write, CNT per thread per round: a global -> LDS copy
 // then waits for one memory latency per round instead of one per element.
-// get(e) returns element e, put(e, v) stores it.
+// get(e) returns element e, put(e, v) stores it.  The reads are not under a
+// branch (a worker past the end re-reads the last element) and stay ahead of
+// the writes: a read in a conditional block makes the compiler wait for
+// every earlier read before it, which would serialise the round.
 // staged_copy_t: the same for worker `tid` of STRIDE workers (a wave's lanes).
 template <int STRIDE, int CNT, typename V, typename Get, typename Put>
 __device__ __forceinline__ void staged_copy_t(int tid, int total, Get get, Put put)
 {
-    for (int b = 0; b < total; b += CNT * STRIDE) {
+    auto round = [&](int b) {
         V v[CNT];
 #pragma unroll
-        for (int t = 0; t < CNT; ++t) {
-            int e = b + tid + t * STRIDE;
-            if (e < total) v[t] = get(e);
-        }
+        for (int t = 0; t < CNT; ++t) v[t] = get(min(b + tid + t * STRIDE, total - 1));
+        // keeps the compiler from sinking a read into the conditional write
+        // that consumes it
+        asm volatile("" ::: "memory");
 #pragma unroll
         for (int t = 0; t < CNT; ++t) {
             int e = b + tid + t * STRIDE;
             if (e < total) put(e, v[t]);
         }
-    }
+    };
+    // the first round is peeled: at the head of a loop the compiler cannot
+    // tell which reads of the previous round are still pending, and waits
+    // for all of them (including reads the caller issued just before)
+    if (total <= 0) return;
+    round(0);
+    for (int b = CNT * STRIDE; b < total; b += CNT * STRIDE) round(b);
 }
 
 template <int NTH, int CNT, typename V, typename Get, typename Put>

@@ -74,6 +74,23 @@ __device__ __forceinline__ MNbr march_nbr(const Dom &d, const MGeo &g, const MTi
     return n;
 }
 
+// Plane prefetched during plane k: k + 1, or k itself on the last plane of
+// the chunk (a redundant read whose values are never used).  The prefetch
+// loads, halo items included, are all unconditional, at addresses that are
+// valid for every thread: a load under a branch inside the marching loop
+// makes the compiler wait for every outstanding load (the next plane's
+// included) before the plane's first LDS write.
+__device__ __forceinline__ int march_next(int k, const MTile &t) { return min(k + 1, t.ke - 1); }
+
+// z-metric coefficient of plane k (uniform) by a scalar load: the plan's
+// tables are never written by a kernel, and a scalar load does not queue
+// behind the vector prefetch (waiting for a vector load waits for every
+// vector load issued before it).
+__device__ __forceinline__ double ztab(const double *p, int k)
+{
+    return ((const __attribute__((address_space(4))) double *)p)[__builtin_amdgcn_readfirstlane(k)];
+}
+
 __device__ __forceinline__ double amax_nan(double m, double v)
 {
     double a = fabs(v);
@@ -160,7 +177,7 @@ __device__ __forceinline__ void pass_rhs(const Dom &d, int tile, char *smem)
     double Pc = d.ps[k * sz + col], Rc = d.rho[k * sz + col];
     double Pp = d.ps[kp(k) * sz + col], Rp = d.rho[kp(k) * sz + col];
     double U = d.u[k * sz + col], V = d.v[k * sz + col], W = d.w[k * sz + col];
-    double h0 = hv0 ? H.fp[0][k * sz + H.off[0]] : 0.0, h1 = hv1 ? H.fp[1][k * sz + H.off[1]] : 0.0;
+    double h0 = H.fp[0][k * sz + H.off[0]], h1 = H.fp[1][k * sz + H.off[1]];
     double Fb = 0.0, Wb = 0.0; // flux of (1 - rho0/rho) G p* and w* on face k - 1/2
     if (!(d.bcz == BC_WALL && k == 0)) {
         const int km = (k == 0) ? nz - 1 : k - 1;
@@ -170,16 +187,11 @@ __device__ __forceinline__ void pass_rhs(const Dom &d, int tile, char *smem)
     }
     double amax = 0.0;
     for (; k < t.ke; ++k) {
-        // prefetch plane k+1
-        const bool more = k + 1 < t.ke;
-        double P2 = 0.0, R2 = 0.0, U1 = 0.0, V1 = 0.0, W1 = 0.0, g0 = 0.0, g1 = 0.0;
-        if (more) {
-            const int k1 = k + 1, k2 = kp(k1);
-            P2 = d.ps[k2 * sz + col]; R2 = d.rho[k2 * sz + col];
-            U1 = d.u[k1 * sz + col]; V1 = d.v[k1 * sz + col]; W1 = d.w[k1 * sz + col];
-            if (hv0) g0 = H.fp[0][k1 * sz + H.off[0]];
-            if (hv1) g1 = H.fp[1][k1 * sz + H.off[1]];
-        }
+        // prefetch plane k+1 (no load is under a branch; see march_next)
+        const int k1 = march_next(k, t), k2 = kp(k1);
+        const double P2 = d.ps[k2 * sz + col], R2 = d.rho[k2 * sz + col];
+        const double U1 = d.u[k1 * sz + col], V1 = d.v[k1 * sz + col], W1 = d.w[k1 * sz + col];
+        const double g0 = H.fp[0][k1 * sz + H.off[0]], g1 = H.fp[1][k1 * sz + H.off[1]];
         const int c = k * sz + col;
         const bool wt = d.bcz == BC_WALL && k == nz - 1;
         sP[me] = Pc; sR[me] = Rc; sU[me] = U; sV[me] = V;
@@ -200,11 +212,11 @@ __device__ __forceinline__ void pass_rhs(const Dom &d, int tile, char *smem)
         const double Fw = n.ww ? 0.0 : (1.0 - tr0 * rcp_nr(Rw + Rc)) * (Pc - Pw);
         const double Fn = n.wn ? 0.0 : (1.0 - tr0 * rcp_nr(Rc + Rn)) * (Pn - Pc);
         const double Fs = n.ws ? 0.0 : (1.0 - tr0 * rcp_nr(Rs + Rc)) * (Pc - Ps);
-        const double Ft = wt ? 0.0 : (1.0 - rr0 * rcp_nr(Rc * d.rzlo[k] + Rp * d.rzhi[k])) * (Pp - Pc) * d.idzc[k];
+        const double Ft = wt ? 0.0 : (1.0 - rr0 * rcp_nr(Rc * ztab(d.rzlo, k) + Rp * ztab(d.rzhi, k))) * (Pp - Pc) * ztab(d.idzc, k);
         const double ue = n.we ? 0.0 : U, uwf = n.ww ? 0.0 : uw;
         const double vn = n.wn ? 0.0 : V, vsf = n.ws ? 0.0 : vs;
         const double wt_ = wt ? 0.0 : W;
-        const double idzf = d.idzf[k];
+        const double idzf = ztab(d.idzf, k);
         const double f = cdiv * ((ue - uwf) * d.idx + (vn - vsf) * d.idy + (wt_ - Wb) * idzf) + (Fe - Fw) * idx2 +
                          (Fn - Fs) * idy2 + (Ft - Fb) * idzf;
         if (t.act) {
@@ -261,7 +273,7 @@ __device__ __forceinline__ void pass_resid(const Dom &d, int tile, char *smem, i
     auto kp = [&](int k) { return k == nz - 1 ? 0 : k + 1; };
     int k = t.kb;
     double Pc = d.po[k * sz + col], Pp = d.po[kp(k) * sz + col], F = d.f[k * sz + col];
-    double hc = hv ? d.po[k * sz + hoff] : 0.0;
+    double hc = d.po[k * sz + hoff];
     double Gb = 0.0;
     if (!(d.bcz == BC_WALL && k == 0)) {
         const int km = (k == 0) ? nz - 1 : k - 1;
@@ -269,14 +281,8 @@ __device__ __forceinline__ void pass_resid(const Dom &d, int tile, char *smem, i
     }
     double amax = 0.0;
     for (; k < t.ke; ++k) {
-        const bool more = k + 1 < t.ke;
-        double P2 = 0.0, F1 = 0.0, hn = 0.0;
-        if (more) {
-            const int k1 = k + 1;
-            P2 = d.po[kp(k1) * sz + col];
-            F1 = d.f[k1 * sz + col];
-            if (hv) hn = d.po[k1 * sz + hoff];
-        }
+        const int k1 = march_next(k, t);
+        const double P2 = d.po[kp(k1) * sz + col], F1 = d.f[k1 * sz + col], hn = d.po[k1 * sz + hoff];
         const int c = k * sz + col;
         const bool wt = d.bcz == BC_WALL && k == nz - 1;
         sP[me] = Pc;
@@ -289,8 +295,8 @@ __device__ __forceinline__ void pass_resid(const Dom &d, int tile, char *smem, i
         __syncthreads();
         const double ge = n.we ? 0.0 : Pe - Pc, gw = n.ww ? 0.0 : Pc - Pw;
         const double gn = n.wn ? 0.0 : Pn - Pc, gs = n.ws ? 0.0 : Pc - Ps;
-        const double Gt = wt ? 0.0 : (Pp - Pc) * d.idzc[k];
-        const double r = F - ((ge - gw) * idx2 + (gn - gs) * idy2 + (Gt - Gb) * d.idzf[k]);
+        const double Gt = wt ? 0.0 : (Pp - Pc) * ztab(d.idzc, k);
+        const double r = F - ((ge - gw) * idx2 + (gn - gs) * idy2 + (Gt - Gb) * ztab(d.idzf, k));
         if (t.act) {
             d.r[c] = r;
             amax = amax_nan(amax, r);
@@ -386,21 +392,16 @@ __device__ __forceinline__ void pass_corr(const Dom &d, int tile, char *smem, bo
     double P0 = d.po[k * sz + col], S0 = d.ps[k * sz + col], R0 = d.rho[k * sz + col];
     double P1 = d.po[kp(k) * sz + col], S1 = d.ps[kp(k) * sz + col], R1 = d.rho[kp(k) * sz + col];
     double U = d.u[k * sz + col], V = d.v[k * sz + col], W = d.w[k * sz + col];
-    double h0 = hv0 ? H.fp[0][k * sz + H.off[0]] : 0.0, h1 = hv1 ? H.fp[1][k * sz + H.off[1]] : 0.0;
+    double h0 = H.fp[0][k * sz + H.off[0]], h1 = H.fp[1][k * sz + H.off[1]];
     double fb = 0.0;
     if (divcheck && !(d.bcz == BC_WALL && k == 0)) fb = corr_face(d, 2, t.i, t.j, (k == 0) ? nz - 1 : k - 1);
     double dmax = 0.0, omax = 0.0;
     for (; k < t.ke; ++k) {
-        // prefetch plane k+1
-        const bool more = k + 1 < t.ke;
-        double P2 = 0.0, S2 = 0.0, R2 = 0.0, U1 = 0.0, V1 = 0.0, W1 = 0.0, g0 = 0.0, g1 = 0.0;
-        if (more) {
-            const int k1 = k + 1, k2 = kp(k1);
-            P2 = d.po[k2 * sz + col]; S2 = d.ps[k2 * sz + col]; R2 = d.rho[k2 * sz + col];
-            U1 = d.u[k1 * sz + col]; V1 = d.v[k1 * sz + col]; W1 = d.w[k1 * sz + col];
-            if (hv0) g0 = H.fp[0][k1 * sz + H.off[0]];
-            if (hv1) g1 = H.fp[1][k1 * sz + H.off[1]];
-        }
+        // prefetch plane k+1 (no load is under a branch; see march_next)
+        const int k1 = march_next(k, t), k2 = kp(k1);
+        const double P2 = d.po[k2 * sz + col], S2 = d.ps[k2 * sz + col], R2 = d.rho[k2 * sz + col];
+        const double U1 = d.u[k1 * sz + col], V1 = d.v[k1 * sz + col], W1 = d.w[k1 * sz + col];
+        const double g0 = H.fp[0][k1 * sz + H.off[0]], g1 = H.fp[1][k1 * sz + H.off[1]];
         const int c = k * sz + col;
         const bool wt = d.bcz == BC_WALL && k == nz - 1;
         sP[me] = P0; sS[me] = S0; sR[me] = R0;
@@ -414,8 +415,8 @@ __device__ __forceinline__ void pass_corr(const Dom &d, int tile, char *smem, bo
         else { const double *n3 = hal + t.ti; Pn = n3[0]; Sn = n3[TI]; Rn = n3[2 * TI]; }
         const double fe = n.we ? 0.0 : U - dt * (ir0 * (Pe - P0) * d.idx + (2.0 * rcp_nr(R0 + Re) - ir0) * (Se - S0) * d.idx);
         const double fn = n.wn ? 0.0 : V - dt * (ir0 * (Pn - P0) * d.idy + (2.0 * rcp_nr(R0 + Rn) - ir0) * (Sn - S0) * d.idy);
-        const double hz = d.idzc[k];
-        const double ft = wt ? 0.0 : W - dt * (ir0 * (P1 - P0) * hz + (rcp_nr(R0 * d.rzlo[k] + R1 * d.rzhi[k]) - ir0) * (S1 - S0) * hz);
+        const double hz = ztab(d.idzc, k);
+        const double ft = wt ? 0.0 : W - dt * (ir0 * (P1 - P0) * hz + (rcp_nr(R0 * ztab(d.rzlo, k) + R1 * ztab(d.rzhi, k)) - ir0) * (S1 - S0) * hz);
         if (t.act) {
             d.uo[c] = fe;
             d.vo[c] = fn;
@@ -442,7 +443,7 @@ __device__ __forceinline__ void pass_corr(const Dom &d, int tile, char *smem, bo
         if (divcheck) {
             if (t.ti > 0) fw = sE[me - 1];
             if (t.tj > 0) fs = sF[me - TI];
-            const double dv = (fe - fw) * d.idx + (fn - fs) * d.idy + (ft - fb) * d.idzf[k];
+            const double dv = (fe - fw) * d.idx + (fn - fs) * d.idy + (ft - fb) * ztab(d.idzf, k);
             if (t.act) dmax = amax_nan(dmax, dv);
             fb = ft;
         }
@@ -493,7 +494,8 @@ __device__ __forceinline__ void pass_xfwd(const Dom &d, int tile, char *smem)
     const int rows = min(d.tj, d.ny - j0);
     const int nx = d.nx, M = d.M, half = M / 2;
     const double *src = (SRC == SRC_RHS ? d.f : d.r) + ((size_t)k * d.ny + j0) * nx;
-    stage_twiddles<T, NTH>(ltw, d.fx);
+    TwStage<T, NTH> tws;
+    tws.fetch(d.fx);
     const bool wx = d.bcx == BC_WALL;
     const int hx = nx >> 1;
     const double2 *src2 = (const double2 *)src;
@@ -548,6 +550,7 @@ __device__ __forceinline__ void pass_xfwd(const Dom &d, int tile, char *smem)
             staged_copy_t<64, 8, double2>(
                 lane, hx, [&](int h) { return sr[h]; }, [&](int h, double2 s) { put_pair(row, h, s); });
         }
+        tws.put(ltw, d.fx);
         __syncthreads(); // the twiddles
         if (wid < rows) {
             C *row = buf + wid * ldr;
@@ -566,6 +569,7 @@ __device__ __forceinline__ void pass_xfwd(const Dom &d, int tile, char *smem)
                 int r = (int)fdiv((uint32_t)e, d.dM);
                 put_pair(buf + r * ldr, e - r * hx, s);
             });
+        tws.put(ltw, d.fx);
         __syncthreads();
         lds_fft<T, false, NTH>(buf, ldr, rows, d.fx, ltw);
         for (int idx = threadIdx.x; idx < rows * (half + 1); idx += NTH) {
@@ -619,7 +623,8 @@ __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
     const int kt = tile % ntk, l = tile / ntk;
     const int k0 = kt * tk;
     const int cols = min(tk, nz - k0);
-    stage_twiddles<T, NTH>(ltw, d.fy);
+    TwStage<T, NTH> tws;
+    tws.fetch(d.fy);
     // one wave per column when the tile has at most one column per wave and
     // the length has the fixed wave plan (which must be the descriptor's)
     constexpr int NW = NTH / 64;
@@ -676,6 +681,7 @@ __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
             }
         }
     }
+    tws.put(ltw, d.fy);
     __syncthreads();
     if (wv) {
         if (wid < cols) {
@@ -969,7 +975,8 @@ __device__ __forceinline__ void pass_xinv(const Dom &d, int tile, char *smem, in
     const int ldr = lds_line(d.nl);
     C *ltw = buf + d.tj * ldr;
     double *red = (double *)(ltw + tw_half(d.fx.n));
-    stage_twiddles<T, NTH>(ltw, d.fx);
+    TwStage<T, NTH> tws;
+    tws.fetch(d.fx);
     const int jt = tile % d.ntj, k = tile / d.ntj;
     const int j0 = jt * d.tj;
     const int rows = min(d.tj, d.ny - j0);
@@ -1009,6 +1016,7 @@ __device__ __forceinline__ void pass_xinv(const Dom &d, int tile, char *smem, in
             oldv[q] = e < npair ? po2[e] : double2{0.0, 0.0};
         }
     }
+    tws.put(ltw, d.fx);
     __syncthreads();
     const bool wx = d.bcx == BC_WALL;
     const C *wd = (const C *)d.dctx;
