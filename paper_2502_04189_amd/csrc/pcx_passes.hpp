@@ -13,6 +13,8 @@
 //   corr   : velocity correction with the divergence check (k-marching)
 #pragma once
 
+#include <type_traits>
+
 #include "pcx_dev.hpp"
 
 namespace pcx {
@@ -809,155 +811,168 @@ __device__ __forceinline__ void pass_z(const Dom &d, int tile, char *smem)
     const int gls = active ? gl : wl0;
     const long q = q0 + gls;
     const int l = (int)(q / d.ny), m = (int)(q - (long)l * d.ny);
-    const bool sing = (l == 0 && m == 0);
-    const bool cyc = (d.bcz == BC_PER) && !sing;
+    const bool sing_line = (l == 0 && m == 0);
     const T *za = (const T *)d.za, *zb = (const T *)d.zb, *zc = (const T *)d.zc, *dzf = (const T *)d.dzf_s;
     const T sh = ((const T *)d.lamx)[l] + ((const T *)d.lamy)[m];
     const T scale = (T)d.scale;
     const int base = nz / G, rem = nz - base * G;
-    const int S = base + (t < rem ? 1 : 0);
-    const int k0 = t * base + min(t, rem);
-    const int mi = S - 1;                        // interior rows
     const int lbase = lane & ~(G - 1);
-
-    C y[SMAX];
-    T g[SMAX], cp[SMAX];
+    // The solve body, FULL: every lane holds SMAX levels and no line of the
+    // wave is the singular mode (all but one wave of the grid), so the
+    // per-level guards and the singular-mode steps fold away at compile
+    // time; CY: 1 periodic, 2 not, 0 decided at run time.
+    auto solve = [&](auto full_tag, auto cy_tag) {
+        constexpr bool FULL = decltype(full_tag)::value;
+        constexpr int CY = decltype(cy_tag)::value;
+        const bool sing = FULL ? false : sing_line;
+        const bool cyc = CY == 1 ? true : (CY == 2 ? false : (d.bcz == BC_PER) && !sing);
+        const int S = FULL ? SMAX : base + (t < rem ? 1 : 0);
+        const int k0 = FULL ? t * SMAX : t * base + min(t, rem);
+        const int mi = S - 1;                        // interior rows
+        C y[SMAX];
+        T g[SMAX], cp[SMAX];
 #pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-        if (s < S) {
-            C v = buf[ZP(gls * nz + k0 + s)];
-            y[s] = C{v.x * scale, v.y * scale};
+        for (int s = 0; s < SMAX; ++s) {
+            if (s < S) {
+                C v = buf[ZP(gls * nz + k0 + s)];
+                y[s] = C{v.x * scale, v.y * scale};
+            }
         }
-    }
-    // compatibility of the singular mode: remove the dzf-weighted mean
-    if (sing) {
-        C acc = {T(0), T(0)};
-#pragma unroll
-        for (int s = 0; s < SMAX; ++s)
-            if (s < S) { T w = dzf[k0 + s]; acc.x += w * y[s].x; acc.y += w * y[s].y; }
-        for (int o = 1; o < G; o <<= 1) { acc.x += __shfl_xor(acc.x, o, 64); acc.y += __shfl_xor(acc.y, o, 64); }
-        T il = T(1) / (T)d.lz;
-#pragma unroll
-        for (int s = 0; s < SMAX; ++s)
-            if (s < S) { y[s].x -= acc.x * il; y[s].y -= acc.y * il; }
-        // the pinned level nz-1 is the identity row x = 0
-#pragma unroll
-        for (int s = 0; s < SMAX; ++s)
-            if (s < S && k0 + s == nz - 1) y[s] = C{T(0), T(0)};
-    }
-    // row coefficients (pinned system for the singular mode)
-    auto coef = [&](int k, T &A, T &B, T &Cc) {
-        A = za[k]; Cc = zc[k]; B = zb[k] + sh;
+        // compatibility of the singular mode: remove the dzf-weighted mean
         if (sing) {
-            if (k == nz - 1) { A = T(0); Cc = T(0); B = T(1); }
-            if (k == nz - 2) Cc = T(0);
-            if (k == 0) A = T(0);
+            C acc = {T(0), T(0)};
+#pragma unroll
+            for (int s = 0; s < SMAX; ++s)
+                if (s < S) { T w = dzf[k0 + s]; acc.x += w * y[s].x; acc.y += w * y[s].y; }
+            for (int o = 1; o < G; o <<= 1) { acc.x += __shfl_xor(acc.x, o, 64); acc.y += __shfl_xor(acc.y, o, 64); }
+            T il = T(1) / (T)d.lz;
+#pragma unroll
+            for (int s = 0; s < SMAX; ++s)
+                if (s < S) { y[s].x -= acc.x * il; y[s].y -= acc.y * il; }
+            // the pinned level nz-1 is the identity row x = 0
+#pragma unroll
+            for (int s = 0; s < SMAX; ++s)
+                if (s < S && k0 + s == nz - 1) y[s] = C{T(0), T(0)};
+        }
+        // row coefficients (pinned system for the singular mode)
+        auto coef = [&](int k, T &A, T &B, T &Cc) {
+            A = za[k]; Cc = zc[k]; B = zb[k] + sh;
+            if (sing) {
+                if (k == nz - 1) { A = T(0); Cc = T(0); B = T(1); }
+                if (k == nz - 2) Cc = T(0);
+                if (k == 0) A = T(0);
+            }
+        };
+        // local elimination of the interior rows k0 .. k0+mi-1
+        T hlast = T(0);
+        {
+            T cpp = T(0), gp = T(0);
+            C yp = {T(0), T(0)};
+#pragma unroll
+            for (int s = 0; s < SMAX - 1; ++s) {
+                if (s < mi) {
+                    T A, B, Cc;
+                    coef(k0 + s, A, B, Cc);
+                    T a = (s == 0) ? T(0) : A;
+                    T inv = rcp_t(B - a * cpp);
+                    cp[s] = Cc * inv;
+                    y[s] = C{(y[s].x - a * yp.x) * inv, (y[s].y - a * yp.y) * inv};
+                    g[s] = ((s == 0) ? -A : -a * gp) * inv;
+                    if (s == mi - 1) hlast = -Cc * inv;
+                    cpp = cp[s]; yp = y[s]; gp = g[s];
+                }
+            }
+        }
+        T h0 = hlast;
+#pragma unroll
+        for (int s = SMAX - 3; s >= 0; --s) {
+            if (s < mi - 1) {
+                y[s].x -= cp[s] * y[s + 1].x;
+                y[s].y -= cp[s] * y[s + 1].y;
+                g[s] -= cp[s] * g[s + 1];
+                h0 = -cp[s] * h0;
+            }
+        }
+        // E-row of this lane: row ke = k0 + mi
+        T Ae, Be, Ce;
+        coef(k0 + mi, Ae, Be, Ce);
+        C ye = y[0];
+        T gl_last = T(0), hl_last = hlast;
+        C yl_last = {T(0), T(0)};
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) {
+            if (s == mi) ye = y[s];
+            if (s == mi - 1) { yl_last = y[s]; gl_last = g[s]; }
+        }
+        // first interior unknown of the next lane (wraps for a cyclic line)
+        const int nxt = lbase | ((t + 1) & (G - 1));
+        C y0n = {__shfl(y[0].x, nxt, 64), __shfl(y[0].y, nxt, 64)};
+        T g0n = __shfl(g[0], nxt, 64);
+        T h0n = __shfl(h0, nxt, 64);
+        T al = Ae * gl_last;
+        T be = Be + Ae * hl_last + Ce * g0n;
+        T ga = Ce * h0n;
+        C rh = {ye.x - Ae * yl_last.x - Ce * y0n.x, ye.y - Ae * yl_last.y - Ce * y0n.y};
+        // parallel cyclic reduction over the G lanes of the line
+        for (int dd = 1; dd < G; dd <<= 1) {
+            int lo = t - dd, hi = t + dd;
+            bool vlo = cyc || lo >= 0, vhi = cyc || hi < G;
+            int slo = lbase | (lo & (G - 1)), shi = lbase | (hi & (G - 1));
+            T al_lo = __shfl(al, slo, 64), be_lo = __shfl(be, slo, 64), ga_lo = __shfl(ga, slo, 64);
+            T rx_lo = __shfl(rh.x, slo, 64), ry_lo = __shfl(rh.y, slo, 64);
+            T al_hi = __shfl(al, shi, 64), be_hi = __shfl(be, shi, 64), ga_hi = __shfl(ga, shi, 64);
+            T rx_hi = __shfl(rh.x, shi, 64), ry_hi = __shfl(rh.y, shi, 64);
+            if (!vlo) { al_lo = T(0); be_lo = T(1); ga_lo = T(0); rx_lo = T(0); ry_lo = T(0); }
+            if (!vhi) { al_hi = T(0); be_hi = T(1); ga_hi = T(0); rx_hi = T(0); ry_hi = T(0); }
+            T k1 = al * rcp_t(be_lo), k2 = ga * rcp_t(be_hi);
+            T nal = -k1 * al_lo, nga = -k2 * ga_hi;
+            T nbe = be - k1 * ga_lo - k2 * al_hi;
+            rh = C{rh.x - k1 * rx_lo - k2 * rx_hi, rh.y - k1 * ry_lo - k2 * ry_hi};
+            al = nal; be = nbe; ga = nga;
+        }
+        T den = cyc ? (al + be + ga) : be;
+        const T iden = rcp_t(den);
+        C E = {rh.x * iden, rh.y * iden};
+        const int prv = lbase | ((t - 1) & (G - 1));
+        C Ep = {__shfl(E.x, prv, 64), __shfl(E.y, prv, 64)};
+        // reconstruction x_s = y_s + g_s E_{t-1} + h_s E_t
+        {
+            T h = hlast;
+#pragma unroll
+            for (int s = SMAX - 2; s >= 0; --s) {
+                if (s < mi) {
+                    y[s] = C{y[s].x + g[s] * Ep.x + h * E.x, y[s].y + g[s] * Ep.y + h * E.y};
+                    if (s > 0) h = -cp[s - 1] * h;
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < SMAX; ++s)
+                if (s == mi) y[s] = E;
+        }
+        // gauge of the singular mode: zero dzf-weighted mean
+        if (sing) {
+            C acc = {T(0), T(0)};
+#pragma unroll
+            for (int s = 0; s < SMAX; ++s)
+                if (s < S) { T w = dzf[k0 + s]; acc.x += w * y[s].x; acc.y += w * y[s].y; }
+            for (int o = 1; o < G; o <<= 1) { acc.x += __shfl_xor(acc.x, o, 64); acc.y += __shfl_xor(acc.y, o, 64); }
+            T il = T(1) / (T)d.lz;
+#pragma unroll
+            for (int s = 0; s < SMAX; ++s)
+                if (s < S) { y[s].x -= acc.x * il; y[s].y -= acc.y * il; }
+        }
+        wave_sync();
+        if (active) {
+#pragma unroll
+            for (int s = 0; s < SMAX; ++s)
+                if (s < S) buf[ZP(gl * nz + k0 + s)] = y[s];
         }
     };
-    // local elimination of the interior rows k0 .. k0+mi-1
-    T hlast = T(0);
-    {
-        T cpp = T(0), gp = T(0);
-        C yp = {T(0), T(0)};
-#pragma unroll
-        for (int s = 0; s < SMAX - 1; ++s) {
-            if (s < mi) {
-                T A, B, Cc;
-                coef(k0 + s, A, B, Cc);
-                T a = (s == 0) ? T(0) : A;
-                T inv = rcp_t(B - a * cpp);
-                cp[s] = Cc * inv;
-                y[s] = C{(y[s].x - a * yp.x) * inv, (y[s].y - a * yp.y) * inv};
-                g[s] = ((s == 0) ? -A : -a * gp) * inv;
-                if (s == mi - 1) hlast = -Cc * inv;
-                cpp = cp[s]; yp = y[s]; gp = g[s];
-            }
-        }
-    }
-    T h0 = hlast;
-#pragma unroll
-    for (int s = SMAX - 3; s >= 0; --s) {
-        if (s < mi - 1) {
-            y[s].x -= cp[s] * y[s + 1].x;
-            y[s].y -= cp[s] * y[s + 1].y;
-            g[s] -= cp[s] * g[s + 1];
-            h0 = -cp[s] * h0;
-        }
-    }
-    // E-row of this lane: row ke = k0 + mi
-    T Ae, Be, Ce;
-    coef(k0 + mi, Ae, Be, Ce);
-    C ye = y[0];
-    T gl_last = T(0), hl_last = hlast;
-    C yl_last = {T(0), T(0)};
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-        if (s == mi) ye = y[s];
-        if (s == mi - 1) { yl_last = y[s]; gl_last = g[s]; }
-    }
-    // first interior unknown of the next lane (wraps for a cyclic line)
-    const int nxt = lbase | ((t + 1) & (G - 1));
-    C y0n = {__shfl(y[0].x, nxt, 64), __shfl(y[0].y, nxt, 64)};
-    T g0n = __shfl(g[0], nxt, 64);
-    T h0n = __shfl(h0, nxt, 64);
-    T al = Ae * gl_last;
-    T be = Be + Ae * hl_last + Ce * g0n;
-    T ga = Ce * h0n;
-    C rh = {ye.x - Ae * yl_last.x - Ce * y0n.x, ye.y - Ae * yl_last.y - Ce * y0n.y};
-    // parallel cyclic reduction over the G lanes of the line
-    for (int dd = 1; dd < G; dd <<= 1) {
-        int lo = t - dd, hi = t + dd;
-        bool vlo = cyc || lo >= 0, vhi = cyc || hi < G;
-        int slo = lbase | (lo & (G - 1)), shi = lbase | (hi & (G - 1));
-        T al_lo = __shfl(al, slo, 64), be_lo = __shfl(be, slo, 64), ga_lo = __shfl(ga, slo, 64);
-        T rx_lo = __shfl(rh.x, slo, 64), ry_lo = __shfl(rh.y, slo, 64);
-        T al_hi = __shfl(al, shi, 64), be_hi = __shfl(be, shi, 64), ga_hi = __shfl(ga, shi, 64);
-        T rx_hi = __shfl(rh.x, shi, 64), ry_hi = __shfl(rh.y, shi, 64);
-        if (!vlo) { al_lo = T(0); be_lo = T(1); ga_lo = T(0); rx_lo = T(0); ry_lo = T(0); }
-        if (!vhi) { al_hi = T(0); be_hi = T(1); ga_hi = T(0); rx_hi = T(0); ry_hi = T(0); }
-        T k1 = al * rcp_t(be_lo), k2 = ga * rcp_t(be_hi);
-        T nal = -k1 * al_lo, nga = -k2 * ga_hi;
-        T nbe = be - k1 * ga_lo - k2 * al_hi;
-        rh = C{rh.x - k1 * rx_lo - k2 * rx_hi, rh.y - k1 * ry_lo - k2 * ry_hi};
-        al = nal; be = nbe; ga = nga;
-    }
-    T den = cyc ? (al + be + ga) : be;
-    const T iden = rcp_t(den);
-    C E = {rh.x * iden, rh.y * iden};
-    const int prv = lbase | ((t - 1) & (G - 1));
-    C Ep = {__shfl(E.x, prv, 64), __shfl(E.y, prv, 64)};
-    // reconstruction x_s = y_s + g_s E_{t-1} + h_s E_t
-    {
-        T h = hlast;
-#pragma unroll
-        for (int s = SMAX - 2; s >= 0; --s) {
-            if (s < mi) {
-                y[s] = C{y[s].x + g[s] * Ep.x + h * E.x, y[s].y + g[s] * Ep.y + h * E.y};
-                if (s > 0) h = -cp[s - 1] * h;
-            }
-        }
-#pragma unroll
-        for (int s = 0; s < SMAX; ++s)
-            if (s == mi) y[s] = E;
-    }
-    // gauge of the singular mode: zero dzf-weighted mean
-    if (sing) {
-        C acc = {T(0), T(0)};
-#pragma unroll
-        for (int s = 0; s < SMAX; ++s)
-            if (s < S) { T w = dzf[k0 + s]; acc.x += w * y[s].x; acc.y += w * y[s].y; }
-        for (int o = 1; o < G; o <<= 1) { acc.x += __shfl_xor(acc.x, o, 64); acc.y += __shfl_xor(acc.y, o, 64); }
-        T il = T(1) / (T)d.lz;
-#pragma unroll
-        for (int s = 0; s < SMAX; ++s)
-            if (s < S) { y[s].x -= acc.x * il; y[s].y -= acc.y * il; }
-    }
-    wave_sync();
-    if (active) {
-#pragma unroll
-        for (int s = 0; s < SMAX; ++s)
-            if (s < S) buf[ZP(gl * nz + k0 + s)] = y[s];
-    }
+    using std::integral_constant;
+    const bool full = rem == 0 && base == SMAX && !__any(sing_line ? 1 : 0);
+    if (full && d.bcz == BC_PER) solve(integral_constant<bool, true>{}, integral_constant<int, 1>{});
+    else if (full) solve(integral_constant<bool, true>{}, integral_constant<int, 2>{});
+    else solve(integral_constant<bool, false>{}, integral_constant<int, 0>{});
     wave_sync();
     staged_copy_t<64, 8, C>(lane, wn, [&](int e) { return buf[ZP(wb + e)]; },
                             [&](int e, C v) { s2[gbase + wb + e] = v; });
