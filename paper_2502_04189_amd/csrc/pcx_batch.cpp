@@ -187,8 +187,8 @@ extern "C" pcx_status pcx_batch_create(const pcx_domain *domains, int32_t n, con
         off_s2[i] = take(nspec * csz);
         off_f[i] = take(ncell * 8);
         off_r[i] = B->prec == PREC_F32 ? take(ncell * 8) : 0;
-        off_pp[i] = B->prec == PREC_F32 ? take(((size_t)B->doms[i].ntj * B->grids[i].nz + 8) * 8) : 0;
-        off_xp[i] = take((size_t)2 * B->doms[i].ntj * B->grids[i].nz * 8);
+        off_pp[i] = B->prec == PREC_F32 ? take(((size_t)xslots(B->doms[i]) + PMEAN_LEN) * 8) : 0;
+        off_xp[i] = take((size_t)2 * xslots(B->doms[i]) * 8);
     }
     if (o.tune_cache && o.autotune) cache.save(o.tune_cache);
     if (hipMalloc(&B->ws, std::max<size_t>(total, 256)) != hipSuccess) { batch_free(B); return fail(PCX_ERR_NOMEM, "batch workspace allocation failed"); }
@@ -205,7 +205,7 @@ extern "C" pcx_status pcx_batch_create(const pcx_domain *domains, int32_t n, con
         d.f = (double *)((char *)B->ws + off_f[i]);
         d.r = B->prec == PREC_F32 ? (double *)((char *)B->ws + off_r[i]) : nullptr;
         d.ppart = B->prec == PREC_F32 ? (double *)((char *)B->ws + off_pp[i]) : nullptr;
-        d.pmean = d.ppart ? d.ppart + (size_t)d.ntj * B->grids[i].nz : nullptr;
+        d.pmean = d.ppart ? d.ppart + (size_t)xslots(d) : nullptr;
         d.xpart = (double *)((char *)B->ws + off_xp[i]);
         d.stats = B->stats + (size_t)i * NSTAT;
         d.dt = dm.dt; d.rho0 = dm.rho0; d.irho0 = 1.0 / dm.rho0;

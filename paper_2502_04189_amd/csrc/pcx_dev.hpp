@@ -90,10 +90,18 @@ struct Dom {
     double *r;                        // FP64 residual f - L p (refined form)
     void *s1, *s2;                    // spectral workspaces
     unsigned long long *stats;        // NSTAT slots
-    double *ppart;                    // per x-tile dzf-weighted sums of p
+    double *ppart;                    // per x-tile wave dzf-weighted sums of p
     double *pmean;                    // [0]: volume mean of p after the last xinv pass
-    double *xpart;                    // per x-tile max |update|, max |p| (NULL: atomics)
+    double *xpart;                    // per x-tile wave max |update|, max |p| (NULL: atomics)
 };
+
+// Partial-result slots of the x inverse: one per wave of each x tile.  They
+// are reduced by at most XMAX_WG workgroups, whose sums of p go to
+// pmean[8 ..]; pmean[0] is the mean (PMEAN_LEN doubles in all).
+constexpr int XMAX_WG = 64;
+constexpr int PMEAN_LEN = 8 + XMAX_WG;
+__host__ __device__ inline int xslots(const Dom &d) { return d.ntj * d.nz * (d.xth >> 6); }
+
 
 // ------------------------------------------------------------ complex math
 template <typename T> struct T2;
@@ -459,6 +467,39 @@ __device__ __forceinline__ void block_max2_to(unsigned long long *sa, double a, 
         if (sa) atomicMax(sa, (unsigned long long)__double_as_longlong(a));
         if (sb) atomicMax(sb, (unsigned long long)__double_as_longlong(b));
     }
+}
+
+// Wave-wide versions (no barrier; the result is valid in every lane): two
+// maxima with block_max2's NaN handling, and a sum in a fixed shuffle order.
+__device__ __forceinline__ void wave_max2(double &a, double &b)
+{
+    const double qnan = __longlong_as_double(0x7ff8000000000000LL);
+    if (a != a) a = qnan;
+    if (b != b) b = qnan;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        double x = __shfl_xor(a, o, 64), y = __shfl_xor(b, o, 64);
+        a = (x != x || x > a) ? x : a;
+        b = (y != y || y > b) ? y : b;
+    }
+}
+
+__device__ __forceinline__ double wave_max1(double a)
+{
+    if (a != a) a = __longlong_as_double(0x7ff8000000000000LL);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        double x = __shfl_xor(a, o, 64);
+        a = (x != x || x > a) ? x : a;
+    }
+    return a;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
 }
 
 // Deterministic block-wide sum (fixed shuffle tree, then waves in order);

@@ -389,19 +389,19 @@ extern "C" pcx_status pcx_plan_create(const pcx_grid *grid, const pcx_options *o
     if (hipMalloc(&P->s1, nspec * csz) != hipSuccess || hipMalloc(&P->s2, nspec * csz) != hipSuccess ||
         hipMalloc(&P->stats, NSTAT * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&P->psum, (size_t)grid->nz * sizeof(double)) != hipSuccess ||
-        hipMalloc(&P->xpart, (size_t)2 * P->dom.ntj * grid->nz * sizeof(double)) != hipSuccess) {
+        hipMalloc(&P->xpart, (size_t)2 * xslots(P->dom) * sizeof(double)) != hipSuccess) {
         plan_free(P);
         return fail(PCX_ERR_NOMEM, "workspace allocation failed");
     }
     if (hipMalloc(&P->f, ncell * sizeof(double)) != hipSuccess ||
         (P->prec == PREC_F32 &&
          (hipMalloc(&P->r, ncell * sizeof(double)) != hipSuccess ||
-          hipMalloc(&P->ppart, ((size_t)P->dom.ntj * grid->nz + 8) * sizeof(double)) != hipSuccess))) {
+          hipMalloc(&P->ppart, ((size_t)xslots(P->dom) + PMEAN_LEN) * sizeof(double)) != hipSuccess))) {
         plan_free(P);
         return fail(PCX_ERR_NOMEM, "workspace allocation failed (f, r)");
     }
     P->ws_bytes = 2 * nspec * csz + NSTAT * 8 + grid->nz * 8 + P->tables.bytes + ncell * 8 + (P->r ? ncell * 8 : 0) +
-                  (P->ppart ? ((size_t)P->dom.ntj * grid->nz + 8) * 8 : 0) + (size_t)2 * P->dom.ntj * grid->nz * 8;
+                  (P->ppart ? ((size_t)xslots(P->dom) + PMEAN_LEN) * 8 : 0) + (size_t)2 * xslots(P->dom) * 8;
     P->dom.s1 = P->s1;
     P->dom.s2 = P->s2;
     P->dom.f = P->f;
@@ -409,7 +409,7 @@ extern "C" pcx_status pcx_plan_create(const pcx_grid *grid, const pcx_options *o
     P->dom.stats = P->stats;
     P->dom.ppart = P->ppart;
     P->dom.xpart = P->xpart;
-    P->dom.pmean = P->ppart ? P->ppart + (size_t)P->dom.ntj * grid->nz : nullptr;
+    P->dom.pmean = P->ppart ? P->ppart + (size_t)xslots(P->dom) : nullptr;
     P->lx = lds_x(P->dom, P->prec);
     P->ly = lds_y(P->dom, P->prec);
     P->lzs = lds_z(P->dom, P->prec);

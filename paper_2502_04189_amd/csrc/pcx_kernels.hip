@@ -92,10 +92,9 @@ __global__ __launch_bounds__(NT) void k_xmax(Dom d, int solve)
     pass_xmax(d, solve, blockIdx.x, gridDim.x, (char *)red);
 }
 
-__global__ __launch_bounds__(NT) void k_pmean(Dom d)
+__global__ void k_pmean(Dom d, int nwg)
 {
-    __shared__ double red[NT / 64];
-    pass_pmean(d, (char *)red);
+    pass_pmean(d, nwg);
 }
 
 __global__ void k_zero(unsigned long long *p, int n)
@@ -254,15 +253,19 @@ hipError_t launch_corr(const Dom &d, bool divcheck, hipStream_t s)
     PCX_LAUNCH_B(k_corr, xcd_grid(d.mg[1].ntiles), MTC, 0, s, d, divcheck ? 1 : 0);
 }
 
+static int xmax_grid(const Dom &d)
+{
+    return std::max(1, std::min(XMAX_WG, (xslots(d) + 4 * NT - 1) / (4 * NT)));
+}
+
 hipError_t launch_xmax(const Dom &d, int solve, hipStream_t s)
 {
-    const int nt = d.ntj * d.nz;
-    PCX_LAUNCH(k_xmax, std::max(1, std::min(64, (nt + 4 * NT - 1) / (4 * NT))), 0, s, d, solve);
+    PCX_LAUNCH(k_xmax, xmax_grid(d), 0, s, d, solve);
 }
 
 hipError_t launch_pmean(const Dom &d, hipStream_t s)
 {
-    PCX_LAUNCH(k_pmean, 1, 0, s, d);
+    PCX_LAUNCH_B(k_pmean, 1, 64, 0, s, d, xmax_grid(d));
 }
 
 hipError_t launch_div(const Dom &d, hipStream_t s)
@@ -361,7 +364,7 @@ __global__ __launch_bounds__(NT) void k_persist(PersistArgs a)
             case PK_PMEAN:
                 pass_xmax(d, sv, 0, 1, smem);
                 __syncthreads();
-                if (d.ppart) pass_pmean(d, smem);
+                if (d.ppart) pass_pmean(d, 1);
                 break;
             default: pass_corr(d, tile, smem, true); break;
             }

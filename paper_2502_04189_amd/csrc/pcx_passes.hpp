@@ -1139,67 +1139,70 @@ __device__ __forceinline__ void pass_xinv(const Dom &d, int tile, char *smem, in
         }
     }
     if (MODE == XOUT_STORE) pmax = emax;
+    // per-wave partials, reduced by pass_xmax / pass_pmean (one atomic per
+    // statistic per launch, and no workgroup barrier at the end of a tile);
+    // the slot of wave wid of this tile (the launch has d.xth threads)
+    const int slot = tile * (d.xth >> 6) + wid;
     if (d.ppart) {
-        double ts = block_sum<NTH>(psum, red);
-        if (threadIdx.x == 0) d.ppart[tile] = ts * d.dzf[k];
+        const double ws = wave_sum(psum);
+        if (lane == 0) d.ppart[slot] = ws * d.dzf[k];
     }
     if (d.xpart) {
-        // per-tile maxima, reduced by pass_xmax: one atomic per slot per
-        // launch instead of one per tile
-        block_max2<NTH>(emax, pmax, red);
-        if (threadIdx.x == 0) {
-            d.xpart[2 * tile] = emax;
-            d.xpart[2 * tile + 1] = pmax;
+        if (MODE == XOUT_STORE) emax = pmax = wave_max1(emax);
+        else wave_max2(emax, pmax);
+        if (lane == 0) {
+            d.xpart[2 * slot] = emax;
+            d.xpart[2 * slot + 1] = pmax;
         }
     } else {
         block_max2_to<NTH>(d.stats + ST_SOLVE0 + 4 * solve + 1, emax, d.stats + ST_SOLVE0 + 4 * solve + 2, pmax, red);
     }
 }
 
-// Maxima of the x-inverse tiles' partials into the solve's statistics slots
-// (workgroup `wg` of `nwg` takes every nwg-th block of NT partials).
+// Maxima of the x-inverse partials into the solve's statistics slots and,
+// when the plan tracks the mean of p, their sum: workgroup `wg` of `nwg`
+// (nwg <= XMAX_WG) takes every nwg-th block of NT partials, sums them in a
+// fixed order and stores the sum in pmean[8 + wg].
 __device__ __forceinline__ void pass_xmax(const Dom &d, int solve, int wg, int nwg, char *smem)
 {
     double *red = (double *)smem;
-    const int nt = d.ntj * d.nz;
-    double a = 0.0, b = 0.0;
+    const int nt = xslots(d);
+    double a = 0.0, b = 0.0, s = 0.0;
     const double2 *xp = (const double2 *)d.xpart;
+    const double *pp = d.ppart ? d.ppart : d.xpart; // a valid address for the unused loads
     for (int q0 = wg * NT; q0 < nt; q0 += 8 * nwg * NT) {
         double2 v[8];
+        double w[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int q = q0 + u * nwg * NT + threadIdx.x;
-            v[u] = q < nt ? xp[q] : double2{0.0, 0.0};
+            const int q = min(q0 + u * nwg * NT + (int)threadIdx.x, nt - 1);
+            v[u] = xp[q];
+            w[u] = pp[q];
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
+            if (q0 + u * nwg * NT + (int)threadIdx.x >= nt) continue;
             a = (v[u].x != v[u].x || v[u].x > a) ? v[u].x : a;
             b = (v[u].y != v[u].y || v[u].y > b) ? v[u].y : b;
+            s += w[u];
         }
+    }
+    if (d.ppart) {
+        const double tot = block_sum(s, red);
+        if (threadIdx.x == 0) d.pmean[8 + wg] = tot;
+        __syncthreads(); // red is reused below
     }
     block_max2_to<NT>(d.stats + ST_SOLVE0 + 4 * solve + 1, a, d.stats + ST_SOLVE0 + 4 * solve + 2, b, red);
 }
 
-// Volume mean of p from the x-tile partial sums, summed in a fixed order by
-// one workgroup: pmean[0] = sum / (nx ny lz).
-__device__ __forceinline__ void pass_pmean(const Dom &d, char *smem)
+// Volume mean of p from the nwg workgroup sums of pass_xmax, added in a
+// fixed order by one thread: pmean[0] = sum / (nx ny lz).
+__device__ __forceinline__ void pass_pmean(const Dom &d, int nwg)
 {
-    double *red = (double *)smem;
-    const int nt = d.ntj * d.nz;
+    if (threadIdx.x != 0) return;
     double s = 0.0;
-    // eight loads in flight per thread; the additions keep one fixed order
-    for (int t0 = 0; t0 < nt; t0 += 8 * NT) {
-        double v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int t = t0 + u * NT + threadIdx.x;
-            v[u] = t < nt ? d.ppart[t] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) s += v[u];
-    }
-    double tot = block_sum(s, red);
-    if (threadIdx.x == 0) d.pmean[0] = tot / ((double)d.nx * (double)d.ny * d.lz);
+    for (int w = 0; w < nwg; ++w) s += d.pmean[8 + w];
+    d.pmean[0] = s / ((double)d.nx * (double)d.ny * d.lz);
 }
 
 } // namespace pcx

@@ -133,7 +133,9 @@ pcx_status autotune_class(const pcx_grid &g, int prec, hipStream_t s, TuneParams
     double *f = (double *)sc.alloc(ncell * 8);
     double *rr = (double *)sc.alloc(ncell * 8);
     unsigned long long *stats = (unsigned long long *)sc.alloc(NSTAT * 8);
-    double *ppart = (double *)sc.alloc(((size_t)g.ny * g.nz + 8) * 8);
+    // partial sums of the x inverse: at most one per wave of a 1024-thread
+    // workgroup per row, plus the mean
+    double *ppart = (double *)sc.alloc(((size_t)g.ny * g.nz * 16 + PMEAN_LEN) * 8);
     if (!s1 || !s2 || !f || !rr || !stats || !ppart) return fail(PCX_ERR_NOMEM, "autotune scratch allocation failed");
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(PCX_ERR_HIP, "hipEventCreate");
@@ -148,7 +150,7 @@ pcx_status autotune_class(const pcx_grid &g, int prec, hipStream_t s, TuneParams
         d.uo = fld[5]; d.vo = fld[6]; d.wo = fld[7]; d.po = fld[8];
         d.f = f; d.r = rr; d.s1 = s1; d.s2 = s2; d.stats = stats;
         d.ppart = prec == PREC_F32 ? ppart : nullptr;
-        d.pmean = prec == PREC_F32 ? ppart + (size_t)d.ntj * g.nz : nullptr;
+        d.pmean = prec == PREC_F32 ? ppart + (size_t)xslots(d) : nullptr;
         lx = lds_x(d, prec); ly = lds_y(d, prec); lz = lds_z(d, prec); smax = sh.smax;
         return PCX_OK;
     };
