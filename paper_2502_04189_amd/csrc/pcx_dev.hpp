@@ -469,37 +469,50 @@ __device__ __forceinline__ void block_max2_to(unsigned long long *sa, double a, 
     }
 }
 
-// Wave-wide versions (no barrier; the result is valid in every lane): two
-// maxima with block_max2's NaN handling, and a sum in a fixed shuffle order.
-__device__ __forceinline__ void wave_max2(double &a, double &b)
+// Wave-wide reductions by DPP lane moves (VALU operations, no LDS round
+// trips): xor 1 and xor 2 within quads, mirrors within 8 and 16 lanes, then
+// row 0 -> row 1, row 2 -> row 3 and row 1 -> rows 2, 3 broadcasts.  The
+// result is complete in lane 63 only (wave_last reads it); the combination
+// order is fixed, so sums are deterministic.  A lane a move does not write
+// keeps its own value.
+template <int CTRL, int RM = 0xf>
+__device__ __forceinline__ double dpp_d(double v)
 {
-    const double qnan = __longlong_as_double(0x7ff8000000000000LL);
-    if (a != a) a = qnan;
-    if (b != b) b = qnan;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        double x = __shfl_xor(a, o, 64), y = __shfl_xor(b, o, 64);
-        a = (x != x || x > a) ? x : a;
-        b = (y != y || y > b) ? y : b;
-    }
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int l2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, RM, 0xf, false);
+    const int h2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, RM, 0xf, false);
+    return __hiloint2double(h2, l2);
 }
 
+template <typename Op>
+__device__ __forceinline__ double wave_reduce(double v, Op op)
+{
+    v = op(v, dpp_d<0xB1>(v));       // quad_perm [1,0,3,2]
+    v = op(v, dpp_d<0x4E>(v));       // quad_perm [2,3,0,1]
+    v = op(v, dpp_d<0x141>(v));      // row_half_mirror
+    v = op(v, dpp_d<0x140>(v));      // row_mirror
+    v = op(v, dpp_d<0x142, 0xA>(v)); // row_bcast:15
+    v = op(v, dpp_d<0x143, 0xC>(v)); // row_bcast:31
+    return v;
+}
+
+// value of lane 63, in every lane
+__device__ __forceinline__ double wave_last(double v)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                            __builtin_amdgcn_readlane(__double2loint(v), 63));
+}
+
+// max of non-negative values, NaN propagating (as block_max2)
 __device__ __forceinline__ double wave_max1(double a)
 {
     if (a != a) a = __longlong_as_double(0x7ff8000000000000LL);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        double x = __shfl_xor(a, o, 64);
-        a = (x != x || x > a) ? x : a;
-    }
-    return a;
+    return wave_last(wave_reduce(a, [](double x, double y) { return (y != y || y > x) ? y : x; }));
 }
 
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    return wave_last(wave_reduce(v, [](double x, double y) { return x + y; }));
 }
 
 // Deterministic block-wide sum (fixed shuffle tree, then waves in order);

@@ -1148,8 +1148,8 @@ __device__ __forceinline__ void pass_xinv(const Dom &d, int tile, char *smem, in
         if (lane == 0) d.ppart[slot] = ws * d.dzf[k];
     }
     if (d.xpart) {
-        if (MODE == XOUT_STORE) emax = pmax = wave_max1(emax);
-        else wave_max2(emax, pmax);
+        emax = wave_max1(emax);
+        pmax = MODE == XOUT_STORE ? emax : wave_max1(pmax);
         if (lane == 0) {
             d.xpart[2 * slot] = emax;
             d.xpart[2 * slot + 1] = pmax;

@@ -86,6 +86,9 @@ def test_small_fp64(pcx, orc, dims, bc, stretch):
     _say(f"errors {e} div {rep['max_div_rel']:.3e}")
     assert max(e.values()) <= FP64_TOL
     assert rep["max_div_rel"] <= FP64_TOL
+    # the FP64 solve stores p itself as the update: the wave and workgroup
+    # maxima of the x inverse must give max |p| exactly
+    assert rep["last_update_inf"] == np.abs(got[3]).max()
 
 
 @pytest.mark.parametrize("dims,bc,stretch", [((32, 32, 32), (0, 0, 1), 0.0), ((48, 36, 20), (0, 0, 1), 1.8),
