@@ -109,6 +109,22 @@ template <> struct T2<double> { using type = double2; };
 template <> struct T2<float> { using type = float2; };
 template <typename T> using c2 = typename T2<T>::type;
 
+// Store of a streamed output (written once, not read again by the pass that
+// writes it): non-temporal, so it does not displace lines still being read.
+__device__ __forceinline__ void st_stream(double *p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_stream(double2 *p, double2 v)
+{
+    typedef double v2d __attribute__((ext_vector_type(2)));
+    v2d w = {v.x, v.y};
+    __builtin_nontemporal_store(w, (v2d *)p);
+}
+__device__ __forceinline__ void st_stream(float2 *p, float2 v)
+{
+    typedef float v2f __attribute__((ext_vector_type(2)));
+    v2f w = {v.x, v.y};
+    __builtin_nontemporal_store(w, (v2f *)p);
+}
+
 template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return {a.x + b.x, a.y + b.y}; }
 template <typename C> __device__ __forceinline__ C csub(C a, C b) { return {a.x - b.x, a.y - b.y}; }
 template <typename C> __device__ __forceinline__ C cmul(C a, C b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }

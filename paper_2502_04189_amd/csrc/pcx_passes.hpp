@@ -222,7 +222,7 @@ __device__ __forceinline__ void pass_rhs(const Dom &d, int tile, char *smem)
         const double f = cdiv * ((ue - uwf) * d.idx + (vn - vsf) * d.idy + (wt_ - Wb) * idzf) + (Fe - Fw) * idx2 +
                          (Fn - Fs) * idy2 + (Ft - Fb) * idzf;
         if (t.act) {
-            d.f[c] = f;
+            st_stream(d.f + c, f);
             amax = amax_nan(amax, f);
         }
         Fb = Ft;
@@ -300,7 +300,7 @@ __device__ __forceinline__ void pass_resid(const Dom &d, int tile, char *smem, i
         const double Gt = wt ? 0.0 : (Pp - Pc) * ztab(d.idzc, k);
         const double r = F - ((ge - gw) * idx2 + (gn - gs) * idy2 + (Gt - Gb) * ztab(d.idzf, k));
         if (t.act) {
-            d.r[c] = r;
+            st_stream(d.r + c, r);
             amax = amax_nan(amax, r);
         }
         Gb = Gt;
@@ -420,9 +420,9 @@ __device__ __forceinline__ void pass_corr(const Dom &d, int tile, char *smem, bo
         const double hz = ztab(d.idzc, k);
         const double ft = wt ? 0.0 : W - dt * (ir0 * (P1 - P0) * hz + (rcp_nr(R0 * ztab(d.rzlo, k) + R1 * ztab(d.rzhi, k)) - ir0) * (S1 - S0) * hz);
         if (t.act) {
-            d.uo[c] = fe;
-            d.vo[c] = fn;
-            d.wo[c] = ft;
+            st_stream(d.uo + c, fe);
+            st_stream(d.vo + c, fn);
+            st_stream(d.wo + c, ft);
             omax = amax_nan(amax_nan(amax_nan(omax, fe), fn), ft);
         }
         // faces below and west of the tile, from the halo (before the halo is rewritten)
@@ -599,7 +599,7 @@ __device__ __forceinline__ void pass_xfwd(const Dom &d, int tile, char *smem)
         [&](int e, C v) {
             int l = (int)fdiv((uint32_t)e, d.dtj);
             int r = e - l * tj;
-            if (r < rows) s1[((size_t)k * nl + l) * d.ny + j0 + r] = v;
+            if (r < rows) st_stream(s1 + ((size_t)k * nl + l) * d.ny + j0 + r, v);
         });
 }
 
@@ -717,7 +717,7 @@ __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
                 // the column goes back to S1 by its own wave
                 wave_sync();
                 C *dst = s1 + ((size_t)(k0 + wid) * nl + l) * ny;
-                for (int j = lane; j < ny; j += 64) dst[j] = col[pidx(pos(j))];
+                for (int j = lane; j < ny; j += 64) st_stream(dst + j, col[pidx(pos(j))]);
             }
         }
         if (INV) return;
@@ -750,7 +750,7 @@ __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
             },
             [&](int e, C v) {
                 const int m = (int)fdiv((uint32_t)e, dtk), c = e - m * tk;
-                if (c < cols) s2[((size_t)l * ny + m) * nz + k0 + c] = v;
+                if (c < cols) st_stream(s2 + ((size_t)l * ny + m) * nz + k0 + c, v);
             });
     } else {
         staged_copy<NTH, 8, C>(
@@ -761,7 +761,7 @@ __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
             },
             [&](int e, C v) {
                 const int c = (int)fdiv((uint32_t)e, d.dnyc), j = e - c * ny;
-                s1[((size_t)(k0 + c) * nl + l) * ny + j] = v;
+                st_stream(s1 + ((size_t)(k0 + c) * nl + l) * ny + j, v);
             });
     }
 }
@@ -975,7 +975,7 @@ __device__ __forceinline__ void pass_z(const Dom &d, int tile, char *smem)
     else solve(integral_constant<bool, false>{}, integral_constant<int, 0>{});
     wave_sync();
     staged_copy_t<64, 8, C>(lane, wn, [&](int e) { return buf[ZP(wb + e)]; },
-                            [&](int e, C v) { s2[gbase + wb + e] = v; });
+                            [&](int e, C v) { st_stream(s2 + gbase + wb + e, v); });
 #undef ZP
 }
 
@@ -1081,7 +1081,7 @@ __device__ __forceinline__ void pass_xinv(const Dom &d, int tile, char *smem, in
     };
     auto emit = [&](int e, double2 val, double2 old) {
         double2 pv = (MODE == XOUT_STORE) ? val : double2{(old.x - shift) + val.x, (old.y - shift) + val.y};
-        po2[e] = pv;
+        st_stream(po2 + e, pv);
         psum += pv.x + pv.y;
         emax = amax_nan(amax_nan(emax, val.x), val.y);
         // a stored p is the update itself: its maximum is emax
