@@ -125,6 +125,22 @@ __device__ __forceinline__ void st_stream(float2 *p, float2 v)
     __builtin_nontemporal_store(w, (v2f *)p);
 }
 
+// Non-temporal load, for a streamed input no other tile of the pass reads
+// (inputs that neighbouring tiles re-read as halo stay cached normally).
+__device__ __forceinline__ double ld_stream(const double *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ double2 ld_stream(const double2 *p)
+{
+    typedef double v2d __attribute__((ext_vector_type(2)));
+    v2d w = __builtin_nontemporal_load((const v2d *)p);
+    return double2{w.x, w.y};
+}
+__device__ __forceinline__ float2 ld_stream(const float2 *p)
+{
+    typedef float v2f __attribute__((ext_vector_type(2)));
+    v2f w = __builtin_nontemporal_load((const v2f *)p);
+    return float2{w.x, w.y};
+}
+
 template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return {a.x + b.x, a.y + b.y}; }
 template <typename C> __device__ __forceinline__ C csub(C a, C b) { return {a.x - b.x, a.y - b.y}; }
 template <typename C> __device__ __forceinline__ C cmul(C a, C b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }

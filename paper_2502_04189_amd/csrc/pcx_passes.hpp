@@ -192,7 +192,7 @@ __device__ __forceinline__ void pass_rhs(const Dom &d, int tile, char *smem)
         // prefetch plane k+1 (no load is under a branch; see march_next)
         const int k1 = march_next(k, t), k2 = kp(k1);
         const double P2 = d.ps[k2 * sz + col], R2 = d.rho[k2 * sz + col];
-        const double U1 = d.u[k1 * sz + col], V1 = d.v[k1 * sz + col], W1 = d.w[k1 * sz + col];
+        const double U1 = d.u[k1 * sz + col], V1 = d.v[k1 * sz + col], W1 = ld_stream(d.w + k1 * sz + col);
         const double g0 = H.fp[0][k1 * sz + H.off[0]], g1 = H.fp[1][k1 * sz + H.off[1]];
         const int c = k * sz + col;
         const bool wt = d.bcz == BC_WALL && k == nz - 1;
@@ -284,7 +284,7 @@ __device__ __forceinline__ void pass_resid(const Dom &d, int tile, char *smem, i
     double amax = 0.0;
     for (; k < t.ke; ++k) {
         const int k1 = march_next(k, t);
-        const double P2 = d.po[kp(k1) * sz + col], F1 = d.f[k1 * sz + col], hn = d.po[k1 * sz + hoff];
+        const double P2 = d.po[kp(k1) * sz + col], F1 = ld_stream(d.f + k1 * sz + col), hn = d.po[k1 * sz + hoff];
         const int c = k * sz + col;
         const bool wt = d.bcz == BC_WALL && k == nz - 1;
         sP[me] = Pc;
@@ -402,7 +402,7 @@ __device__ __forceinline__ void pass_corr(const Dom &d, int tile, char *smem, bo
         // prefetch plane k+1 (no load is under a branch; see march_next)
         const int k1 = march_next(k, t), k2 = kp(k1);
         const double P2 = d.po[k2 * sz + col], S2 = d.ps[k2 * sz + col], R2 = d.rho[k2 * sz + col];
-        const double U1 = d.u[k1 * sz + col], V1 = d.v[k1 * sz + col], W1 = d.w[k1 * sz + col];
+        const double U1 = d.u[k1 * sz + col], V1 = d.v[k1 * sz + col], W1 = ld_stream(d.w + k1 * sz + col);
         const double g0 = H.fp[0][k1 * sz + H.off[0]], g1 = H.fp[1][k1 * sz + H.off[1]];
         const int c = k * sz + col;
         const bool wt = d.bcz == BC_WALL && k == nz - 1;
@@ -638,14 +638,14 @@ __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
             const C *src = s1 + ((size_t)(k0 + wid) * nl + l) * ny;
             C *col = buf + wid * ldc;
             staged_copy_t<64, 8, C>(
-                lane, ny, [&](int j) { return src[j]; }, [&](int j, C v) { col[pidx(pos(j))] = v; });
+                lane, ny, [&](int j) { return ld_stream(src + j); }, [&](int j, C v) { col[pidx(pos(j))] = v; });
         }
     } else if (!INV) {
         staged_copy<NTH, 8, C>(
             cols * ny,
             [&](int e) {
                 const int c = (int)fdiv((uint32_t)e, d.dnyc), j = e - c * ny;
-                return s1[((size_t)(k0 + c) * nl + l) * ny + j];
+                return ld_stream(s1 + ((size_t)(k0 + c) * nl + l) * ny + j);
             },
             [&](int e, C v) {
                 const int c = (int)fdiv((uint32_t)e, d.dnyc), j = e - c * ny;
@@ -656,7 +656,7 @@ __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
             tk * ny,
             [&](int e) {
                 const int m = (int)fdiv((uint32_t)e, dtk), c = e - m * tk;
-                return s2[((size_t)l * ny + m) * nz + k0 + min(c, cols - 1)];
+                return ld_stream(s2 + ((size_t)l * ny + m) * nz + k0 + min(c, cols - 1));
             },
             [&](int e, C v) {
                 const int m = (int)fdiv((uint32_t)e, dtk), c = e - m * tk;
