@@ -314,7 +314,7 @@ struct TwStage {
 };
 
 // ------------------------------------------------------ wave-level FFT
-// Lengths 256 and 512 (the default radix plans 8.8.4 and 8.8.8) can also be
+// Lengths 256 and 512 (plans 4.4.4.4 or 8.8.4, and 8.8.8; see wave_plan) can also be
 // transformed by one wave per line: butterfly j of a stage is lane j mod 64,
 // every index is a compile-time shift or mask, and no workgroup barrier is
 // needed between stages (the LDS operations of one wave execute in order;
@@ -373,11 +373,26 @@ __device__ __forceinline__ void wstage(c2<T> *ln, const c2<T> *tw, int lane)
 }
 
 // Whole line of length n (wave_len(n)) by the calling wave.
+// The plans the wave path has: 256 as 4.4.4.4 (every lane holds one
+// butterfly in every stage) or 8.8.4, 512 as 8.8.8.
+__host__ __device__ inline bool wave_plan(const FftDesc &fd)
+{
+    if (fd.n == 512) return fd.nst == 3 && fd.rad[0] == 8 && fd.rad[1] == 8 && fd.rad[2] == 8;
+    if (fd.n != 256) return false;
+    if (fd.nst == 4) return fd.rad[0] == 4 && fd.rad[1] == 4 && fd.rad[2] == 4 && fd.rad[3] == 4;
+    return fd.nst == 3 && fd.rad[0] == 8 && fd.rad[1] == 8 && fd.rad[2] == 4;
+}
+
 template <typename T, bool INV>
-__device__ __forceinline__ void wave_fft(c2<T> *ln, const c2<T> *tw, int n, int lane)
+__device__ __forceinline__ void wave_fft(c2<T> *ln, const c2<T> *tw, const FftDesc &fd, int lane)
 {
     wave_sync();
-    if (n == 256) {
+    if (fd.n == 256 && fd.nst == 4) {
+        wstage<T, INV, 256, 4, 1>(ln, tw, lane);
+        wstage<T, INV, 256, 4, 4>(ln, tw, lane);
+        wstage<T, INV, 256, 4, 16>(ln, tw, lane);
+        wstage<T, INV, 256, 4, 64>(ln, tw, lane);
+    } else if (fd.n == 256) {
         wstage<T, INV, 256, 8, 1>(ln, tw, lane);
         wstage<T, INV, 256, 8, 8>(ln, tw, lane);
         wstage<T, INV, 256, 4, 64>(ln, tw, lane);

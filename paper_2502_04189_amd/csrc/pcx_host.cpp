@@ -41,6 +41,10 @@ FastDiv mkdiv(uint32_t d)
 
 std::vector<int> default_radices(int n)
 {
+    // 256 as four radix-4 stages: the wave-level FFT then has one butterfly
+    // on every lane in every stage (8.8.4 leaves half the lanes idle in the
+    // radix-8 stages)
+    if (n == 256) return {4, 4, 4, 4};
     std::vector<int> r;
     int a = 0, b = 0;
     while (n % 2 == 0) { n /= 2; ++a; }

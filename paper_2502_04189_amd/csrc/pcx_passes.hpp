@@ -543,8 +543,7 @@ __device__ __forceinline__ void pass_xfwd(const Dom &d, int tile, char *smem)
     // half length has the fixed wave plan (which must be the descriptor's)
     constexpr int NW = NTH / 64;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const bool wv = WV && d.tj <= NW && wave_len(M) && d.fx.nst == 3 && d.fx.rad[0] == 8 && d.fx.rad[1] == 8 &&
-                    d.fx.rad[2] == (M == 512 ? 8 : 4);
+    const bool wv = WV && d.tj <= NW && wave_plan(d.fx);
     if (wv) {
         if (wid < rows) {
             C *row = buf + wid * ldr;
@@ -556,7 +555,7 @@ __device__ __forceinline__ void pass_xfwd(const Dom &d, int tile, char *smem)
         __syncthreads(); // the twiddles
         if (wid < rows) {
             C *row = buf + wid * ldr;
-            wave_fft<T, false>(row, ltw, M, lane);
+            wave_fft<T, false>(row, ltw, d.fx, lane);
             for (int l = lane; l <= half; l += 64) split(row, l);
             if (wx) {
                 wave_sync();
@@ -631,8 +630,7 @@ __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
     // the length has the fixed wave plan (which must be the descriptor's)
     constexpr int NW = NTH / 64;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const bool wv = WV && tk <= NW && wave_len(ny) && d.fy.nst == 3 && d.fy.rad[0] == 8 && d.fy.rad[1] == 8 &&
-                    d.fy.rad[2] == (ny == 512 ? 8 : 4);
+    const bool wv = WV && tk <= NW && wave_plan(d.fy);
     if (!INV && wv) {
         if (wid < cols) {
             const C *src = s1 + ((size_t)(k0 + wid) * nl + l) * ny;
@@ -703,7 +701,7 @@ __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
                     }
                 }
             }
-            wave_fft<T, INV>(col, ltw, ny, lane);
+            wave_fft<T, INV>(col, ltw, d.fy, lane);
             if (!INV && wy) {
                 for (int kk = 1 + lane; kk <= hy; kk += 64) {
                     const int kn = ny - kk;
@@ -1020,8 +1018,7 @@ __device__ __forceinline__ void pass_xinv(const Dom &d, int tile, char *smem, in
     // wave and the half length has the fixed wave plan
     constexpr int NW = NTH / 64;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const bool wv = WV && d.tj <= NW && wave_len(M) && d.fx.nst == 3 && d.fx.rad[0] == 8 && d.fx.rad[1] == 8 &&
-                    d.fx.rad[2] == (M == 512 ? 8 : 4) && (M >> 6) <= PF;
+    const bool wv = WV && d.tj <= NW && wave_plan(d.fx) && (M >> 6) <= PF;
     if (MODE == XOUT_ACCUM) {
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
@@ -1096,7 +1093,7 @@ __device__ __forceinline__ void pass_xinv(const Dom &d, int tile, char *smem, in
                 wave_sync();
             }
             for (int l = lane; l <= half; l += 64) c2r_pre(row, l);
-            wave_fft<T, true>(row, ltw, M, lane);
+            wave_fft<T, true>(row, ltw, d.fx, lane);
 #pragma unroll
             for (int q = 0; q < PF; ++q) {
                 const int h = lane + 64 * q;
