@@ -298,18 +298,22 @@ __device__ void lds_fft(c2<T> *buf, int ldb, int nlines, const FftDesc &fd, cons
 // of its tile's reads and store it after them (one memory latency instead of
 // two).  Roots beyond the first NTH are copied by put() directly.
 template <typename T, int NTH>
-struct TwStage {
+struct TabStage {
     c2<T> v;
-    __device__ __forceinline__ void fetch(const FftDesc &fd)
+    __device__ __forceinline__ void fetch(const c2<T> *tab, int n) { v = tab[min((int)threadIdx.x, n - 1)]; }
+    __device__ __forceinline__ void put(c2<T> *lds, const c2<T> *tab, int n) const
     {
-        v = ((const c2<T> *)fd.tw)[min((int)threadIdx.x, tw_half(fd.n) - 1)];
+        if ((int)threadIdx.x < n) lds[threadIdx.x] = v;
+        for (int e = threadIdx.x + NTH; e < n; e += NTH) lds[e] = tab[e];
     }
+};
+template <typename T, int NTH>
+struct TwStage {
+    TabStage<T, NTH> t;
+    __device__ __forceinline__ void fetch(const FftDesc &fd) { t.fetch((const c2<T> *)fd.tw, tw_half(fd.n)); }
     __device__ __forceinline__ void put(c2<T> *ltw, const FftDesc &fd) const
     {
-        const c2<T> *tw = (const c2<T> *)fd.tw;
-        const int th = tw_half(fd.n);
-        if ((int)threadIdx.x < th) ltw[threadIdx.x] = v;
-        for (int e = threadIdx.x + NTH; e < th; e += NTH) ltw[e] = tw[e];
+        t.put(ltw, (const c2<T> *)fd.tw, tw_half(fd.n));
     }
 };
 

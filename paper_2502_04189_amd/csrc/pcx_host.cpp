@@ -311,7 +311,8 @@ pcx_status build_domain(const pcx_grid &g, int prec, const Shapes &sh, const Rad
 
 size_t lds_x(const Dom &d, int prec)
 {
-    return ((size_t)d.tj * lds_line(d.nl) + tw_half(d.M)) * (prec == PREC_F64 ? 16 : 8) + 128;
+    // rows, FFT roots, split twiddles, then (x inverse) 16 reduction doubles
+    return ((size_t)d.tj * lds_line(d.nl) + tw_half(d.M) + d.M / 2 + 1) * (prec == PREC_F64 ? 16 : 8) + 128;
 }
 size_t lds_y(const Dom &d, int prec)
 {

@@ -496,12 +496,16 @@ __device__ __forceinline__ void pass_xfwd(const Dom &d, int tile, char *smem)
     const int rows = min(d.tj, d.ny - j0);
     const int nx = d.nx, M = d.M, half = M / 2;
     const double *src = (SRC == SRC_RHS ? d.f : d.r) + ((size_t)k * d.ny + j0) * nx;
+    // LDS: the tile's rows, the FFT roots, the split twiddles (M/2 + 1)
+    C *ltr = ltw + tw_half(d.fx.n);
     TwStage<T, NTH> tws;
+    TabStage<T, NTH> trs;
     tws.fetch(d.fx);
+    trs.fetch((const C *)d.twr, M / 2 + 1);
     const bool wx = d.bcx == BC_WALL;
     const int hx = nx >> 1;
     const double2 *src2 = (const double2 *)src;
-    const C *twr = (const C *)d.twr;
+    const C *twr = ltr;
     const C *wd = (const C *)d.dctx;
     // pairs (s[2h], s[2h+1]) form complex point h of the half-length FFT;
     // wall x: cosine transform by reordering v[h] = s[2h], v[N-1-h] = s[2h+1]
@@ -552,6 +556,7 @@ __device__ __forceinline__ void pass_xfwd(const Dom &d, int tile, char *smem)
                 lane, hx, [&](int h) { return sr[h]; }, [&](int h, double2 s) { put_pair(row, h, s); });
         }
         tws.put(ltw, d.fx);
+        trs.put(ltr, (const C *)d.twr, M / 2 + 1);
         __syncthreads(); // the twiddles
         if (wid < rows) {
             C *row = buf + wid * ldr;
@@ -571,6 +576,7 @@ __device__ __forceinline__ void pass_xfwd(const Dom &d, int tile, char *smem)
                 put_pair(buf + r * ldr, e - r * hx, s);
             });
         tws.put(ltw, d.fx);
+        trs.put(ltr, (const C *)d.twr, M / 2 + 1);
         __syncthreads();
         lds_fft<T, false, NTH>(buf, ldr, rows, d.fx, ltw);
         for (int idx = threadIdx.x; idx < rows * (half + 1); idx += NTH) {
@@ -986,10 +992,15 @@ __device__ __forceinline__ void pass_xinv(const Dom &d, int tile, char *smem, in
     using C = c2<T>;
     C *buf = (C *)smem;
     const int ldr = lds_line(d.nl);
+    // LDS: the tile's rows, the FFT roots, the split twiddles (M/2 + 1), the
+    // reduction slots
     C *ltw = buf + d.tj * ldr;
-    double *red = (double *)(ltw + tw_half(d.fx.n));
+    C *ltr = ltw + tw_half(d.fx.n);
+    double *red = (double *)(ltr + d.M / 2 + 1);
     TwStage<T, NTH> tws;
+    TabStage<T, NTH> trs;
     tws.fetch(d.fx);
+    trs.fetch((const C *)d.twr, d.M / 2 + 1);
     const int jt = tile % d.ntj, k = tile / d.ntj;
     const int j0 = jt * d.tj;
     const int rows = min(d.tj, d.ny - j0);
@@ -1029,10 +1040,11 @@ __device__ __forceinline__ void pass_xinv(const Dom &d, int tile, char *smem, in
         }
     }
     tws.put(ltw, d.fx);
+    trs.put(ltr, (const C *)d.twr, M / 2 + 1);
     __syncthreads();
     const bool wx = d.bcx == BC_WALL;
     const C *wd = (const C *)d.dctx;
-    const C *twr = (const C *)d.twr;
+    const C *twr = ltr;
     // inverse DCT-II: half spectrum of the reordered row,
     // V_k = conj(W_{4N}^k) (X_k - i X_{N-k}), X_N = 0, k in [0, M]
     auto dct_pre = [&](C *row, int kk) {
