@@ -721,7 +721,9 @@ __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
                 // the column goes back to S1 by its own wave
                 wave_sync();
                 C *dst = s1 + ((size_t)(k0 + wid) * nl + l) * ny;
-                for (int j = lane; j < ny; j += 64) st_stream(dst + j, col[pidx(pos(j))]);
+                // eight LDS reads in flight per lane, then the stores
+                staged_copy_t<64, 8, C>(
+                    lane, ny, [&](int j) { return col[pidx(pos(j))]; }, [&](int j, C v) { st_stream(dst + j, v); });
             }
         }
         if (INV) return;
