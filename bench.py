@@ -19,6 +19,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -166,8 +167,8 @@ def run_batch(steps, warmup, ndom):
         o = [torch.empty(c.grid.shape, dtype=torch.float64, device="cuda") for _ in range(4)]
         doms.append({"grid": c.grid, "dt": c.dt, "rho0": c.rho0, "rho": f[0], "pstar": f[1], "u": f[2],
                      "v": f[3], "w": f[4], "u_out": o[0], "v_out": o[1], "w_out": o[2], "p_out": o[3]})
-    cache = os.path.join(ROOT, "gpurun_out", "batch_tune_cache.txt") if os.path.isdir(
-        os.path.join(ROOT, "gpurun_out")) else None
+    # the tuned shapes of the batch's size classes, kept between runs on one machine
+    cache = os.path.join(tempfile.gettempdir(), "pcx_batch_tune_cache.txt")
     t0 = time.perf_counter()
     b = pcx.Batch(doms, "fp32_refined", autotune=True, tune_cache=cache)
     t_create = time.perf_counter() - t0

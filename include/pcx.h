@@ -45,7 +45,7 @@ extern "C" {
 typedef enum {
     PCX_OK = 0,
     PCX_ERR_INVALID = 1,       /* bad argument, descriptor, or aliasing      */
-    PCX_ERR_UNSUPPORTED = 2,   /* valid, but a size this build cannot run     */
+    PCX_ERR_UNSUPPORTED = 2,   /* valid, but a size the library does not run */
     PCX_ERR_NOMEM = 3,         /* device or host allocation failed            */
     PCX_ERR_HIP = 4,           /* HIP runtime failure, including "no device"  */
     PCX_ERR_NOT_CONVERGED = 5, /* refinement missed rtol; outputs written     */
