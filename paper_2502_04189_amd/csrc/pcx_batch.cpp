@@ -146,7 +146,7 @@ extern "C" pcx_status pcx_batch_create(const pcx_domain *domains, int32_t n, con
     addph(PK_RHS, 0);
     addph(PK_XFWD_RHS, 0);
     addph(PK_YF, 0); addph(PK_Z, 0); addph(PK_YI, 0); addph(PK_XINV_STORE, 0);
-    // after every x-inverse phase: the maxima of its tiles (and, refined, the
+    // after every x-inverse phase: the maxima of its wave partials (and, refined, the
     // volume mean of p), one workgroup per domain
     addph(PK_PMEAN, 0);
     for (int s = 1; s < B->solves; ++s) {

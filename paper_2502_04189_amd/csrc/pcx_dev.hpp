@@ -224,7 +224,7 @@ __host__ __device__ constexpr int tw_half(int n) { return (n & 1) ? n : n / 2; }
 //   twiddle W_{ns R}^{(j mod ns) r}
 //   outputs y[line][(j / ns) ns R + (j mod ns) + r ns]
 // Results are held in registers across a barrier, so the stage is in place.
-// Twiddles come from an LDS copy of the first th roots (see stage_twiddles).
+// Twiddles come from an LDS copy of the first th roots (see TwStage).
 template <typename T, bool INV, int R, int NTH>
 __device__ __forceinline__ void fft_stage(c2<T> *buf, int ldb, int nlines, const FftDesc &fd, int s,
                                           const c2<T> *tw, int th)
@@ -292,11 +292,12 @@ __device__ void lds_fft(c2<T> *buf, int ldb, int nlines, const FftDesc &fd, cons
     }
 }
 
-// Copies the first tw_half(n) roots of fd into LDS (no barrier: the caller's
-// next barrier publishes them), in two halves: fetch() reads this thread's
-// root into a register, put() stores it, so a pass can issue the read ahead
-// of its tile's reads and store it after them (one memory latency instead of
-// two).  Roots beyond the first NTH are copied by put() directly.
+// Copies a table of n complex values into LDS (no barrier: the caller's next
+// barrier publishes them), in two halves: fetch() reads this thread's entry
+// into a register, put() stores it, so a pass can issue the read ahead of its
+// tile's reads and store it after them (one memory latency instead of two).
+// Entries beyond the first NTH are copied by put() directly.  TwStage: the
+// first tw_half(n) roots of an FFT descriptor.
 template <typename T, int NTH>
 struct TabStage {
     c2<T> v;
@@ -447,13 +448,6 @@ __device__ __forceinline__ void staged_copy(int total, Get get, Put put)
 }
 
 // ------------------------------------------------------------- reductions
-__device__ __forceinline__ double wave_max(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
 // Block-wide max of non-negative values (NaN propagates), then one atomicMax
 // on the uint64 bit pattern (order-preserving for non-negative doubles).
 template <int NTH = NT>
