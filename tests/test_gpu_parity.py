@@ -72,6 +72,10 @@ SMALL = [
     ((24, 27, 7), (0, 1, 1), 1.1),
     ((96, 162, 5), (1, 1, 0), 0.0),
     ((96, 18, 9), (0, 0, 1), 1.4),
+    # wave-level FFT paths: x half length 256 and y length 256 (4.4.4.4),
+    # y length 512 (8.8.8); z both on and off the full-chunk fast path
+    ((512, 256, 12), (0, 0, 1), 1.3),
+    ((512, 512, 8), (0, 0, 0), 0.0),
 ]
 
 
@@ -95,7 +99,9 @@ def test_small_fp64(pcx, orc, dims, bc, stretch):
                                              ((64, 96, 33), (0, 0, 0), 0.0),
                                              ((64, 48, 40), (1, 1, 1), 1.5),
                                              # partial stencil tiles in x and y (last tiles of 32 and 2)
-                                             ((64, 18, 12), (0, 0, 1), 1.3), ((96, 162, 5), (1, 1, 0), 0.0)])
+                                             ((64, 18, 12), (0, 0, 1), 1.3), ((96, 162, 5), (1, 1, 0), 0.0),
+                                             # wave-level FFT paths in FP32 (x half length and y length 256)
+                                             ((512, 256, 16), (0, 0, 1), 1.2)])
 def test_small_refined(pcx, orc, dims, bc, stretch):
     case = W.config0() if dims == (32, 32, 32) else W.random_case(5 + sum(dims), *dims, *bc, stretch=stretch)
     _say(f"case {case.name} fp32_refined")
