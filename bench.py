@@ -102,7 +102,7 @@ def src_hash():
 
 
 # pass name -> kernel-name prefix in the rocprofv3 summaries
-KERNEL_OF_PASS = {"correct_div": "pcx::k_corr", "rhs_stencil": "pcx::k_rhs", "x_fft_fwd": "void pcx::k_xfwd<double, 0",
+KERNEL_OF_PASS = {"correct_div": "void pcx::k_corr<", "rhs_stencil": "void pcx::k_rhs<", "x_fft_fwd": "void pcx::k_xfwd<double, 0",
                   "y_fft_fwd": "void pcx::k_y<double, false", "y_fft_inv": "void pcx::k_y<double, true",
                   "z_solve": "void pcx::k_z<double", "x_fft_inv_store_p": "void pcx::k_xinv<double, 0"}
 

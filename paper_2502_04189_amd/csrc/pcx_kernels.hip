@@ -26,12 +26,13 @@ __device__ __forceinline__ int xcd_tile(int ntiles)
 constexpr int MT = 512;
 constexpr int MTC = 1024;
 
+template <bool TWO>
 __global__ __launch_bounds__(MT) void k_rhs(Dom d)
 {
     __shared__ double sm[16 + 6 * MT];
     const int t = xcd_tile(d.mg[0].ntiles);
     if (t >= d.mg[0].ntiles) return;
-    pass_rhs<MT>(d, t, (char *)sm);
+    pass_rhs<MT, TWO>(d, t, (char *)sm);
 }
 
 __global__ __launch_bounds__(MT) void k_resid(Dom d, int solve)
@@ -72,12 +73,13 @@ __global__ __launch_bounds__(NTH) void k_xinv(Dom d, int solve)
     pass_xinv<T, MODE, NTH>(d, blockIdx.x, smem, solve);
 }
 
+template <bool TWO>
 __global__ __launch_bounds__(MTC) void k_corr(Dom d, int divcheck)
 {
     __shared__ double sm[16 + 7 * MTC];
     const int t = xcd_tile(d.mg[1].ntiles);
     if (t >= d.mg[1].ntiles) return;
-    pass_corr<MTC>(d, t, (char *)sm, divcheck != 0);
+    pass_corr<MTC, TWO>(d, t, (char *)sm, divcheck != 0);
 }
 
 __global__ __launch_bounds__(NT) void k_div(Dom d)
@@ -175,7 +177,9 @@ static int xcd_grid(int ntiles) { return ((ntiles + 7) >> 3) << 3; }
 
 hipError_t launch_rhs(const Dom &d, hipStream_t s)
 {
-    PCX_LAUNCH_B(k_rhs, xcd_grid(d.mg[0].ntiles), MT, 0, s, d);
+    // a second halo item per thread only when the halo outnumbers the threads
+    if (5 * (d.mg[0].cti + d.mg[0].ctj) > MT) PCX_LAUNCH_B(k_rhs<true>, xcd_grid(d.mg[0].ntiles), MT, 0, s, d);
+    PCX_LAUNCH_B(k_rhs<false>, xcd_grid(d.mg[0].ntiles), MT, 0, s, d);
 }
 
 hipError_t launch_resid(const Dom &d, int solve, hipStream_t s)
@@ -250,7 +254,9 @@ hipError_t launch_xinv(const Dom &d, int prec, int mode, int solve, size_t lds, 
 
 hipError_t launch_corr(const Dom &d, bool divcheck, hipStream_t s)
 {
-    PCX_LAUNCH_B(k_corr, xcd_grid(d.mg[1].ntiles), MTC, 0, s, d, divcheck ? 1 : 0);
+    if (7 * (d.mg[1].cti + d.mg[1].ctj) > MTC)
+        PCX_LAUNCH_B(k_corr<true>, xcd_grid(d.mg[1].ntiles), MTC, 0, s, d, divcheck ? 1 : 0);
+    PCX_LAUNCH_B(k_corr<false>, xcd_grid(d.mg[1].ntiles), MTC, 0, s, d, divcheck ? 1 : 0);
 }
 
 static int xmax_grid(const Dom &d)

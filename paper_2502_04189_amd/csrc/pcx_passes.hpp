@@ -153,7 +153,7 @@ __device__ __forceinline__ Halo rhs_halo(const Dom &d, const MGeo &g, int tile, 
 // previous plane.  Every global read of plane k+1 is issued while plane k
 // is computed.  LDS: 16 reduction slots, p* / rho / u* / v* of the plane and
 // the halo items.
-template <int NTH = NT>
+template <int NTH = NT, bool TWO = true>
 __device__ __forceinline__ void pass_rhs(const Dom &d, int tile, char *smem)
 {
     constexpr int MG = 0;
@@ -168,7 +168,9 @@ __device__ __forceinline__ void pass_rhs(const Dom &d, int tile, char *smem)
     const double idx2 = d.idx * d.idx, idy2 = d.idy * d.idy, cdiv = d.rho0 / d.dt;
     const int nh = 5 * (TI + TJ);
     const Halo H = rhs_halo(d, g, tile, NTH);
-    const bool hv0 = threadIdx.x < nh, hv1 = threadIdx.x + NTH < nh;
+    // TWO: a thread may own a second halo item (more halo items than
+    // threads); without it the second item's load is not issued at all
+    const bool hv0 = threadIdx.x < nh, hv1 = TWO && threadIdx.x + NTH < nh;
     // tile origin from the tile index (t.i, t.j are clamped for idle threads)
     const int per = g.cnti * g.cntj, rem = tile - (tile / per) * per;
     const int i0 = (rem % g.cnti) * TI, j0 = (rem / g.cnti) * TJ;
@@ -179,7 +181,7 @@ __device__ __forceinline__ void pass_rhs(const Dom &d, int tile, char *smem)
     double Pc = d.ps[k * sz + col], Rc = d.rho[k * sz + col];
     double Pp = d.ps[kp(k) * sz + col], Rp = d.rho[kp(k) * sz + col];
     double U = d.u[k * sz + col], V = d.v[k * sz + col], W = d.w[k * sz + col];
-    double h0 = H.fp[0][k * sz + H.off[0]], h1 = H.fp[1][k * sz + H.off[1]];
+    double h0 = H.fp[0][k * sz + H.off[0]], h1 = TWO ? H.fp[1][k * sz + H.off[1]] : 0.0;
     double Fb = 0.0, Wb = 0.0; // flux of (1 - rho0/rho) G p* and w* on face k - 1/2
     if (!(d.bcz == BC_WALL && k == 0)) {
         const int km = (k == 0) ? nz - 1 : k - 1;
@@ -193,7 +195,7 @@ __device__ __forceinline__ void pass_rhs(const Dom &d, int tile, char *smem)
         const int k1 = march_next(k, t), k2 = kp(k1);
         const double P2 = d.ps[k2 * sz + col], R2 = d.rho[k2 * sz + col];
         const double U1 = d.u[k1 * sz + col], V1 = d.v[k1 * sz + col], W1 = ld_stream(d.w + k1 * sz + col);
-        const double g0 = H.fp[0][k1 * sz + H.off[0]], g1 = H.fp[1][k1 * sz + H.off[1]];
+        const double g0 = H.fp[0][k1 * sz + H.off[0]], g1 = TWO ? H.fp[1][k1 * sz + H.off[1]] : 0.0;
         const int c = k * sz + col;
         const bool wt = d.bcz == BC_WALL && k == nz - 1;
         sP[me] = Pc; sR[me] = Rc; sU[me] = U; sV[me] = V;
@@ -367,7 +369,7 @@ __device__ __forceinline__ Halo corr_halo(const Dom &d, const MGeo &g, int tile,
 // plane k is computed, so each workgroup keeps a plane of loads in flight.
 // LDS: 16 reduction slots, p / p* / rho / u_out / v_out of the plane (one per
 // thread), and the halo items.
-template <int NTH = NT>
+template <int NTH = NT, bool TWO = true>
 __device__ __forceinline__ void pass_corr(const Dom &d, int tile, char *smem, bool divcheck)
 {
     constexpr int MG = 1;
@@ -381,7 +383,9 @@ __device__ __forceinline__ void pass_corr(const Dom &d, int tile, char *smem, bo
     const double dt = d.dt, ir0 = d.irho0;
     const int nh = 7 * (TI + TJ);
     const Halo H = corr_halo(d, g, tile, NTH);
-    const bool hv0 = threadIdx.x < nh, hv1 = threadIdx.x + NTH < nh;
+    // TWO: a thread may own a second halo item (more halo items than
+    // threads); without it the second item's load is not issued at all
+    const bool hv0 = threadIdx.x < nh, hv1 = TWO && threadIdx.x + NTH < nh;
     // tile extent and where the neighbours of this cell live
     // tile origin from the tile index (t.i, t.j are clamped for idle threads)
     const int per = g.cnti * g.cntj, rem = tile - (tile / per) * per;
@@ -394,7 +398,7 @@ __device__ __forceinline__ void pass_corr(const Dom &d, int tile, char *smem, bo
     double P0 = d.po[k * sz + col], S0 = d.ps[k * sz + col], R0 = d.rho[k * sz + col];
     double P1 = d.po[kp(k) * sz + col], S1 = d.ps[kp(k) * sz + col], R1 = d.rho[kp(k) * sz + col];
     double U = d.u[k * sz + col], V = d.v[k * sz + col], W = d.w[k * sz + col];
-    double h0 = H.fp[0][k * sz + H.off[0]], h1 = H.fp[1][k * sz + H.off[1]];
+    double h0 = H.fp[0][k * sz + H.off[0]], h1 = TWO ? H.fp[1][k * sz + H.off[1]] : 0.0;
     double fb = 0.0;
     if (divcheck && !(d.bcz == BC_WALL && k == 0)) fb = corr_face(d, 2, t.i, t.j, (k == 0) ? nz - 1 : k - 1);
     double dmax = 0.0, omax = 0.0;
@@ -403,7 +407,7 @@ __device__ __forceinline__ void pass_corr(const Dom &d, int tile, char *smem, bo
         const int k1 = march_next(k, t), k2 = kp(k1);
         const double P2 = d.po[k2 * sz + col], S2 = d.ps[k2 * sz + col], R2 = d.rho[k2 * sz + col];
         const double U1 = d.u[k1 * sz + col], V1 = d.v[k1 * sz + col], W1 = ld_stream(d.w + k1 * sz + col);
-        const double g0 = H.fp[0][k1 * sz + H.off[0]], g1 = H.fp[1][k1 * sz + H.off[1]];
+        const double g0 = H.fp[0][k1 * sz + H.off[0]], g1 = TWO ? H.fp[1][k1 * sz + H.off[1]] : 0.0;
         const int c = k * sz + col;
         const bool wt = d.bcz == BC_WALL && k == nz - 1;
         sP[me] = P0; sS[me] = S0; sR[me] = R0;
