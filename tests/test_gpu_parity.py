@@ -76,6 +76,9 @@ SMALL = [
     # y length 512 (8.8.8); z both on and off the full-chunk fast path
     ((512, 256, 12), (0, 0, 1), 1.3),
     ((512, 512, 8), (0, 0, 0), 0.0),
+    # narrow and tall: the stencil halos outnumber the threads (two items each)
+    ((4, 192, 6), (0, 0, 1), 1.2),
+    ((6, 144, 4), (1, 1, 0), 0.0),
 ]
 
 
