@@ -38,24 +38,33 @@ def spectral_bytes(gs, csz):
     return (gs.nx // 2 + 1) * gs.ny * gs.nz * csz
 
 
+# Algorithmic HBM bytes per cell of each pass, from the step's byte model:
+# every separable pass reads its compulsory inputs once and writes its
+# compulsory outputs once.  The model fuses the RHS into the forward x
+# transform (P1: 40 read + the spectral write) and the correction into the
+# inverse x transform (P5: spectral read + 40 read + 32 write), so where a
+# pass is split in two here, each kernel is charged its own share and the
+# round trip between them (f written and read back, p read back by the
+# correction) is reported as overhead, not as algorithmic bytes.
 def kernel_bytes(name, gs, csz):
-    """Compulsory HBM bytes of one launch of a pass (algorithmic model: every
-    input read once, every output written once)."""
+    """(algorithmic bytes, overhead bytes) of one launch of a pass."""
     n = gs.cells
     sp = spectral_bytes(gs, csz)
     table = {
-        "rhs_stencil": 5 * 8 * n + 8 * n,          # rho, p*, u*, v*, w* -> f
-        "resid_stencil": 2 * 8 * n + 8 * n,        # f, p -> r
-        "x_fft_fwd": 8 * n + sp,                   # f -> S1
-        "x_fft_fwd_resid": 8 * n + sp,             # r -> S1
-        "y_fft_fwd": 2 * sp, "z_solve": 2 * sp, "y_fft_inv": 2 * sp,
-        "x_fft_inv_store_p": sp + 8 * n,           # S1 -> p
-        "x_fft_inv_accum_p": sp + 16 * n,          # S1, p -> p
-        "p_mean": 0,
-        "correct_div": 6 * 8 * n + 3 * 8 * n,      # u*, v*, w*, rho, p*, p -> u, v, w
-        "div_check": 3 * 8 * n,
+        "rhs_stencil": (5 * 8 * n, 8 * n),           # rho, p*, u*, v*, w* in; f stored (overhead)
+        "rhs_fftx": (5 * 8 * n + sp, 0),             # fused: rho, p*, u*, v*, w* -> spectral
+        "resid_stencil": (2 * 8 * n, 8 * n),         # f, p in; r stored (overhead)
+        "resid_fftx": (2 * 8 * n + sp, 0),           # fused: f, p -> spectral
+        "x_fft_fwd": (sp, 8 * n),                    # spectral out; f read back (overhead)
+        "x_fft_fwd_resid": (sp, 8 * n),              # spectral out; r read back (overhead)
+        "y_fft_fwd": (2 * sp, 0), "z_solve": (2 * sp, 0), "y_fft_inv": (2 * sp, 0),
+        "x_fft_inv_store_p": (sp + 8 * n, 0),        # spectral in, p out
+        "x_fft_inv_accum_p": (sp + 16 * n, 0),       # spectral in, p in and out
+        "p_mean": (0, 0), "x_max": (0, 0),
+        "correct_div": (5 * 8 * n + 3 * 8 * n, 8 * n),  # u*, v*, w*, rho, p* in, u, v, w out; p read back
+        "div_check": (0, 3 * 8 * n),
     }
-    return table.get(name, 0)
+    return table.get(name, (0, 0))
 
 
 def time_plan(plan, case_dev, dt, rho0, steps, warmup, outs):
@@ -107,47 +116,100 @@ KERNEL_OF_PASS = {"correct_div": "void pcx::k_corr<", "rhs_stencil": "void pcx::
                   "z_solve": "void pcx::k_z<double", "x_fft_inv_store_p": "void pcx::k_xinv<double, 0"}
 
 
-def measured_traffic(pass_name, profile="fp64_512cube_step"):
-    """HBM bytes per launch of the kernel behind a pass, from the committed
-    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, calibrated), or
-    None when the kernel sources changed since the counters were taken."""
+def _profile(profile="fp64_512cube_step"):
     fn = os.path.join(ROOT, "profiles", profile + "_traffic.json")
     if not os.path.exists(fn):
         return None
     d = json.load(open(fn))
-    if d.get("src_hash") != src_hash():
-        return None
+    return d if d.get("src_hash") == src_hash() else None
+
+
+def _profile_kernel(pass_name, prof):
     pre = KERNEL_OF_PASS.get(pass_name)
-    for k, v in d["kernels"].items():
-        if pre and k.startswith(pre):
-            return int(v["fetch_bytes"] + v["write_bytes"])
+    if not prof or not pre:
+        return None
+    for k, v in prof["kernels"].items():
+        if k.startswith(pre):
+            return v
     return None
 
 
 def roofline(pass_summary, gs, csz):
-    # dominant kernel = largest total time per step
+    """Roofline of the dominant kernel (largest time per step): algorithmic
+    bytes per launch over its average launch duration, timed with HIP events
+    the library records on the step's stream around each pass.  The committed
+    rocprofv3 summary of the same kernel gives its kernel-trace average and
+    the HBM bytes the counters saw (null once the sources have changed)."""
     best = max(pass_summary.items(), key=lambda kv: kv[1]["ms_avg"] * kv[1]["launches_per_step"])
     name, s = best
-    by = kernel_bytes(name, gs, csz)
-    gbs = by / (s["ms_avg"] * 1e-3) / 1e9
-    return name, {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name) if csz == 16 else None,
-                  "kernel": name, "bytes_per_launch": by, "ms_per_launch": round(s["ms_avg"], 4)}
+    alg, ovh = kernel_bytes(name, gs, csz)
+    gbs = alg / (s["ms_avg"] * 1e-3) / 1e9
+    pk = _profile_kernel(name, _profile()) if csz == 16 else None
+    out = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(gbs / HBM_PEAK_GBS, 4),
+           "traffic": int(pk["fetch_bytes"] + pk["write_bytes"]) if pk else None,
+           "kernel": name, "bytes_per_launch": alg, "overhead_bytes_per_launch": ovh,
+           "bytes_per_cell": alg / gs.cells, "cells_per_launch": gs.cells,
+           "ms_per_launch": round(s["ms_avg"], 4)}
+    if pk:
+        out["ms_per_launch_rocprof"] = round(pk["ms"], 4)
+        out["frac_rocprof"] = round(alg / (pk["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    return name, out
 
 
-def cpu_baseline(n_cpu):
-    """The oracle, single-threaded, on one full step of the same recipe at
-    n_cpu^3 (a bounded sample of the workload)."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(case):
+    """The oracle as it stands (single-threaded C, FP64) on one whole step of
+    the benchmarked case's own inputs, pinned to one host core."""
     import oracle
-    from paper_2502_04189_amd import workloads as W
-    case = W.channel_bubbles(n_cpu, max(1, (n_cpu // 64) ** 3), 1003, f"cpu_sample_{n_cpu}^3")
     g = oracle.Grid.from_workload(case.grid)
-    t0 = time.perf_counter()
-    oracle.step(g, case.dt, case.rho0, *case.fields())
-    t = time.perf_counter() - t0
+    fields = case.fields()
+    old = os.sched_getaffinity(0)
+    core = min(old)
+    os.sched_setaffinity(0, {core})
+    try:
+        t0 = time.perf_counter()
+        oracle.step(g, case.dt, case.rho0, *fields)
+        t = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, old)
     return {"value": round(case.grid.cells / t / 1e6, 3), "unit": "Mpts/s", "cores": 1, "kind": "oracle",
-            "sample": f"one full oracle step (FP64, 1 thread) of the wall-channel bubble recipe at "
-                      f"{n_cpu}^3 ({case.grid.cells} cells) in {t:.1f} s"}
+            "sample": f"one whole oracle step (FP64, single thread pinned to core {core}) on the benchmarked "
+                      f"inputs ({case.name}, {case.grid.cells} cells) in {t:.1f} s",
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(), "seconds": round(t, 2)}
+
+
+def reference_bandwidth():
+    """Achievable-bandwidth reference points measured in the same run: a
+    1 GiB device-to-device copy and a 1 GiB streaming elementwise kernel
+    (read + write), each timed with events over 10 repetitions."""
+    import torch
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    out = {}
+    for name, fn in (("copy_1GiB", lambda: dst.copy_(src)), ("scale_1GiB", lambda: torch.mul(src, 2.0, out=dst))):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        out[name] = {"ms": round(ms, 4), "GB/s": round(2 * src.numel() * 8 / (ms * 1e-3) / 1e9, 1)}
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
 
 
 def run_batch(steps, warmup, ndom):
@@ -168,7 +230,7 @@ def run_batch(steps, warmup, ndom):
         doms.append({"grid": c.grid, "dt": c.dt, "rho0": c.rho0, "rho": f[0], "pstar": f[1], "u": f[2],
                      "v": f[3], "w": f[4], "u_out": o[0], "v_out": o[1], "w_out": o[2], "p_out": o[3]})
     # the tuned shapes of the batch's size classes, kept between runs on one machine
-    cache = os.path.join(tempfile.gettempdir(), "pcx_batch_tune_cache.txt")
+    cache = pcx.batch_tune_cache_path()
     t0 = time.perf_counter()
     b = pcx.Batch(doms, "fp32_refined", autotune=True, tune_cache=cache)
     t_create = time.perf_counter() - t0
@@ -232,7 +294,6 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=512, help="grid size n^3 of the channel workload")
-    ap.add_argument("--cpu-n", type=int, default=256, help="grid of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-refined", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
@@ -254,7 +315,7 @@ def main():
 
     t0 = time.perf_counter()
     nb = 512 if args.n == 512 else max(1, (args.n // 64) ** 3)
-    case = W.channel_bubbles(args.n, nb, 1003, f"channel_{args.n}^3")
+    case = W.config3() if args.n == 512 else W.channel_bubbles(args.n, nb, 1003, f"channel_{args.n}^3")
     log(f"generated {case.name} in {time.perf_counter() - t0:.1f} s")
     gs = case.grid
     dev = [torch.from_numpy(a).to("cuda") for a in case.fields()]
@@ -329,8 +390,9 @@ def main():
     if not args.no_batch:
         res["batched"] = run_batch(args.steps, args.warmup, args.ndom)
 
+    res["reference_bandwidth"] = reference_bandwidth()
     if not args.no_cpu:
-        cb = cpu_baseline(args.cpu_n)
+        cb = cpu_baseline(case)
         res["cpu_baseline"] = cb
         res["speedup_vs_cpu_oracle"] = round(res["value"] / cb["value"], 1)
     print(json.dumps(res))

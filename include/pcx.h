@@ -69,7 +69,9 @@ typedef enum { PCX_FP64 = 0, PCX_FP32_REFINED = 1 } pcx_precision;
  * nx even (its transform is a half-length complex FFT, also for the cosine
  * transform of a wall x); ny even when periodic (any ny with a wall in y);
  * transform lengths nx, ny of the form 2^a 3^b
- * and at most 4096 (else UNSUPPORTED); nz <= 1024 (else UNSUPPORTED). */
+ * and at most 4096 (else UNSUPPORTED); nz <= 1024 (else UNSUPPORTED);
+ * nx*ny*nz <= 2^31 - 1 cells (else UNSUPPORTED: cell offsets in the kernels
+ * are 32-bit). */
 typedef struct {
     int32_t nx, ny, nz;
     double lx, ly;
@@ -163,11 +165,17 @@ pcx_status pcx_batch_create(const pcx_domain *domains, int32_t n, const pcx_opti
                             void *stream, pcx_batch *out);
 /* Enqueues one solve of every domain (one graph launch) on `stream`. */
 pcx_status pcx_batch_launch(pcx_batch batch, void *stream);
-/* Synchronizes and fills n reports (one per domain). */
+/* Fills n reports (one per domain) for the last launch: waits for the
+ * stream that launch was enqueued on (not the whole device), and runs its
+ * small report kernels and copies on that stream. */
 pcx_status pcx_batch_reports(pcx_batch batch, pcx_report *out_n);
 pcx_status pcx_batch_destroy(pcx_batch batch);
 
-/* Helper: *out = min over n doubles of rho (device pointer); synchronizes. */
+/* Helper: *out = min over n doubles of rho (device pointer), the splitting
+ * density rho0 of the paper's constant-coefficient splitting.  Enqueues on
+ * `stream` and synchronizes it.  Allocates nothing: the reduction key is a
+ * static 8-byte device variable per device, so concurrent calls from several
+ * host threads are serialized by the library. */
 pcx_status pcx_rho_min(const double *rho, int64_t n, void *stream, double *out);
 
 /* Refinement stop test used by the refined forms: nonzero when

@@ -48,6 +48,7 @@ struct pcx_batch_s {
     PhaseTab tab;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipStream_t last = nullptr;     // stream of the last launch (reports run on it)
 };
 
 static void batch_free(pcx_batch B)
@@ -80,8 +81,8 @@ static long tiles_of(const Dom &d, int kind)
 {
     switch (kind) {
     case PK_RHS:
-    case PK_RESID:
-    case PK_CORR: return d.mg[1].ntiles;
+    case PK_RESID: return d.mg[0].ntiles; // pass_rhs, pass_resid walk mg[0]
+    case PK_CORR: return d.mg[1].ntiles;  // pass_corr walks mg[1]
     case PK_XFWD_RHS:
     case PK_XFWD_RESID:
     case PK_XINV_STORE:
@@ -142,7 +143,11 @@ extern "C" pcx_status pcx_batch_create(const pcx_domain *domains, int32_t n, con
     // phases
     PhaseTab &tab = B->tab;
     std::memset(&tab, 0, sizeof(tab));
-    auto addph = [&](int kind, int solve) { tab.kind[tab.nphase] = (uint8_t)kind; tab.solve[tab.nphase] = (uint8_t)solve; tab.nphase++; };
+    bool ph_over = false;
+    auto addph = [&](int kind, int solve) {
+        if (tab.nphase >= MAXPH) { ph_over = true; return; }
+        tab.kind[tab.nphase] = (uint8_t)kind; tab.solve[tab.nphase] = (uint8_t)solve; tab.nphase++;
+    };
     addph(PK_RHS, 0);
     addph(PK_XFWD_RHS, 0);
     addph(PK_YF, 0); addph(PK_Z, 0); addph(PK_YI, 0); addph(PK_XINV_STORE, 0);
@@ -156,6 +161,7 @@ extern "C" pcx_status pcx_batch_create(const pcx_domain *domains, int32_t n, con
         addph(PK_PMEAN, s);
     }
     addph(PK_CORR, 0);
+    if (ph_over) { batch_free(B); return fail(PCX_ERR_UNSUPPORTED, "too many solves for the batch phase table"); }
 
     // per-domain tables, shapes and workspace layout
     const size_t csz = B->prec == PREC_F64 ? 16 : 8;
@@ -306,26 +312,29 @@ extern "C" pcx_status pcx_batch_launch(pcx_batch B, void *stream)
     if (!B) return fail(PCX_ERR_INVALID, "batch is NULL");
     hipError_t e = hipGraphLaunch(B->exec, (hipStream_t)stream);
     if (e != hipSuccess) return fail(PCX_ERR_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+    B->last = (hipStream_t)stream;
     return PCX_OK;
 }
 
 extern "C" pcx_status pcx_batch_reports(pcx_batch B, pcx_report *out_n)
 {
     if (!B || !out_n) return fail(PCX_ERR_INVALID, "NULL argument");
-    hipError_t e = hipDeviceSynchronize();
-    if (e != hipSuccess) return fail(PCX_ERR_HIP, std::string("hipDeviceSynchronize: ") + hipGetErrorString(e));
+    // everything runs on the stream of the last launch, in its order
+    const hipStream_t s = B->last;
     std::vector<unsigned long long> h((size_t)B->n * NSTAT);
     unsigned err = 0;
-    e = hipMemcpy(h.data(), B->stats, h.size() * 8, hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(&err, B->ctl + 1, sizeof(unsigned), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return fail(PCX_ERR_HIP, std::string("hipMemcpy(stats): ") + hipGetErrorString(e));
+    hipError_t e = hipMemcpyAsync(h.data(), B->stats, h.size() * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&err, B->ctl + 1, sizeof(unsigned), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(PCX_ERR_HIP, std::string("batch stats: ") + hipGetErrorString(e));
     bool all_conv = true;
     for (int i = 0; i < B->n; ++i) {
         const pcx_grid &g = B->grids[i];
         auto sd = [&](int k) { double v; std::memcpy(&v, &h[(size_t)i * NSTAT + k], 8); return v; };
-        e = launch_plane_sums(B->pouts[i], g.nx * g.ny, g.nz, B->psum, nullptr);
+        e = launch_plane_sums(B->pouts[i], g.nx * g.ny, g.nz, B->psum, s);
         std::vector<double> ps(g.nz);
-        if (e == hipSuccess) e = hipMemcpy(ps.data(), B->psum, g.nz * 8, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpyAsync(ps.data(), B->psum, g.nz * 8, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return fail(PCX_ERR_HIP, std::string("plane sums: ") + hipGetErrorString(e));
         double num = 0.0, lz = g.zf[g.nz] - g.zf[0];
         for (int k = 0; k < g.nz; ++k) num += (g.zf[k + 1] - g.zf[k]) * ps[k];

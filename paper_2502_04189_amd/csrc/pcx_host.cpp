@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -121,6 +122,10 @@ pcx_status validate_grid(const pcx_grid *g)
     if (!is_2a3b(g->nx) || !is_2a3b(g->ny) || g->nx > 4096 || g->ny > 4096)
         return fail(PCX_ERR_UNSUPPORTED, "transform lengths must be 2^a 3^b and at most 4096");
     if (g->nz > 1024) return fail(PCX_ERR_UNSUPPORTED, "nz above 1024 is not supported");
+    // cell offsets inside the kernels are 32-bit: nx ny nz (which bounds the
+    // spectral count nl ny nz as well, nl <= nx) must fit in int32
+    if ((int64_t)g->nx * g->ny * g->nz > (int64_t)INT32_MAX)
+        return fail(PCX_ERR_UNSUPPORTED, "grids of more than 2^31 - 1 cells are not supported");
     return PCX_OK;
 }
 
@@ -654,21 +659,16 @@ extern "C" pcx_status pcx_step(pcx_plan P, double dt, double rho0, const double 
 
 // ------------------------------------------------------------------ misc
 
+static std::mutex g_min_mutex;
+
 extern "C" pcx_status pcx_rho_min(const double *rho, int64_t n, void *stream, double *out)
 {
     if (!rho || !out || n <= 0) return fail(PCX_ERR_INVALID, "bad argument");
-    hipStream_t s = (hipStream_t)stream;
-    unsigned long long *key = nullptr;
-    HIPCHK(hipMalloc(&key, 8));
-    unsigned long long init = ~0ull, hk = 0;
-    hipError_t e = hipMemcpyAsync(key, &init, 8, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_min(rho, (long long)n, key, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(&hk, key, 8, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(key);
+    // one reduction slot per device in static device memory: calls are
+    // serialised here, and each synchronises its stream before returning
+    std::lock_guard<std::mutex> lk(g_min_mutex);
+    hipError_t e = min_to_host(rho, (long long)n, (hipStream_t)stream, out);
     if (e != hipSuccess) return fail(PCX_ERR_HIP, std::string("rho_min: ") + hipGetErrorString(e));
-    unsigned long long u = (hk >> 63) ? (hk & 0x7fffffffffffffffull) : ~hk;
-    std::memcpy(out, &u, 8);
     return PCX_OK;
 }
 

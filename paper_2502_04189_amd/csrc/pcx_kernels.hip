@@ -128,28 +128,6 @@ __device__ __forceinline__ unsigned long long dkey(double v)
     return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
 }
 
-__global__ __launch_bounds__(NT) void k_min(const double *a, long long n, unsigned long long *key)
-{
-    __shared__ unsigned long long part[NT / 64];
-    unsigned long long m = ~0ull;
-    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
-        unsigned long long kk = dkey(a[i]);
-        m = kk < m ? kk : m;
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        unsigned long long x = __shfl_xor(m, o, 64);
-        m = x < m ? x : m;
-    }
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = 1; i < NT / 64; ++i) m = part[i] < m ? part[i] : m;
-        m = part[0] < m ? part[0] : m;
-        atomicMin(key, m);
-    }
-}
-
 // ----------------------------------------------------------------- launch
 
 static hipError_t lds_attr(const void *fn, size_t lds)
@@ -284,12 +262,56 @@ hipError_t launch_plane_sums(const double *p, int nxy, int nz, double *out, hipS
     PCX_LAUNCH(k_plane_sums, nz, 0, s, p, nxy, out);
 }
 
-hipError_t launch_min(const double *a, long long n, unsigned long long *key, hipStream_t s)
+// The 8-byte key of pcx_rho_min: a file-scope device variable (one per
+// device, held for the process lifetime), so the helper allocates nothing.
+// Its kernels name it directly; the host reads it back by symbol.  Calls are
+// serialised by the caller (a host mutex) and each one synchronises its
+// stream before the next may start.
+__device__ unsigned long long g_min_key;
+
+__global__ void k_min_init() { g_min_key = ~0ull; }
+
+__global__ __launch_bounds__(NT) void k_min_slot(const double *a, long long n)
+{
+    __shared__ unsigned long long part[NT / 64];
+    unsigned long long m = ~0ull;
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
+        unsigned long long kk = dkey(a[i]);
+        m = kk < m ? kk : m;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long x = __shfl_xor(m, o, 64);
+        m = x < m ? x : m;
+    }
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < NT / 64; ++i) m = part[i] < m ? part[i] : m;
+        m = part[0] < m ? part[0] : m;
+        atomicMin(&g_min_key, m);
+    }
+}
+
+hipError_t min_to_host(const double *a, long long n, hipStream_t s, double *out)
 {
     long long blocks = (n + NT - 1) / NT;
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
-    PCX_LAUNCH(k_min, (unsigned)blocks, 0, s, a, n, key);
+    hipLaunchKernelGGL(k_min_init, dim3(1), dim3(1), 0, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_min_slot, dim3((unsigned)blocks), dim3(NT), 0, s, a, n);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    unsigned long long hk = 0;
+    e = hipMemcpyFromSymbolAsync(&hk, HIP_SYMBOL(g_min_key), sizeof(hk), 0, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    // invert the order-preserving key
+    const unsigned long long u = (hk >> 63) ? (hk & 0x7fffffffffffffffull) : ~hk;
+    __builtin_memcpy(out, &u, 8);
+    return hipSuccess;
 }
 
 } // namespace pcx

@@ -17,14 +17,18 @@ hipError_t launch_div(const Dom &d, hipStream_t s);
 hipError_t launch_pmean(const Dom &d, hipStream_t s);
 hipError_t launch_xmax(const Dom &d, int solve, hipStream_t s);
 hipError_t launch_plane_sums(const double *p, int nxy, int nz, double *out, hipStream_t s);
-hipError_t launch_min(const double *a, long long n, unsigned long long *key, hipStream_t s);
+// min over n doubles into *out (host); synchronises s
+hipError_t min_to_host(const double *a, long long n, hipStream_t s, double *out);
 
 } // namespace pcx
 
 namespace pcx {
 
 // ---------------------------------------------------------------- batched
-constexpr int MAXPH = 64;
+// phases of a batch: 8 for the first solve (RHS, x, y, z, y, x, maxima,
+// correction) and 7 per further solve, for up to MAXIT solves
+constexpr int MAXPH = 96;
+static_assert(MAXPH >= 8 + 7 * (MAXIT - 1), "phase table too small for MAXIT solves");
 enum { PK_RHS = 0, PK_RESID, PK_XFWD_RHS, PK_XFWD_RESID, PK_YF, PK_Z, PK_YI, PK_XINV_STORE, PK_XINV_ACCUM, PK_PMEAN, PK_CORR };
 
 struct Item {

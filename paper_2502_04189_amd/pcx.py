@@ -233,6 +233,13 @@ class Batch:
     __del__ = close
 
 
+def batch_tune_cache_path():
+    """Tune cache of the batch's size classes, kept between runs on one
+    machine (the benchmark and the GPU tests use the same file)."""
+    import tempfile
+    return os.path.join(tempfile.gettempdir(), "pcx_batch_tune_cache.txt")
+
+
 def rho_min(rho, stream=None):
     out = C.c_double()
     _check(lib().pcx_rho_min(C.c_void_p(rho.data_ptr()), rho.numel(), _stream_handle(stream), C.byref(out)),

@@ -61,6 +61,22 @@ def test_descriptor_validation(L):
     assert L.pcx_step(None, 1.0, 1.0, *([None] * 9), None, None) == P.PCX_ERR_INVALID
 
 
+def test_cell_count_limit(L):
+    """Cell offsets in the kernels are 32-bit: a grid of 2^31 cells or more
+    is rejected as UNSUPPORTED before any device work (checked here without a
+    GPU: a grid just below the limit passes validation and then reports the
+    missing device, or is created when a GPU is present)."""
+    import torch
+    big = W.GridSpec(2048, 2048, 512, 1.0, 1.0, W.zf_uniform(512, 1.0))
+    assert _create(L, big) == P.PCX_ERR_UNSUPPORTED
+    assert "2^31" in L.pcx_last_error().decode()
+    big_wall = W.GridSpec(4096, 1024, 512, 1.0, 1.0, W.zf_uniform(512, 1.0), 1, 1, 1)
+    assert _create(L, big_wall) == P.PCX_ERR_UNSUPPORTED
+    if not torch.cuda.is_available():
+        under = W.GridSpec(2048, 2048, 511, 1.0, 1.0, W.zf_uniform(511, 1.0))
+        assert _create(L, under) == P.PCX_ERR_HIP
+
+
 def test_missing_device_is_hip_error(L):
     import torch
     if torch.cuda.is_available():

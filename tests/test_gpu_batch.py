@@ -8,7 +8,7 @@ import pytest
 
 from paper_2502_04189_amd import workloads as W
 from tests import manufactured as M
-from tests.gpu_util import to_dev
+from tests.gpu_util import check_div, to_dev
 
 pytestmark = pytest.mark.gpu
 REF_TOL = 1e-10
@@ -47,7 +47,8 @@ def _outs(d):
 def test_batch_refined_vs_oracle(pcx, orc):
     import torch
     cases = W.config4(ndom=10)
-    _say("batch refined: first 10 domains of the 192-domain mix: " + ", ".join(c.name for c in cases))
+    _say("batch refined: 10 domains drawn by the batch recipe (seed 1004, ndom=10): " +
+         ", ".join(c.name for c in cases))
     doms = _domains(cases)
     b = pcx.Batch(doms, "fp32_refined")
     b.launch()
@@ -60,6 +61,7 @@ def test_batch_refined_vs_oracle(pcx, orc):
         _say(f"{c.name}: errors {e} div {r['max_div_rel']:.2e} converged {r['converged']}")
         assert max(e.values()) <= REF_TOL
         assert r["max_div_rel"] <= REF_TOL
+        check_div(orc, c, _outs(d), r, c.name)
     assert st == pcx.PCX_OK
 
 
@@ -146,4 +148,5 @@ def test_batch_mixed_walls_vs_oracle(pcx, orc):
             _say(f"  {c.name}: errors {e} report {r}")
             assert max(e.values()) <= tol
             assert r["max_div_rel"] <= tol
+            check_div(orc, c, _outs(d), r, c.name)
         assert st == pcx.PCX_OK

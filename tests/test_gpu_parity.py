@@ -10,7 +10,7 @@ import pytest
 
 from paper_2502_04189_amd import workloads as W
 from tests import manufactured as M
-from tests.gpu_util import errors, run_plan, to_dev
+from tests.gpu_util import check_div, errors, run_plan, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -49,6 +49,7 @@ def test_config0_fp64(pcx, orc):
     _say(f"errors {e} report {rep}")
     assert max(e.values()) <= FP64_TOL
     assert rep["max_div_rel"] <= FP64_TOL
+    check_div(orc, case, got, rep, case.name)
     assert abs(rep["mean_p"]) <= 1e-13 * np.abs(ref[3]).max()
     assert np.all(got[2][-1] == 0.0)
 
@@ -93,6 +94,7 @@ def test_small_fp64(pcx, orc, dims, bc, stretch):
     _say(f"errors {e} div {rep['max_div_rel']:.3e}")
     assert max(e.values()) <= FP64_TOL
     assert rep["max_div_rel"] <= FP64_TOL
+    check_div(orc, case, got, rep, case.name)
     # the FP64 solve stores p itself as the update: the wave and workgroup
     # maxima of the x inverse must give max |p| exactly
     assert rep["last_update_inf"] == np.abs(got[3]).max()
@@ -116,6 +118,7 @@ def test_small_refined(pcx, orc, dims, bc, stretch):
     assert rep["converged"] == 1
     assert max(e.values()) <= REF_TOL
     assert rep["max_div_rel"] <= REF_TOL
+    check_div(orc, case, got, rep, case.name)
 
 
 @pytest.mark.parametrize("dims,ndrops,kmax", [((64, 64, 32), 6, 8.0), ((96, 96, 48), 12, 12.0)])
@@ -132,3 +135,4 @@ def test_emulsion_small(pcx, orc, dims, ndrops, kmax):
         _say(f"errors {e} div {rep['max_div_rel']:.3e} solves {rep['solves']}")
         assert max(e.values()) <= tol
         assert rep["max_div_rel"] <= tol
+        check_div(orc, case, got, rep, case.name)
