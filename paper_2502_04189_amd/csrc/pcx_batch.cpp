@@ -1,15 +1,23 @@
-// pcx_batch.cpp -- batched form: many independent domains of uneven size in
-// one persistent kernel launch, captured once into a HIP graph.
+// pcx_batch.cpp -- batched form: many independent domains of uneven size,
+// solved by one HIP graph launch.
 //
-// At create time every domain gets its own tables and workspace, and a
-// device work list is built: phase by phase, domains in decreasing size
-// (longest first), every tile of a (domain, phase) in a row.  The graph holds
-// a reset kernel (queue head, phase counters, reduction slots; no memset
-// nodes) followed by the persistent kernel.
+// At create time every domain gets its own tables and workspace.  Two
+// schedules of the same pass bodies can be captured into the graph:
+//   phased (default): one node per pass of the step, each a grouped launch
+//     over the tiles of every domain for that pass (domains largest first),
+//     each kernel with its own workgroup size and register budget; with
+//     PCX_BATCH_MODE=persistent the same nodes run persistent grids (one
+//     workgroup slot per resident workgroup, items taken in a fixed stride);
+//   mega (PCX_BATCH_MODE=mega): a single persistent kernel pulling
+//     (domain, pass, tile) items from a device queue, with per-domain phase
+//     counters for the dependencies.
+// The graph starts with a reset kernel (queue head, phase counters,
+// reduction slots; no memset nodes).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -49,6 +57,15 @@ struct pcx_batch_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t last = nullptr;     // stream of the last launch (reports run on it)
+    int mode = 0;                   // 0 phased, 1 phased persistent, 2 mega
+    GItem *gitems = nullptr;        // phased: items of every group, in launch order
+    struct Group {
+        GVariant v;
+        int first, count, grid, solve;
+        size_t lds;
+    };
+    std::vector<Group> groups;
+    std::vector<int> smaxs;         // z levels per lane of each domain
 };
 
 static void batch_free(pcx_batch B)
@@ -61,6 +78,7 @@ static void batch_free(pcx_batch B)
     if (B->d_doms) (void)hipFree(B->d_doms);
     if (B->ws) (void)hipFree(B->ws);
     if (B->items) (void)hipFree(B->items);
+    if (B->gitems) (void)hipFree(B->gitems);
     if (B->ctl) (void)hipFree(B->ctl);
     if (B->need) (void)hipFree(B->need);
     if (B->stats) (void)hipFree(B->stats);
@@ -93,6 +111,167 @@ static long tiles_of(const Dom &d, int kind)
     case PK_PMEAN: return 1;
     default: return d.mg[0].ntiles;
     }
+}
+
+// Schedule of the batch, from PCX_BATCH_MODE: "phased" (default),
+// "persistent" (phased with persistent grids) or "mega".
+static int batch_mode()
+{
+    const char *m = std::getenv("PCX_BATCH_MODE");
+    if (!m) return 0;
+    if (!std::strcmp(m, "persistent")) return 1;
+    if (!std::strcmp(m, "mega")) return 2;
+    return 0;
+}
+
+namespace pcx {
+
+// Kernel variant of pass `kind` for domain d (see launch_group).
+GVariant variant_of(const Dom &d, int kind, int smax)
+{
+    GVariant v{kind, NT, 0, 0};
+    switch (kind) {
+    case PK_RHS: v.nth = march_threads(0); v.two = 5 * (d.mg[0].cti + d.mg[0].ctj) > v.nth; break;
+    case PK_RESID: v.nth = march_threads(0); break;
+    case PK_CORR: v.nth = march_threads(1); v.two = 7 * (d.mg[1].cti + d.mg[1].ctj) > v.nth; break;
+    case PK_XFWD_RHS:
+    case PK_XFWD_RESID:
+    case PK_XINV_STORE:
+    case PK_XINV_ACCUM: v.nth = d.xth; break;
+    case PK_YF:
+    case PK_YI: v.nth = d.yth; break;
+    case PK_Z: v.smax = smax; break;
+    case PK_PMEAN: v.nth = 64; break;
+    default: break;
+    }
+    return v;
+}
+
+long group_tiles(const Dom &d, int kind)
+{
+    switch (kind) {
+    case PK_XMAX: return xmax_wgs(d);
+    case PK_PMEAN: return 1;
+    default: return ::tiles_of(d, kind);
+    }
+}
+
+size_t group_lds(const Dom &d, int kind, int prec)
+{
+    switch (kind) {
+    case PK_XFWD_RHS:
+    case PK_XFWD_RESID:
+    case PK_XINV_STORE:
+    case PK_XINV_ACCUM: return lds_x(d, prec);
+    case PK_YF:
+    case PK_YI: return lds_y(d, prec);
+    case PK_Z: return lds_z(d, prec);
+    default: return 0;
+    }
+}
+
+} // namespace pcx
+
+// Phased schedule: one grouped launch per (pass, kernel variant), in the
+// order of the single-domain step, captured into the graph after the reset
+// of the reduction slots.  Within a launch the domains come largest first;
+// the stencil passes hand each XCD a contiguous range of tiles (consecutive
+// workgroups go to different XCDs), so tiles adjacent in a domain share an
+// L2 for their halos, as in the single-domain launches.
+static pcx_status build_phased(pcx_batch B)
+{
+    const int n = B->n;
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    auto cells = [&](int i) { return (long)B->grids[i].nx * B->grids[i].ny * B->grids[i].nz; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cells(a) > cells(b); });
+    struct Ph {
+        int kind, solve;
+    };
+    std::vector<Ph> phs;
+    const bool ref = B->prec == PREC_F32;
+    phs.push_back({PK_RHS, 0});
+    phs.push_back({PK_XFWD_RHS, 0});
+    for (int k : {PK_YF, PK_Z, PK_YI, PK_XINV_STORE, PK_XMAX}) phs.push_back({k, 0});
+    if (ref) phs.push_back({PK_PMEAN, 0});
+    for (int sv = 1; sv < B->solves; ++sv)
+        for (int k : {PK_RESID, PK_XFWD_RESID, PK_YF, PK_Z, PK_YI, PK_XINV_ACCUM, PK_XMAX, PK_PMEAN})
+            phs.push_back({k, sv});
+    phs.push_back({PK_CORR, 0});
+
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return fail(PCX_ERR_HIP, "hipGetDeviceProperties failed");
+    std::vector<GItem> all;
+    for (const Ph &ph : phs) {
+        // domains of each kernel variant, in first-appearance order
+        std::vector<std::pair<GVariant, std::vector<int>>> grp;
+        for (int i : order) {
+            const GVariant v = variant_of(B->doms[i], ph.kind, B->smaxs[i]);
+            auto it = std::find_if(grp.begin(), grp.end(), [&](const std::pair<GVariant, std::vector<int>> &g) {
+                return g.first.nth == v.nth && g.first.two == v.two && g.first.smax == v.smax;
+            });
+            if (it == grp.end()) grp.push_back({v, {i}});
+            else it->second.push_back(i);
+        }
+        for (auto &g : grp) {
+            std::vector<GItem> lst;
+            size_t lds = 0;
+            for (int i : g.second) {
+                const Dom &d = B->doms[i];
+                const long t = group_tiles(d, ph.kind);
+                for (long q = 0; q < t; ++q)
+                    lst.push_back(GItem{(uint32_t)i, (uint32_t)(ph.kind == PK_Z ? t - 1 - q : q)});
+                lds = std::max(lds, group_lds(d, ph.kind, B->prec));
+            }
+            const bool stencil = ph.kind == PK_RHS || ph.kind == PK_RESID || ph.kind == PK_CORR;
+            if (stencil) {
+                const size_t cnt = lst.size(), per = (cnt + 7) / 8;
+                std::vector<GItem> perm(8 * per, GItem{GSKIP, 0});
+                for (size_t b = 0; b < 8 * per; ++b) {
+                    const size_t L = (b & 7) * per + (b >> 3);
+                    if (L < cnt) perm[b] = lst[L];
+                }
+                lst.swap(perm);
+            }
+            int grid = (int)lst.size();
+            if (B->mode == 1) {
+                int per_cu = 0;
+                if (group_occupancy(g.first, B->prec, lds, &per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
+                long cap = std::max(8L, ((long)prop.multiProcessorCount * per_cu) & ~7L);
+                grid = (int)std::min<long>(grid, cap);
+            }
+            B->groups.push_back({g.first, (int)all.size(), (int)lst.size(), grid, ph.solve, lds});
+            all.insert(all.end(), lst.begin(), lst.end());
+        }
+    }
+    if (hipMalloc(&B->gitems, std::max<size_t>(all.size(), 1) * sizeof(GItem)) != hipSuccess)
+        return fail(PCX_ERR_NOMEM, "batch item list allocation failed");
+    if (hipMemcpy(B->gitems, all.data(), all.size() * sizeof(GItem), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(PCX_ERR_HIP, "batch item list copy failed");
+    B->nctl = 2;
+    if (hipMalloc(&B->ctl, (size_t)B->nctl * sizeof(unsigned)) != hipSuccess)
+        return fail(PCX_ERR_NOMEM, "batch control allocation failed");
+
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(PCX_ERR_HIP, "stream create");
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = launch_reset(B->ctl, B->nctl, cs);
+    if (e == hipSuccess) e = launch_reset((unsigned *)B->stats, n * NSTAT * 2, cs);
+    for (const auto &g : B->groups) {
+        if (e != hipSuccess) break;
+        GArgs a{B->d_doms, B->gitems + g.first, g.count, g.solve};
+        e = launch_group(g.v, B->prec, a, g.grid, g.lds, cs);
+    }
+    hipGraph_t gr = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &gr);
+    if (e == hipSuccess) e = e2;
+    B->graph = gr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return fail(PCX_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    return PCX_OK;
 }
 
 extern "C" pcx_status pcx_batch_create(const pcx_domain *domains, int32_t n, const pcx_options *opts, void *stream,
@@ -139,6 +318,8 @@ extern "C" pcx_status pcx_batch_create(const pcx_domain *domains, int32_t n, con
     B->pouts.resize(n);
     TuneCache cache;
     if (o.tune_cache) cache.load(o.tune_cache);
+    B->mode = batch_mode();
+    B->smaxs.assign(n, 4);
 
     // phases
     PhaseTab &tab = B->tab;
@@ -177,11 +358,14 @@ extern "C" pcx_status pcx_batch_create(const pcx_domain *domains, int32_t n, con
         RadixChoice rc;
         bool have = cache.lookup(B->grids[i], B->prec, tp, rc);
         if (!have && o.autotune) {
-            pcx_status st = autotune_class(B->grids[i], B->prec, (hipStream_t)stream, tp, rc);
+            pcx_status st = autotune_class(B->grids[i], B->prec, (hipStream_t)stream, tp, rc, B->mode != 2);
             if (st != PCX_OK) { batch_free(B); return st; }
             cache.store(B->grids[i], B->prec, tp, rc);
         }
-        choose_shapes(B->grids[i], B->prec, have || o.autotune ? &tp : nullptr, sh, true);
+        // the phased schedule runs the single-domain pass shapes; the mega
+        // kernel runs every pass in NT-thread workgroups
+        choose_shapes(B->grids[i], B->prec, have || o.autotune ? &tp : nullptr, sh, B->mode == 2);
+        B->smaxs[i] = sh.smax;
         pcx_status st = build_domain(B->grids[i], B->prec, sh, have || o.autotune ? &rc : nullptr, B->tables[i], B->doms[i]);
         if (st != PCX_OK) { batch_free(B); return st; }
         B->smax = std::max(B->smax, sh.smax);
@@ -221,6 +405,12 @@ extern "C" pcx_status pcx_batch_create(const pcx_domain *domains, int32_t n, con
     }
     BCHK(hipMalloc(&B->d_doms, (size_t)n * sizeof(Dom)));
     BCHK(hipMemcpy(B->d_doms, B->doms.data(), (size_t)n * sizeof(Dom), hipMemcpyHostToDevice));
+    if (B->mode != 2) {
+        pcx_status st = build_phased(B);
+        if (st != PCX_OK) { batch_free(B); return st; }
+        *out = B;
+        return PCX_OK;
+    }
 
     // work list: phase-major, largest domains first within a phase
     std::vector<int> order(n);

@@ -101,6 +101,12 @@ struct Dom {
 constexpr int XMAX_WG = 64;
 constexpr int PMEAN_LEN = 8 + XMAX_WG;
 __host__ __device__ inline int xslots(const Dom &d) { return d.ntj * d.nz * (d.xth >> 6); }
+// workgroups of the reduction of those slots (pass_xmax), at most XMAX_WG
+__host__ __device__ inline int xmax_wgs(const Dom &d)
+{
+    const int v = (xslots(d) + 4 * NT - 1) / (4 * NT);
+    return v < 1 ? 1 : (v > XMAX_WG ? XMAX_WG : v);
+}
 
 
 // ------------------------------------------------------------ complex math

@@ -382,7 +382,7 @@ extern "C" pcx_status pcx_plan_create(const pcx_grid *grid, const pcx_options *o
     TuneCache cache;
     bool have = o.tune_cache && cache.load(o.tune_cache) && cache.lookup(P->grid, P->prec, tp, rc);
     if (!have && o.autotune) {
-        st = autotune_class(P->grid, P->prec, nullptr, tp, rc);
+        st = autotune_class(P->grid, P->prec, nullptr, tp, rc, false);
         if (st != PCX_OK) { delete P; return st; }
         have = true;
         if (o.tune_cache) {

@@ -237,10 +237,7 @@ hipError_t launch_corr(const Dom &d, bool divcheck, hipStream_t s)
     PCX_LAUNCH_B(k_corr<false>, xcd_grid(d.mg[1].ntiles), MTC, 0, s, d, divcheck ? 1 : 0);
 }
 
-static int xmax_grid(const Dom &d)
-{
-    return std::max(1, std::min(XMAX_WG, (xslots(d) + 4 * NT - 1) / (4 * NT)));
-}
+static int xmax_grid(const Dom &d) { return xmax_wgs(d); }
 
 hipError_t launch_xmax(const Dom &d, int solve, hipStream_t s)
 {
@@ -312,6 +309,154 @@ hipError_t min_to_host(const double *a, long long n, hipStream_t s, double *out)
     const unsigned long long u = (hk >> 63) ? (hk & 0x7fffffffffffffffull) : ~hk;
     __builtin_memcpy(out, &u, 8);
     return hipSuccess;
+}
+
+} // namespace pcx
+
+namespace pcx {
+
+// ------------------------------------------------------------------ grouped
+// Kernels of the batched form: one launch runs one pass over tiles of many
+// domains (a graph node per pass), each kernel with its own workgroup size
+// and register budget.  The domain table is read through the constant
+// address space (scalar loads, no registers held for it across the pass).
+__device__ __forceinline__ const Dom &gdom(const GArgs &a, int i)
+{
+    return *(const Dom *)((const __attribute__((address_space(4))) Dom *)a.doms + i);
+}
+
+// Runs body(domain, tile) for the items of this workgroup; every value that
+// steers the loop is wave-uniform, and a barrier separates consecutive items
+// (the next item rewrites the LDS the last one read).
+template <typename Body>
+__device__ __forceinline__ void gloop(const GArgs &a, Body body)
+{
+    for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
+        const int dom = __builtin_amdgcn_readfirstlane((int)a.items[it].dom);
+        const int tile = __builtin_amdgcn_readfirstlane((int)a.items[it].tile);
+        if ((uint32_t)dom == GSKIP) continue;
+        body(gdom(a, dom), tile);
+        if (it + (int)gridDim.x < a.nitems) __syncthreads();
+    }
+}
+
+template <bool TWO>
+__global__ __launch_bounds__(MT) void kg_rhs(GArgs a)
+{
+    __shared__ double sm[16 + 6 * MT];
+    gloop(a, [&](const Dom &d, int t) { pass_rhs<MT, TWO>(d, t, (char *)sm); });
+}
+
+__global__ __launch_bounds__(MT) void kg_resid(GArgs a)
+{
+    __shared__ double sm[16 + 2 * MT];
+    gloop(a, [&](const Dom &d, int t) { pass_resid<MT>(d, t, (char *)sm, a.solve); });
+}
+
+template <bool TWO>
+__global__ __launch_bounds__(MTC) void kg_corr(GArgs a)
+{
+    __shared__ double sm[16 + 7 * MTC];
+    gloop(a, [&](const Dom &d, int t) { pass_corr<MTC, TWO>(d, t, (char *)sm, true); });
+}
+
+template <typename T, int SRC, int NTH>
+__global__ __launch_bounds__(NTH) void kg_xfwd(GArgs a)
+{
+    extern __shared__ __align__(16) char smem[];
+    gloop(a, [&](const Dom &d, int t) { pass_xfwd<T, SRC, NTH>(d, t, smem); });
+}
+
+template <typename T, bool INV, int NTH>
+__global__ __launch_bounds__(NTH) void kg_y(GArgs a)
+{
+    extern __shared__ __align__(16) char smem[];
+    gloop(a, [&](const Dom &d, int t) { pass_y<T, INV, NTH>(d, t, smem); });
+}
+
+template <typename T, int SMAX>
+__global__ __launch_bounds__(NT) void kg_z(GArgs a)
+{
+    extern __shared__ __align__(16) char smem[];
+    gloop(a, [&](const Dom &d, int t) { pass_z<T, SMAX>(d, t, smem); });
+}
+
+template <typename T, int MODE, int NTH>
+__global__ __launch_bounds__(NTH) void kg_xinv(GArgs a)
+{
+    extern __shared__ __align__(16) char smem[];
+    gloop(a, [&](const Dom &d, int t) { pass_xinv<T, MODE, NTH>(d, t, smem, a.solve); });
+}
+
+// x-inverse maxima: item tile = reduction workgroup wg of the domain
+__global__ __launch_bounds__(NT) void kg_xmax(GArgs a)
+{
+    __shared__ double red[2 * NT / 64];
+    gloop(a, [&](const Dom &d, int wg) { pass_xmax(d, a.solve, wg, xmax_wgs(d), (char *)red); });
+}
+
+__global__ __launch_bounds__(64) void kg_pmean(GArgs a)
+{
+    gloop(a, [&](const Dom &d, int) { pass_pmean(d, xmax_wgs(d)); });
+}
+
+int march_threads(int corr) { return corr ? MTC : MT; }
+
+template <typename T>
+static const void *group_fn(const GVariant &v)
+{
+    switch (v.kind) {
+    case PK_RHS: return v.two ? (const void *)kg_rhs<true> : (const void *)kg_rhs<false>;
+    case PK_RESID: return (const void *)kg_resid;
+    case PK_CORR: return v.two ? (const void *)kg_corr<true> : (const void *)kg_corr<false>;
+    case PK_XFWD_RHS: return v.nth == 512 ? (const void *)kg_xfwd<T, SRC_RHS, 512> : (const void *)kg_xfwd<T, SRC_RHS, NT>;
+    case PK_XFWD_RESID:
+        return v.nth == 512 ? (const void *)kg_xfwd<T, SRC_RESID, 512> : (const void *)kg_xfwd<T, SRC_RESID, NT>;
+    case PK_YF: return v.nth == 512 ? (const void *)kg_y<T, false, 512> : (const void *)kg_y<T, false, NT>;
+    case PK_YI: return v.nth == 512 ? (const void *)kg_y<T, true, 512> : (const void *)kg_y<T, true, NT>;
+    case PK_Z:
+        return v.smax <= 4 ? (const void *)kg_z<T, 4> : (v.smax <= 8 ? (const void *)kg_z<T, 8> : (const void *)kg_z<T, 16>);
+    case PK_XINV_STORE:
+        return v.nth == 512 ? (const void *)kg_xinv<T, XOUT_STORE, 512> : (const void *)kg_xinv<T, XOUT_STORE, NT>;
+    case PK_XINV_ACCUM:
+        return v.nth == 512 ? (const void *)kg_xinv<T, XOUT_ACCUM, 512> : (const void *)kg_xinv<T, XOUT_ACCUM, NT>;
+    case PK_XMAX: return (const void *)kg_xmax;
+    case PK_PMEAN: return (const void *)kg_pmean;
+    }
+    return nullptr;
+}
+
+static int group_threads(const GVariant &v)
+{
+    switch (v.kind) {
+    case PK_RHS:
+    case PK_RESID: return MT;
+    case PK_CORR: return MTC;
+    case PK_Z:
+    case PK_XMAX: return NT;
+    case PK_PMEAN: return 64;
+    default: return v.nth;
+    }
+}
+
+hipError_t launch_group(const GVariant &v, int prec, const GArgs &a, int grid, size_t lds, hipStream_t s)
+{
+    const void *fn = prec == PREC_F64 ? group_fn<double>(v) : group_fn<float>(v);
+    if (!fn) return hipErrorInvalidValue;
+    hipError_t e = lds_attr(fn, lds);
+    if (e != hipSuccess) return e;
+    GArgs arg = a;
+    void *args[] = {&arg};
+    return hipLaunchKernel(fn, dim3(grid), dim3(group_threads(v)), args, lds, s);
+}
+
+hipError_t group_occupancy(const GVariant &v, int prec, size_t lds, int *blocks_per_cu)
+{
+    const void *fn = prec == PREC_F64 ? group_fn<double>(v) : group_fn<float>(v);
+    if (!fn) return hipErrorInvalidValue;
+    hipError_t e = lds_attr(fn, lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, group_threads(v), lds);
 }
 
 } // namespace pcx

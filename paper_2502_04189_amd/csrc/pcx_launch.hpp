@@ -24,12 +24,39 @@ hipError_t min_to_host(const double *a, long long n, hipStream_t s, double *out)
 
 namespace pcx {
 
+// ------------------------------------------------------ grouped (batched)
+// One launch of one pass over tiles of many domains: item i of the launch is
+// tile items[i].tile of domain items[i].dom (dom == GSKIP: no work).  Items
+// are processed by workgroup b in the order b, b + grid, b + 2 grid, ...
+constexpr uint32_t GSKIP = 0xffffffffu;
+struct GItem {
+    uint32_t dom, tile;
+};
+struct GArgs {
+    const Dom *doms;
+    const GItem *items;
+    int nitems;
+    int solve;
+};
+// Which kernel a group runs: the pass kind (PK_*), its workgroup size, and
+// the per-pass template choice (RHS / correction: a second halo item per
+// thread; z: levels per lane).
+struct GVariant {
+    int kind, nth, two, smax;
+};
+hipError_t launch_group(const GVariant &v, int prec, const GArgs &a, int grid, size_t lds, hipStream_t s);
+// resident workgroups per CU of a group's kernel
+hipError_t group_occupancy(const GVariant &v, int prec, size_t lds, int *blocks_per_cu);
+// workgroup size of the marching stencil kernels (RHS and residual; correction)
+int march_threads(int corr);
+
 // ---------------------------------------------------------------- batched
 // phases of a batch: 8 for the first solve (RHS, x, y, z, y, x, maxima,
 // correction) and 7 per further solve, for up to MAXIT solves
 constexpr int MAXPH = 96;
 static_assert(MAXPH >= 8 + 7 * (MAXIT - 1), "phase table too small for MAXIT solves");
-enum { PK_RHS = 0, PK_RESID, PK_XFWD_RHS, PK_XFWD_RESID, PK_YF, PK_Z, PK_YI, PK_XINV_STORE, PK_XINV_ACCUM, PK_PMEAN, PK_CORR };
+enum { PK_RHS = 0, PK_RESID, PK_XFWD_RHS, PK_XFWD_RESID, PK_YF, PK_Z, PK_YI, PK_XINV_STORE, PK_XINV_ACCUM, PK_PMEAN, PK_CORR,
+       PK_XMAX };
 
 struct Item {
     uint16_t dom, phase;

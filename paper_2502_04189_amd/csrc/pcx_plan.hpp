@@ -40,6 +40,12 @@ pcx_status build_domain(const pcx_grid &g, int prec, const Shapes &sh, const Rad
 size_t lds_x(const Dom &d, int prec);
 size_t lds_y(const Dom &d, int prec);
 size_t lds_z(const Dom &d, int prec);
+// grouped (batched) launches: the kernel variant, tile count and LDS bytes
+// of pass `kind` for domain d
+struct GVariant;
+GVariant variant_of(const Dom &d, int kind, int smax);
+long group_tiles(const Dom &d, int kind);
+size_t group_lds(const Dom &d, int kind, int prec);
 
 } // namespace pcx
 

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <functional>
 #include <sstream>
 #include <vector>
 
@@ -113,7 +114,7 @@ struct Scratch {
 };
 } // namespace
 
-pcx_status autotune_class(const pcx_grid &g, int prec, hipStream_t s, TuneParams &best, RadixChoice &brc)
+pcx_status autotune_class(const pcx_grid &g, int prec, hipStream_t s, TuneParams &best, RadixChoice &brc, bool grouped)
 {
     const size_t ncell = (size_t)g.nx * g.ny * g.nz;
     const int M = g.nx / 2;
@@ -139,6 +140,61 @@ pcx_status autotune_class(const pcx_grid &g, int prec, hipStream_t s, TuneParams
     if (!s1 || !s2 || !f || !rr || !stats || !ppart) return fail(PCX_ERR_NOMEM, "autotune scratch allocation failed");
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(PCX_ERR_HIP, "hipEventCreate");
+    // grouped launches (the batch's kernels): a one-entry domain table and an
+    // item list of every tile of the pass, as the batch builds them
+    Dom *ddom = (Dom *)sc.alloc(sizeof(Dom));
+    const size_t max_items = (size_t)std::max<long>({(long)g.ny * g.nz, (long)nlx * g.nz, (long)nlx * g.ny,
+                                                     (long)(ncell / 64 + 64)}) + 64;
+    GItem *ditems = (GItem *)sc.alloc(max_items * sizeof(GItem));
+    if (!ddom || !ditems) return fail(PCX_ERR_NOMEM, "autotune scratch allocation failed");
+    std::vector<GItem> hitems;
+    // uploads d and the tile list of pass `kind`; returns false when it does not fit
+    auto prep_group = [&](const Dom &d, int kind, int smax, GVariant &v, GArgs &a, size_t &lds) {
+        const long t = group_tiles(d, kind);
+        if (t <= 0 || (size_t)t > max_items) return false;
+        hitems.resize(t);
+        for (long q = 0; q < t; ++q) hitems[q] = GItem{0u, (uint32_t)(kind == PK_Z ? t - 1 - q : q)};
+        if (hipMemcpy(ddom, &d, sizeof(Dom), hipMemcpyHostToDevice) != hipSuccess) return false;
+        if (hipMemcpy(ditems, hitems.data(), t * sizeof(GItem), hipMemcpyHostToDevice) != hipSuccess) return false;
+        v = variant_of(d, kind, smax);
+        a = GArgs{ddom, ditems, (int)t, 0};
+        lds = group_lds(d, kind, prec);
+        return true;
+    };
+    // launches of pass kinds k1 (and k2) of d, grouped or single-domain
+    auto passes = [&](const Dom &d, int smax, size_t lx, size_t ly, size_t lz, int k1, int k2) {
+        std::vector<std::pair<GVariant, std::pair<GArgs, size_t>>> gl;
+        if (grouped) {
+            // two passes share the item buffer only when they have the same tiles
+            for (int k : {k1, k2}) {
+                if (k < 0) continue;
+                GVariant v; GArgs a; size_t lds;
+                if (!prep_group(d, k, smax, v, a, lds)) return std::function<hipError_t()>();
+                gl.push_back({v, {a, lds}});
+            }
+        }
+        return std::function<hipError_t()>([=, &d]() {
+            hipError_t e = hipSuccess;
+            if (grouped) {
+                for (auto &x : gl)
+                    if (e == hipSuccess) e = launch_group(x.first, prec, x.second.first, group_tiles(d, x.first.kind),
+                                                          x.second.second, s);
+                return e;
+            }
+            for (int k : {k1, k2}) {
+                if (k < 0 || e != hipSuccess) continue;
+                switch (k) {
+                case PK_XFWD_RHS: e = launch_xfwd(d, prec, SRC_RHS, lx, s); break;
+                case PK_XINV_STORE: e = launch_xinv(d, prec, XOUT_STORE, 0, lx, s); break;
+                case PK_YF: e = launch_y(d, prec, false, ly, s); break;
+                case PK_YI: e = launch_y(d, prec, true, ly, s); break;
+                case PK_Z: e = launch_z(d, prec, smax, lz, s); break;
+                default: break;
+                }
+            }
+            return e;
+        });
+    };
 
     auto make = [&](const TuneParams &tp, const RadixChoice &rc, Dom &d, DomTables &tb, size_t &lx, size_t &ly, size_t &lz, int &smax) {
         Shapes sh;
@@ -190,11 +246,9 @@ pcx_status autotune_class(const pcx_grid &g, int prec, hipStream_t s, TuneParams
                 rc.x = rx;
                 Dom d; DomTables tb; size_t lx, ly, lz; int smax;
                 if (make(tp, rc, d, tb, lx, ly, lz, smax) != PCX_OK) { if (tb.dev) (void)hipFree(tb.dev); continue; }
-                float t = timeit([&]() {
-                    hipError_t e = launch_xfwd(d, prec, SRC_RHS, lx, s);
-                    if (e == hipSuccess) e = launch_xinv(d, prec, XOUT_STORE, 0, lx, s);
-                    return e;
-                });
+                // x forward and inverse have the same tiles, so the item list is shared
+                auto fn = passes(d, smax, lx, ly, lz, PK_XFWD_RHS, PK_XINV_STORE);
+                float t = fn ? timeit(fn) : 1e30f;
                 (void)hipFree(tb.dev);
                 if (t < bt) { bt = t; best.tj = tj; brc.x = rx; }
             }
@@ -213,11 +267,8 @@ pcx_status autotune_class(const pcx_grid &g, int prec, hipStream_t s, TuneParams
                 rc.y = ry;
                 Dom d; DomTables tb; size_t lx, ly, lz; int smax;
                 if (make(tp, rc, d, tb, lx, ly, lz, smax) != PCX_OK) { if (tb.dev) (void)hipFree(tb.dev); continue; }
-                float t = timeit([&]() {
-                    hipError_t e = launch_y(d, prec, false, ly, s);
-                    if (e == hipSuccess) e = launch_y(d, prec, true, ly, s);
-                    return e;
-                });
+                auto fn = passes(d, smax, lx, ly, lz, PK_YF, PK_YI);
+                float t = fn ? timeit(fn) : 1e30f;
                 (void)hipFree(tb.dev);
                 if (t < bt) { bt = t; best.tk = tk; brc.y = ry; }
             }
@@ -232,7 +283,8 @@ pcx_status autotune_class(const pcx_grid &g, int prec, hipStream_t s, TuneParams
             tp.zg = G;
             Dom d; DomTables tb; size_t lx, ly, lz; int smax;
             if (make(tp, brc, d, tb, lx, ly, lz, smax) != PCX_OK) { if (tb.dev) (void)hipFree(tb.dev); continue; }
-            float t = timeit([&]() { return launch_z(d, prec, smax, lz, s); });
+            auto fn = passes(d, smax, lx, ly, lz, PK_Z, -1);
+            float t = fn ? timeit(fn) : 1e30f;
             (void)hipFree(tb.dev);
             if (t < bt) { bt = t; best.zg = G; }
         }

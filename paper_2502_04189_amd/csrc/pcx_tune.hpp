@@ -19,7 +19,9 @@ struct TuneCache {
 };
 
 // Times candidate shapes of each pass on scratch data of this grid and
-// returns the fastest per pass.
-pcx_status autotune_class(const pcx_grid &g, int prec, hipStream_t s, TuneParams &tp, RadixChoice &rc);
+// returns the fastest per pass.  grouped: time the batch's grouped kernels
+// (one-domain item lists), else the single-domain kernels of a plan.
+pcx_status autotune_class(const pcx_grid &g, int prec, hipStream_t s, TuneParams &tp, RadixChoice &rc,
+                          bool grouped);
 
 } // namespace pcx
