@@ -178,6 +178,32 @@ pcx_status pcx_batch_destroy(pcx_batch batch);
  * host threads are serialized by the library. */
 pcx_status pcx_rho_min(const double *rho, int64_t n, void *stream, double *out);
 
+/* Allocation-free step, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same computation, arguments and report as pcx_plan_create +
+ * pcx_step + pcx_plan_destroy on (grid, opts), with the plan's tables and
+ * workspace placed in a fixed device array of PCX_NOALLOC_SCRATCH_BYTES that
+ * the library holds on each device it runs on until the process ends.  Calls
+ * no hipMalloc/hipFree.  The grid's need (tables + workspace, see
+ * pcx_noalloc_scratch_need) must fit the array, else UNSUPPORTED before any
+ * device call: 128^3 fits in both precisions, 256^3 does not.
+ * opts->autotune must be 0 (INVALID otherwise); a tune_cache is read, never
+ * written.  The tables are uploaded from host memory on `stream`, and the
+ * call waits for that upload (so for earlier work on the stream) before it
+ * queues the step; with report == NULL the step itself is then only queued.
+ * Every call on one device shares that device's array and leaves its last
+ * contents there (each step clears what it accumulates): calls whose work
+ * overlaps on one device -- on different streams, or from several host
+ * threads -- race on it and must be serialized by the caller. */
+#define PCX_NOALLOC_SCRATCH_BYTES (64u << 20)
+pcx_status pcx_step_noalloc(const pcx_grid *grid, const pcx_options *opts, double dt, double rho0,
+                            const double *rho, const double *p_star,
+                            const double *u_in, const double *v_in, const double *w_in,
+                            double *u_out, double *v_out, double *w_out, double *p_out,
+                            void *stream, pcx_report *report);
+/* Device bytes pcx_step_noalloc needs for (grid, opts); host-only. */
+pcx_status pcx_noalloc_scratch_need(const pcx_grid *grid, const pcx_options *opts, size_t *bytes);
+
 /* Refinement stop test used by the refined forms: nonzero when
  * rel_residual <= rtol and the error left after the last update, estimated
  * from the observed contraction q = update_inf / prev_update_inf (< 1) as

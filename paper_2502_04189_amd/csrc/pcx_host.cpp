@@ -181,7 +181,10 @@ void choose_shapes(const pcx_grid &g, int prec, const TuneParams *tp, Shapes &sh
     sh.batch = batch;
 }
 
-pcx_status build_domain(const pcx_grid &g, int prec, const Shapes &sh, const RadixChoice *rc, DomTables &tb, Dom &d)
+// Domain descriptor and the host image of its device tables (eigenvalues, z
+// coefficients, twiddles); the table pointers of d are bound by bind_tables
+// once the image sits in device memory.
+void make_domain(const pcx_grid &g, int prec, const Shapes &sh, const RadixChoice *rc, HostTables &ht, Dom &d)
 {
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const int M = nx / 2;
@@ -291,26 +294,40 @@ pcx_status build_domain(const pcx_grid &g, int prec, const Shapes &sh, const Rad
     size_t o_dcx = g.bc_x == PCX_BC_WALL ? addr(4 * nx, false) : 0;
     size_t o_dcy = g.bc_y == PCX_BC_WALL ? addr(4 * ny, false) : 0;
 
-    tb.bytes = b.bytes.size();
+    ht.o_dzf = o_dzf; ht.o_idzf = o_idzf; ht.o_idzc = o_idzc; ht.o_rzlo = o_rzlo; ht.o_rzhi = o_rzhi;
+    ht.o_za = o_za; ht.o_zb = o_zb; ht.o_zc = o_zc; ht.o_dzfs = o_dzfs; ht.o_lx = o_lx; ht.o_ly = o_ly;
+    ht.o_twr = o_twr; ht.o_twx = o_twx; ht.o_twy = o_twy; ht.o_dcx = o_dcx; ht.o_dcy = o_dcy;
+    ht.bytes.swap(b.bytes);
+    fill_fft(d.fx, M, rc && !rc->x.empty() ? rc->x : default_radices(M));
+    fill_fft(d.fy, ny, rc && !rc->y.empty() ? rc->y : default_radices(ny));
+}
+
+void bind_tables(Dom &d, const HostTables &ht, char *base)
+{
+    d.dzf = (const double *)(base + ht.o_dzf);
+    d.idzf = (const double *)(base + ht.o_idzf);
+    d.idzc = (const double *)(base + ht.o_idzc);
+    d.rzlo = (const double *)(base + ht.o_rzlo);
+    d.rzhi = (const double *)(base + ht.o_rzhi);
+    d.za = base + ht.o_za; d.zb = base + ht.o_zb; d.zc = base + ht.o_zc; d.dzf_s = base + ht.o_dzfs;
+    d.lamx = base + ht.o_lx; d.lamy = base + ht.o_ly;
+    d.twr = base + ht.o_twr;
+    d.dctx = d.bcx == BC_WALL ? base + ht.o_dcx : nullptr;
+    d.dcty = d.bcy == BC_WALL ? base + ht.o_dcy : nullptr;
+    d.fx.tw = base + ht.o_twx;
+    d.fy.tw = base + ht.o_twy;
+}
+
+pcx_status build_domain(const pcx_grid &g, int prec, const Shapes &sh, const RadixChoice *rc, DomTables &tb, Dom &d)
+{
+    HostTables ht;
+    make_domain(g, prec, sh, rc, ht, d);
+    tb.bytes = ht.bytes.size();
     hipError_t e = hipMalloc(&tb.dev, tb.bytes);
     if (e != hipSuccess) { tb.dev = nullptr; return fail(PCX_ERR_NOMEM, "hipMalloc(tables) failed"); }
-    e = hipMemcpy(tb.dev, b.bytes.data(), tb.bytes, hipMemcpyHostToDevice);
+    e = hipMemcpy(tb.dev, ht.bytes.data(), tb.bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail(PCX_ERR_HIP, std::string("hipMemcpy(tables): ") + hipGetErrorString(e));
-    char *base = (char *)tb.dev;
-    d.dzf = (const double *)(base + o_dzf);
-    d.idzf = (const double *)(base + o_idzf);
-    d.idzc = (const double *)(base + o_idzc);
-    d.rzlo = (const double *)(base + o_rzlo);
-    d.rzhi = (const double *)(base + o_rzhi);
-    d.za = base + o_za; d.zb = base + o_zb; d.zc = base + o_zc; d.dzf_s = base + o_dzfs;
-    d.lamx = base + o_lx; d.lamy = base + o_ly;
-    d.twr = base + o_twr;
-    d.dctx = g.bc_x == PCX_BC_WALL ? base + o_dcx : nullptr;
-    d.dcty = g.bc_y == PCX_BC_WALL ? base + o_dcy : nullptr;
-    fill_fft(d.fx, M, rc && !rc->x.empty() ? rc->x : default_radices(M));
-    d.fx.tw = base + o_twx;
-    fill_fft(d.fy, ny, rc && !rc->y.empty() ? rc->y : default_radices(ny));
-    d.fy.tw = base + o_twy;
+    bind_tables(d, ht, (char *)tb.dev);
     return PCX_OK;
 }
 
@@ -339,26 +356,17 @@ static pcx_status plan_free(pcx_plan P)
 {
     if (!P) return PCX_OK;
     if (P->tables.dev) (void)hipFree(P->tables.dev);
-    if (P->s1) (void)hipFree(P->s1);
-    if (P->s2) (void)hipFree(P->s2);
-    if (P->f) (void)hipFree(P->f);
-    if (P->r) (void)hipFree(P->r);
-    if (P->stats) (void)hipFree(P->stats);
-    if (P->psum) (void)hipFree(P->psum);
-    if (P->ppart) (void)hipFree(P->ppart);
-    if (P->xpart) (void)hipFree(P->xpart);
+    if (P->ws) (void)hipFree(P->ws);
     for (auto e : P->ev) (void)hipEventDestroy(e);
     delete P;
     return PCX_OK;
 }
 
-extern "C" pcx_status pcx_plan_create(const pcx_grid *grid, const pcx_options *opts, pcx_plan *out)
+namespace pcx {
+
+pcx_status plan_options(const pcx_options *opts, pcx_options &o)
 {
-    if (!out) return fail(PCX_ERR_INVALID, "out is NULL");
-    *out = nullptr;
-    pcx_status st = validate_grid(grid);
-    if (st != PCX_OK) return st;
-    pcx_options o = {PCX_FP64, 1e-10, 8, 0, 0, 0, nullptr};
+    o = {PCX_FP64, 1e-10, 8, 0, 0, 0, nullptr};
     if (opts) o = *opts;
     if (o.precision != PCX_FP64 && o.precision != PCX_FP32_REFINED) return fail(PCX_ERR_INVALID, "unknown precision");
     if (!(o.rtol > 0.0)) o.rtol = 1e-10;
@@ -366,24 +374,23 @@ extern "C" pcx_status pcx_plan_create(const pcx_grid *grid, const pcx_options *o
     if (o.max_iters > MAXIT) o.max_iters = MAXIT;
     if (o.fixed_iters <= 0) o.fixed_iters = 3;
     if (o.fixed_iters > o.max_iters) o.fixed_iters = o.max_iters;
-    int ndev = 0;
-    hipError_t e = hipGetDeviceCount(&ndev);
-    if (e != hipSuccess || ndev < 1) return fail(PCX_ERR_HIP, "no HIP device available");
+    return PCX_OK;
+}
 
-    pcx_plan P = new pcx_plan_s();
+pcx_status plan_prepare(pcx_plan_s *P, const pcx_grid *grid, const pcx_options &o, HostTables &ht)
+{
     P->grid = *grid;
     P->zf.assign(grid->zf, grid->zf + grid->nz + 1);
     P->grid.zf = P->zf.data();
     P->opt = o;
     P->prec = o.precision == PCX_FP64 ? PREC_F64 : PREC_F32;
-    (void)hipGetDevice(&P->device);
     TuneParams tp;
     RadixChoice rc;
     TuneCache cache;
     bool have = o.tune_cache && cache.load(o.tune_cache) && cache.lookup(P->grid, P->prec, tp, rc);
     if (!have && o.autotune) {
-        st = autotune_class(P->grid, P->prec, nullptr, tp, rc, false);
-        if (st != PCX_OK) { delete P; return st; }
+        pcx_status st = autotune_class(P->grid, P->prec, nullptr, tp, rc, false);
+        if (st != PCX_OK) return st;
         have = true;
         if (o.tune_cache) {
             cache.store(P->grid, P->prec, tp, rc);
@@ -391,27 +398,48 @@ extern "C" pcx_status pcx_plan_create(const pcx_grid *grid, const pcx_options *o
         }
     }
     choose_shapes(P->grid, P->prec, have ? &tp : nullptr, P->sh, false);
-    st = build_domain(P->grid, P->prec, P->sh, have ? &rc : nullptr, P->tables, P->dom);
-    if (st != PCX_OK) { plan_free(P); return st; }
+    make_domain(P->grid, P->prec, P->sh, have ? &rc : nullptr, ht, P->dom);
+    return PCX_OK;
+}
+
+WsLayout plan_layout(const pcx_plan_s *P)
+{
     const size_t csz = P->prec == PREC_F64 ? 16 : 8;
-    const size_t nspec = (size_t)P->dom.nl * grid->ny * grid->nz;
-    const size_t ncell = (size_t)grid->nx * grid->ny * grid->nz;
-    if (hipMalloc(&P->s1, nspec * csz) != hipSuccess || hipMalloc(&P->s2, nspec * csz) != hipSuccess ||
-        hipMalloc(&P->stats, NSTAT * sizeof(unsigned long long)) != hipSuccess ||
-        hipMalloc(&P->psum, (size_t)grid->nz * sizeof(double)) != hipSuccess ||
-        hipMalloc(&P->xpart, (size_t)2 * xslots(P->dom) * sizeof(double)) != hipSuccess) {
-        plan_free(P);
-        return fail(PCX_ERR_NOMEM, "workspace allocation failed");
-    }
-    if (hipMalloc(&P->f, ncell * sizeof(double)) != hipSuccess ||
-        (P->prec == PREC_F32 &&
-         (hipMalloc(&P->r, ncell * sizeof(double)) != hipSuccess ||
-          hipMalloc(&P->ppart, ((size_t)xslots(P->dom) + PMEAN_LEN) * sizeof(double)) != hipSuccess))) {
-        plan_free(P);
-        return fail(PCX_ERR_NOMEM, "workspace allocation failed (f, r)");
-    }
-    P->ws_bytes = 2 * nspec * csz + NSTAT * 8 + grid->nz * 8 + P->tables.bytes + ncell * 8 + (P->r ? ncell * 8 : 0) +
-                  (P->ppart ? ((size_t)xslots(P->dom) + PMEAN_LEN) * 8 : 0) + (size_t)2 * xslots(P->dom) * 8;
+    const size_t nspec = (size_t)P->dom.nl * P->grid.ny * P->grid.nz;
+    const size_t ncell = (size_t)P->grid.nx * P->grid.ny * P->grid.nz;
+    const bool ref = P->prec == PREC_F32;
+    WsLayout L;
+    size_t off = 0;
+    auto put = [&](size_t bytes) {
+        size_t o = off;
+        off = (off + bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    L.s1 = put(nspec * csz);
+    L.s2 = put(nspec * csz);
+    L.f = put(ncell * sizeof(double));
+    L.r = ref ? put(ncell * sizeof(double)) : 0;
+    L.stats = put(NSTAT * sizeof(unsigned long long));
+    L.psum = put((size_t)P->grid.nz * sizeof(double));
+    L.xpart = put((size_t)2 * xslots(P->dom) * sizeof(double));
+    L.ppart = ref ? put(((size_t)xslots(P->dom) + PMEAN_LEN) * sizeof(double)) : 0;
+    L.total = off;
+    return L;
+}
+
+void plan_bind(pcx_plan_s *P, const HostTables &ht, char *tables, char *ws, const WsLayout &L)
+{
+    const bool ref = P->prec == PREC_F32;
+    bind_tables(P->dom, ht, tables);
+    P->s1 = ws + L.s1;
+    P->s2 = ws + L.s2;
+    P->f = (double *)(ws + L.f);
+    P->r = ref ? (double *)(ws + L.r) : nullptr;
+    P->stats = (unsigned long long *)(ws + L.stats);
+    P->psum = (double *)(ws + L.psum);
+    P->xpart = (double *)(ws + L.xpart);
+    P->ppart = ref ? (double *)(ws + L.ppart) : nullptr;
+    P->ws_bytes = L.total + ht.bytes.size();
     P->dom.s1 = P->s1;
     P->dom.s2 = P->s2;
     P->dom.f = P->f;
@@ -423,6 +451,46 @@ extern "C" pcx_status pcx_plan_create(const pcx_grid *grid, const pcx_options *o
     P->lx = lds_x(P->dom, P->prec);
     P->ly = lds_y(P->dom, P->prec);
     P->lzs = lds_z(P->dom, P->prec);
+}
+
+} // namespace pcx
+
+extern "C" pcx_status pcx_plan_create(const pcx_grid *grid, const pcx_options *opts, pcx_plan *out)
+{
+    if (!out) return fail(PCX_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    pcx_status st = validate_grid(grid);
+    if (st != PCX_OK) return st;
+    pcx_options o;
+    st = plan_options(opts, o);
+    if (st != PCX_OK) return st;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev < 1) return fail(PCX_ERR_HIP, "no HIP device available");
+
+    pcx_plan P = new pcx_plan_s();
+    (void)hipGetDevice(&P->device);
+    HostTables ht;
+    st = plan_prepare(P, grid, o, ht);
+    if (st != PCX_OK) { delete P; return st; }
+    P->tables.bytes = ht.bytes.size();
+    if (hipMalloc(&P->tables.dev, P->tables.bytes) != hipSuccess) {
+        P->tables.dev = nullptr;
+        plan_free(P);
+        return fail(PCX_ERR_NOMEM, "hipMalloc(tables) failed");
+    }
+    e = hipMemcpy(P->tables.dev, ht.bytes.data(), P->tables.bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        plan_free(P);
+        return fail(PCX_ERR_HIP, std::string("hipMemcpy(tables): ") + hipGetErrorString(e));
+    }
+    const WsLayout L = plan_layout(P);
+    if (hipMalloc(&P->ws, L.total) != hipSuccess) {
+        P->ws = nullptr;
+        plan_free(P);
+        return fail(PCX_ERR_NOMEM, "workspace allocation failed");
+    }
+    plan_bind(P, ht, (char *)P->tables.dev, (char *)P->ws, L);
     *out = P;
     return PCX_OK;
 }

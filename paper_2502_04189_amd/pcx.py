@@ -78,6 +78,9 @@ def lib():
         "pcx_batch_reports": (st, [vp, C.POINTER(PcxReport)]),
         "pcx_batch_destroy": (st, [vp]),
         "pcx_rho_min": (st, [vp, C.c_int64, vp, _DP]),
+        "pcx_step_noalloc": (st, [C.POINTER(PcxGrid), C.POINTER(PcxOptions), dbl, dbl] + [vp] * 9 +
+                             [vp, C.POINTER(PcxReport)]),
+        "pcx_noalloc_scratch_need": (st, [C.POINTER(PcxGrid), C.POINTER(PcxOptions), C.POINTER(C.c_size_t)]),
         "pcx_refine_should_stop": (i32, [dbl, dbl, dbl, dbl, dbl]),
         "pcx_status_str": (C.c_char_p, [st]),
         "pcx_last_error": (C.c_char_p, []),
@@ -190,6 +193,31 @@ class Plan:
         n = C.c_int32()
         _check(lib().pcx_plan_pass_times(self._h, buf, cap, C.byref(n)), "pcx_plan_pass_times")
         return [(lib().pcx_plan_pass_name(self._h, i).decode(), buf[i]) for i in range(min(n.value, cap))]
+
+
+def noalloc_scratch_need(grid, precision="fp64"):
+    """Device bytes pcx_step_noalloc needs for `grid` (host-only)."""
+    g = make_grid(grid)
+    o = make_options(precision)
+    n = C.c_size_t()
+    _check(lib().pcx_noalloc_scratch_need(C.byref(g), C.byref(o), C.byref(n)), "pcx_noalloc_scratch_need")
+    return n.value
+
+
+def step_noalloc(grid, dt, rho0, rho, pstar, u, v, w, u_out, v_out, w_out, p_out, precision="fp64",
+                 rtol=1e-10, max_iters=8, fixed_iters=0, check_finite=False, stream=None, report=True):
+    """pcx_step_noalloc: one step with the library's fixed device scratch array
+    (no device allocation).  Outputs are caller tensors; returns (status,
+    report dict or None)."""
+    g = make_grid(grid)
+    o = make_options(precision, rtol, max_iters, fixed_iters, check_finite)
+    sh = (grid.nz, grid.ny, grid.nx)
+    ptrs = [_ptr(t, sh, n) for t, n in zip((rho, pstar, u, v, w, u_out, v_out, w_out, p_out),
+                                           ("rho", "pstar", "u", "v", "w", "u_out", "v_out", "w_out", "p_out"))]
+    rep = PcxReport()
+    st = lib().pcx_step_noalloc(C.byref(g), C.byref(o), float(dt), float(rho0), *ptrs, _stream_handle(stream),
+                                C.byref(rep) if report else None)
+    return st, (rep.as_dict() if report else None)
 
 
 class Batch:

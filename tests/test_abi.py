@@ -102,3 +102,29 @@ def test_refine_stop_logic(L):
     assert got == [0, 0, 1, 0, 0]
     assert L.pcx_refine_should_stop(float("nan"), 0.0, 1.0, 1.0, rtol) == 0
     assert L.pcx_refine_should_stop(1e-12, 2.0, 1.0, 1.0, rtol) == 0     # diverging
+
+
+def test_noalloc_sizes_and_rejections(L):
+    """The allocation-free step: scratch need of the stated sizes, and the
+    host-side rejections that come before any device call."""
+    fits = W.GridSpec(128, 128, 128, 1.0, 1.0, W.zf_uniform(128, 1.0))
+    big = W.GridSpec(256, 256, 256, 1.0, 1.0, W.zf_uniform(256, 1.0))
+    cap = 64 << 20
+    for prec in ("fp64", "fp32_refined"):
+        assert 0 < P.noalloc_scratch_need(fits, prec) <= cap
+        assert P.noalloc_scratch_need(big, prec) > cap
+    # a grid beyond the array: UNSUPPORTED before any device call (this
+    # host has no GPU; the dummy pointers are never dereferenced)
+    dummy = [C.c_void_p(4096 * (i + 1)) for i in range(9)]
+    g = P.make_grid(big)
+    o = P.make_options("fp64")
+    st = L.pcx_step_noalloc(C.byref(g), C.byref(o), 1e-3, 1.0, *dummy, None, None)
+    assert st == P.PCX_ERR_UNSUPPORTED
+    assert "scratch" in L.pcx_last_error().decode()
+    o = P.make_options("fp64", autotune=True)
+    g = P.make_grid(fits)
+    assert L.pcx_step_noalloc(C.byref(g), C.byref(o), 1e-3, 1.0, *dummy, None, None) == P.PCX_ERR_INVALID
+    bad = W.GridSpec(40, 32, 16, 1.0, 1.0, W.zf_uniform(16, 1.0))
+    g = P.make_grid(bad)
+    o = P.make_options("fp64")
+    assert L.pcx_step_noalloc(C.byref(g), C.byref(o), 1e-3, 1.0, *dummy, None, None) == P.PCX_ERR_UNSUPPORTED
