@@ -265,19 +265,32 @@ def run_batch(steps, warmup, ndom):
     sms = e0.elapsed_time(e1) / steps
     # the same domains batched in FP64 (one solve each): the batching gain at
     # equal arithmetic
-    b64 = pcx.Batch(doms, "fp64", tune_cache=cache)
-    for _ in range(warmup):
-        b64.launch()
-    torch.cuda.synchronize()
-    e0.record(st)
-    for _ in range(steps):
-        b64.launch()
-    e1.record(st)
-    torch.cuda.synchronize()
-    b64ms = e0.elapsed_time(e1) / steps
+    def timed(batch):
+        for _ in range(warmup):
+            batch.launch()
+        torch.cuda.synchronize()
+        e0.record(st)
+        for _ in range(steps):
+            batch.launch()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    b64 = pcx.Batch(doms, "fp64", autotune=True, tune_cache=cache)
+    b64ms = timed(b64)
     _, st64 = b64.reports()
-    log(f"batch: {bms:.3f} ms per launch ({cells} cells), fp64 batch {b64ms:.3f} ms, sequential fp64 {sms:.3f} ms, "
-        f"create {t_create:.1f} s")
+    b64.close()
+    # both forms on the default (untuned) shapes: what the tuning buys
+    bdef = pcx.Batch(doms, "fp32_refined")
+    bdefms = timed(bdef)
+    bdef.close()
+    bdef = pcx.Batch(doms, "fp64")
+    bdef64ms = timed(bdef)
+    bdef.close()
+    solves = reps[0]["solves"]
+    log(f"batch: {bms:.3f} ms per launch ({cells} cells), default shapes {bdefms:.3f} ms, fp64 batch {b64ms:.3f} ms "
+        f"(default shapes {bdef64ms:.3f} ms), "
+        f"sequential fp64 {sms:.3f} ms, create {t_create:.1f} s")
     return {"domains": len(doms), "cells": cells, "ms_per_launch": round(bms, 4),
             "value": round(cells / (bms * 1e-3) / 1e6, 1), "unit": "Mpts/s",
             "solves_per_domain": reps[0]["solves"], "worst_rel_residual": worst,
@@ -285,7 +298,35 @@ def run_batch(steps, warmup, ndom):
             "sequential_fp64_ms": round(sms, 4), "speedup_vs_sequential_fp64": round(sms / bms, 3),
             "fp64_batch_ms": round(b64ms, 4), "fp64_batch_status": st64,
             "fp64_batch_speedup_vs_sequential_fp64": round(sms / b64ms, 3),
+            "refined_default_shapes_ms": round(bdefms, 4),
+            "fp64_default_shapes_ms": round(bdef64ms, 4),
+            # HBM fraction of the per-domain byte model: 176 B/cell for one
+            # FP64 solve, 176 + 64 (s - 1) for s FP32 solves
+            "fp64_batch_hbm_frac_model": round(cells * 176.0 / (b64ms * 1e-3) / 8e12, 4),
+            "refined_batch_hbm_frac_model": round(cells * (176.0 + 64.0 * (solves - 1)) / (bms * 1e-3) / 8e12, 4),
             "create_s_incl_autotune": round(t_create, 2)}
+
+
+def prof_batch(steps, warmup, ndom):
+    """The batch alone, for a kernel trace: FP64 then refined launches."""
+    import torch
+    from paper_2502_04189_amd import pcx
+    from paper_2502_04189_amd import workloads as W
+    cases = W.config4(ndom=ndom)
+    doms = []
+    for c in cases:
+        f = [torch.from_numpy(a).to("cuda") for a in c.fields()]
+        o = [torch.empty(c.grid.shape, dtype=torch.float64, device="cuda") for _ in range(4)]
+        doms.append({"grid": c.grid, "dt": c.dt, "rho0": c.rho0, "rho": f[0], "pstar": f[1], "u": f[2],
+                     "v": f[3], "w": f[4], "u_out": o[0], "v_out": o[1], "w_out": o[2], "p_out": o[3]})
+    cache = pcx.batch_tune_cache_path()
+    for prec in ("fp64", "fp32_refined"):
+        b = pcx.Batch(doms, prec, autotune=True, tune_cache=cache)
+        for _ in range(warmup + steps):
+            b.launch()
+        torch.cuda.synchronize()
+        b.close()
+        log(f"prof batch {prec}: {warmup + steps} launches of {len(doms)} domains")
 
 
 def main():
@@ -302,6 +343,9 @@ def main():
                     help="profiling mode: a few FP64 (or --prof-refined) steps plus a 1 GiB torch copy "
                          "that calibrates the HBM byte counters; prints no JSON")
     ap.add_argument("--prof-refined", action="store_true")
+    ap.add_argument("--prof-batch", action="store_true",
+                    help="profiling mode: only the 192-domain batch, FP64 then refined (tuned shapes); "
+                         "prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is "
@@ -312,6 +356,10 @@ def main():
     from paper_2502_04189_amd import pcx
     from paper_2502_04189_amd import workloads as W
     pcx.lib()
+
+    if args.prof_batch:
+        prof_batch(args.steps, args.warmup, args.ndom)
+        return
 
     t0 = time.perf_counter()
     nb = 512 if args.n == 512 else max(1, (args.n // 64) ** 3)

@@ -151,9 +151,12 @@ const char *pcx_plan_pass_name(pcx_plan plan, int32_t i);
  * boundary conditions, solved together.  Each domain has its own grid, dt,
  * rho0 and device buffers (same rules as pcx_step), which must stay valid
  * until pcx_batch_destroy.  The work of all domains is captured at create
- * time into one HIP graph holding a single persistent kernel that pulls
- * (domain, pass, tile) items from a device queue in dependency order.
- * opts->precision selects the solve precision of every domain. */
+ * time into one HIP graph: one grouped launch per pass of the step (per
+ * kernel variant), each running that pass over the tiles of every domain,
+ * in dependency order.  opts->precision selects the solve precision of every
+ * domain; every domain runs opts->fixed_iters solves in the refined form.
+ * Outputs must not alias inputs (INVALID).  opts->autotune times tile
+ * shapes per size class on the batch's own kernels at create time. */
 typedef struct {
     pcx_grid grid;
     double dt, rho0;

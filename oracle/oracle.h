@@ -77,7 +77,7 @@ int oracle_div(const or_grid *g, const double *u, const double *v,
                const double *w, double *out);
 int oracle_apply_L(const or_grid *g, const double *p, double *out);
 double oracle_volume_mean(const or_grid *g, const double *q);
-/* Bordered dense LU: [[L, 1],[vol^T, 0]] [p; s] = [f; 0].  At most 4096 cells. */
+/* Bordered dense LU: [[L, 1],[vol^T, 0]] [p; s] = [f; 0].  At most 1024 cells. */
 int oracle_dense_poisson(const or_grid *g, const double *f, double *p);
 
 /* 1-D pieces. fft: in-place complex DFT, unnormalised, sign -1 forward. */
