@@ -28,7 +28,10 @@ constexpr int MAXIT = 12;     // max refinement solves tracked
 
 enum { PREC_F64 = 0, PREC_F32 = 1 };
 enum { BC_PER = 0, BC_WALL = 1 };
-enum { SRC_RHS = 0, SRC_RESID = 1 }; // x-transform source buffer: f or r
+// x-transform source: the stored f or r, or (the fused forms) f or r
+// evaluated by the stencil inside the x pass, never stored (f is still
+// stored in the refined form, whose residual needs it)
+enum { SRC_RHS = 0, SRC_RESID = 1, SRC_RHS_ST = 2, SRC_RESID_ST = 3 };
 enum { XOUT_STORE = 0, XOUT_ACCUM = 1 };
 
 // reduction slots (uint64 bit patterns of non-negative doubles, atomicMax)
@@ -93,6 +96,7 @@ struct Dom {
     double *ppart;                    // per x-tile wave dzf-weighted sums of p
     double *pmean;                    // [0]: volume mean of p after the last xinv pass
     double *xpart;                    // per x-tile wave max |update|, max |p| (NULL: atomics)
+    double *spart;                    // per x-tile wave max |f| or |r| of the fused stencil passes
 };
 
 // Partial-result slots of the x inverse: one per wave of each x tile.  They
@@ -101,6 +105,9 @@ struct Dom {
 constexpr int XMAX_WG = 64;
 constexpr int PMEAN_LEN = 8 + XMAX_WG;
 __host__ __device__ inline int xslots(const Dom &d) { return d.ntj * d.nz * (d.xth >> 6); }
+// partial-maximum slots of the fused stencil x passes: one per wave, one
+// wave per row of a tile
+__host__ __device__ inline int sslots(const Dom &d) { return d.ntj * d.nz * d.tj; }
 // workgroups of the reduction of those slots (pass_xmax), at most XMAX_WG
 __host__ __device__ inline int xmax_wgs(const Dom &d)
 {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -423,6 +424,7 @@ WsLayout plan_layout(const pcx_plan_s *P)
     L.psum = put((size_t)P->grid.nz * sizeof(double));
     L.xpart = put((size_t)2 * xslots(P->dom) * sizeof(double));
     L.ppart = ref ? put(((size_t)xslots(P->dom) + PMEAN_LEN) * sizeof(double)) : 0;
+    L.spart = put((size_t)sslots(P->dom) * sizeof(double));
     L.total = off;
     return L;
 }
@@ -448,6 +450,19 @@ void plan_bind(pcx_plan_s *P, const HostTables &ht, char *tables, char *ws, cons
     P->dom.ppart = P->ppart;
     P->dom.xpart = P->xpart;
     P->dom.pmean = P->ppart ? P->ppart + (size_t)xslots(P->dom) : nullptr;
+    P->spart = (double *)(ws + L.spart);
+    P->dom.spart = P->spart;
+    // The fused stencil + x passes need an x pass with one row per wave.
+    // The residual's is the default (r is never stored: 0.63 ms against
+    // 0.59 + 0.33 ms per extra solve at 512^3); the RHS's is opt-in
+    // (PCX_FUSE_RHS=1): its stencil, which reads five fields and their
+    // neighbours straight from memory, is slower than the marching RHS
+    // kernel plus the x pass (1.74 against 1.21 + 0.40 ms at 512^3 FP64).
+    // PCX_FUSE=0 turns both off.
+    const char *fz = std::getenv("PCX_FUSE"), *fr = std::getenv("PCX_FUSE_RHS");
+    const bool fuse = !(fz && fz[0] == '0') && sx_supported(P->dom);
+    P->fuse_resid = fuse;
+    P->fuse_rhs = fuse && fr && fr[0] == '1';
     P->lx = lds_x(P->dom, P->prec);
     P->ly = lds_y(P->dom, P->prec);
     P->lzs = lds_z(P->dom, P->prec);
@@ -642,18 +657,32 @@ extern "C" pcx_status pcx_step(pcx_plan P, double dt, double rho0, const double 
     tmark(P, s, nullptr);
     HIPCHK(launch_zero(P->stats, NSTAT, s));
     int solves = 0;
-    HIPCHK(launch_rhs(d, s));
-    tmark(P, s, "rhs_stencil");
-    HIPCHK(launch_xfwd(d, P->prec, SRC_RHS, P->lx, s));
-    tmark(P, s, "x_fft_fwd");
+    if (P->fuse_rhs) {
+        HIPCHK(launch_sx(d, P->prec, SRC_RHS_ST, P->lx, s));
+        tmark(P, s, "rhs_fftx");
+        HIPCHK(launch_smax(d, ST_FINF, ST_SOLVE0, s));
+        tmark(P, s, "f_max");
+    } else {
+        HIPCHK(launch_rhs(d, s));
+        tmark(P, s, "rhs_stencil");
+        HIPCHK(launch_xfwd(d, P->prec, SRC_RHS, P->lx, s));
+        tmark(P, s, "x_fft_fwd");
+    }
     pcx_status st0 = solve_tail(P, d, 0, XOUT_STORE, s);
     if (st0 != PCX_OK) return st0;
     solves = 1;
     auto refine_once = [&](int solve) -> pcx_status {
-        HIPCHK(launch_resid(d, solve, s));
-        tmark(P, s, "resid_stencil");
-        HIPCHK(launch_xfwd(d, P->prec, SRC_RESID, P->lx, s));
-        tmark(P, s, "x_fft_fwd_resid");
+        if (P->fuse_resid) {
+            HIPCHK(launch_sx(d, P->prec, SRC_RESID_ST, P->lx, s));
+            tmark(P, s, "resid_fftx");
+            HIPCHK(launch_smax(d, ST_SOLVE0 + 4 * solve, -1, s));
+            tmark(P, s, "r_max");
+        } else {
+            HIPCHK(launch_resid(d, solve, s));
+            tmark(P, s, "resid_stencil");
+            HIPCHK(launch_xfwd(d, P->prec, SRC_RESID, P->lx, s));
+            tmark(P, s, "x_fft_fwd_resid");
+        }
         return solve_tail(P, d, solve, XOUT_ACCUM, s);
     };
     if (P->prec == PREC_F32) {

@@ -50,6 +50,44 @@ __global__ __launch_bounds__(NTH) void k_xfwd(Dom d)
     pass_xfwd<T, SRC, NTH>(d, blockIdx.x, smem);
 }
 
+// Tile of a fused stencil x pass (tile = k ntj + jt, as pass_xfwd reads it).
+// The launch is ordered so that the tiles that read each other's rows run
+// together on one XCD: groups of SXG consecutive j tiles, every plane k of
+// a group in turn (k fastest after the SXG tiles of a plane), and each XCD
+// a contiguous range of that order (consecutive workgroups go to different
+// XCDs).  Returns -1 for the surplus workgroups of the padded grid.
+constexpr int SXG = 4;
+__host__ __device__ inline long sx_order_len(const Dom &d) { return (long)((d.ntj + SXG - 1) / SXG) * d.nz * SXG; }
+
+__device__ __forceinline__ int sx_tile(const Dom &d)
+{
+    const long n = sx_order_len(d);
+    const long per = (n + 7) >> 3;
+    const long L = (long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (L >= n) return -1;
+    const int jj = (int)(L % SXG);
+    const long q = L / SXG;
+    const int k = (int)(q % d.nz), g = (int)(q / d.nz);
+    const int jt = g * SXG + jj;
+    if (jt >= d.ntj) return -1;
+    return k * d.ntj + jt;
+}
+
+template <typename T, int SRC, int NTH>
+__global__ __launch_bounds__(NTH) void k_sx(Dom d)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int t = sx_tile(d);
+    if (t < 0) return;
+    pass_xfwd<T, SRC, NTH>(d, t, smem);
+}
+
+__global__ __launch_bounds__(NT) void k_smax(Dom d, int sa, int sb)
+{
+    __shared__ double red[2 * NT / 64];
+    pass_smax(d, sa, sb, blockIdx.x, gridDim.x, (char *)red);
+}
+
 template <typename T, bool INV, int NTH>
 __global__ __launch_bounds__(NTH) void k_y(Dom d)
 {
@@ -179,6 +217,38 @@ template <int NTH> static hipError_t launch_xfwd_t(const Dom &d, int prec, int s
 hipError_t launch_xfwd(const Dom &d, int prec, int src, size_t lds, hipStream_t s)
 {
     return d.xth == 512 ? launch_xfwd_t<512>(d, prec, src, lds, s) : launch_xfwd_t<NT>(d, prec, src, lds, s);
+}
+
+bool sx_supported(const Dom &d)
+{
+    return (d.tj == 8 || d.tj == 16) && wave_plan(d.fx) && d.spart != nullptr;
+}
+
+hipError_t launch_sx(const Dom &d, int prec, int src, size_t lds, hipStream_t s)
+{
+    if (!sx_supported(d)) return hipErrorInvalidValue;
+    const int grid = (int)(((sx_order_len(d) + 7) >> 3) << 3);
+    if (d.tj == 8) {
+        if (prec == PREC_F64) {
+            if (src == SRC_RHS_ST) PCX_LAUNCH_B((k_sx<double, SRC_RHS_ST, 512>), grid, 512, lds, s, d);
+            return hipErrorInvalidValue; // the FP64 form has no residual pass
+        }
+        if (src == SRC_RHS_ST) PCX_LAUNCH_B((k_sx<float, SRC_RHS_ST, 512>), grid, 512, lds, s, d);
+        PCX_LAUNCH_B((k_sx<float, SRC_RESID_ST, 512>), grid, 512, lds, s, d);
+    }
+    if (prec == PREC_F64) {
+        if (src == SRC_RHS_ST) PCX_LAUNCH_B((k_sx<double, SRC_RHS_ST, 1024>), grid, 1024, lds, s, d);
+        return hipErrorInvalidValue;
+    }
+    if (src == SRC_RHS_ST) PCX_LAUNCH_B((k_sx<float, SRC_RHS_ST, 1024>), grid, 1024, lds, s, d);
+    PCX_LAUNCH_B((k_sx<float, SRC_RESID_ST, 1024>), grid, 1024, lds, s, d);
+}
+
+hipError_t launch_smax(const Dom &d, int sa, int sb, hipStream_t s)
+{
+    const int v = (sslots(d) + 4 * NT - 1) / (4 * NT);
+    const int nwg = v < 1 ? 1 : (v > XMAX_WG ? XMAX_WG : v);
+    PCX_LAUNCH(k_smax, nwg, 0, s, d, sa, sb);
 }
 
 hipError_t launch_y(const Dom &d, int prec, bool inv, size_t lds, hipStream_t s)

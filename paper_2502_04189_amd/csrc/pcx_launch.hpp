@@ -9,6 +9,11 @@ hipError_t launch_zero(unsigned long long *p, int n, hipStream_t s);
 hipError_t launch_rhs(const Dom &d, hipStream_t s);
 hipError_t launch_resid(const Dom &d, int solve, hipStream_t s);
 hipError_t launch_xfwd(const Dom &d, int prec, int src, size_t lds, hipStream_t s);
+// fused stencil + forward x pass (src SRC_RHS_ST or SRC_RESID_ST), with its
+// per-wave maxima reduced by launch_smax into stats slots sa (and sb >= 0)
+bool sx_supported(const Dom &d);
+hipError_t launch_sx(const Dom &d, int prec, int src, size_t lds, hipStream_t s);
+hipError_t launch_smax(const Dom &d, int sa, int sb, hipStream_t s);
 hipError_t launch_y(const Dom &d, int prec, bool inv, size_t lds, hipStream_t s);
 hipError_t launch_z(const Dom &d, int prec, int smax, size_t lds, hipStream_t s);
 hipError_t launch_xinv(const Dom &d, int prec, int mode, int solve, size_t lds, hipStream_t s);

@@ -484,6 +484,146 @@ __device__ __forceinline__ void pass_div(const Dom &d, int tile, char *smem)
     block_max_to(d.stats + ST_DIV, dmax, red);
 }
 
+// ------------------------------------------------------- fused stencils
+// The RHS f (SRC_RHS_ST) or the residual r = f - L p (SRC_RESID_ST) at the
+// cells of row j of plane k, evaluated by the calling wave straight from the
+// fields, as the pairs (2h, 2h+1) the real x FFT takes (lane: h = lane + 64 t),
+// handed to put(h, value).  Same stencil and wall rules as pass_rhs and
+// pass_resid; the neighbours in y and z are read from memory (the tiles of
+// the neighbouring rows and planes run at the same time, so these reads are
+// mostly cache hits), the x neighbours of a pair are its two outer cells.
+// Returns the lane's max |value|.
+struct SxRow {
+    int c, cn, cs, cu, cd;       // offsets of row j / j+1 / j-1 of plane k, row j of planes k+1 / k-1
+    bool wn, ws, wt, wb;         // wall faces north, south, top, bottom
+};
+
+__device__ __forceinline__ SxRow sx_row(const Dom &d, int j, int k)
+{
+    SxRow r;
+    const int nx = d.nx, ny = d.ny, nz = d.nz;
+    const size_t sz = (size_t)nx * ny;
+    const bool wy = d.bcy == BC_WALL, wz = d.bcz == BC_WALL;
+    r.wn = wy && j == ny - 1;
+    r.ws = wy && j == 0;
+    r.wt = wz && k == nz - 1;
+    r.wb = wz && k == 0;
+    // neighbours across a wall are never used: a valid (clamped) row instead
+    const int jn = j == ny - 1 ? (wy ? j : 0) : j + 1;
+    const int js = j == 0 ? (wy ? j : ny - 1) : j - 1;
+    const int ku = k == nz - 1 ? (wz ? k : 0) : k + 1;
+    const int kd = k == 0 ? (wz ? k : nz - 1) : k - 1;
+    r.c = (int)(k * sz) + j * nx;
+    r.cn = (int)(k * sz) + jn * nx;
+    r.cs = (int)(k * sz) + js * nx;
+    r.cu = (int)(ku * sz) + j * nx;
+    r.cd = (int)(kd * sz) + j * nx;
+    return r;
+}
+
+template <int SRC, typename Put>
+__device__ __forceinline__ double stencil_row(const Dom &d, int j, int k, int lane, Put put)
+{
+    const SxRow R = sx_row(d, j, k);
+    const int nx = d.nx, hx = nx >> 1;
+    const bool wx = d.bcx == BC_WALL;
+    const int kd = k == 0 ? d.nz - 1 : k - 1; // z face below (unused on a bottom wall)
+    const double idzf = ztab(d.idzf, k), idzc = ztab(d.idzc, k), idzcb = ztab(d.idzc, kd);
+    const double idx2 = d.idx * d.idx, idy2 = d.idy * d.idy;
+    double amax = 0.0;
+    if constexpr (SRC == SRC_RHS_ST) {
+        const double rr0 = d.rho0, tr0 = 2.0 * d.rho0, cdiv = d.rho0 / d.dt;
+        const double rlo = ztab(d.rzlo, k), rhi = ztab(d.rzhi, k), rlob = ztab(d.rzlo, kd), rhib = ztab(d.rzhi, kd);
+        auto ld2 = [](const double *p, int o) { return *(const double2 *)(p + o); };
+#pragma unroll 1
+        for (int h = lane; h < hx; h += 64) {
+            const int i0 = 2 * h;
+            const int iw = h == 0 ? nx - 1 : i0 - 1, ie = h == hx - 1 ? 0 : i0 + 2;
+            const double2 P = ld2(d.ps, R.c + i0), Rh = ld2(d.rho, R.c + i0);
+            const double Pw = d.ps[R.c + iw], Rw = d.rho[R.c + iw], Pe = d.ps[R.c + ie], Re = d.rho[R.c + ie];
+            const double2 Pn = ld2(d.ps, R.cn + i0), Rn = ld2(d.rho, R.cn + i0);
+            const double2 Ps = ld2(d.ps, R.cs + i0), Rs = ld2(d.rho, R.cs + i0);
+            const double2 Pu = ld2(d.ps, R.cu + i0), Ru = ld2(d.rho, R.cu + i0);
+            const double2 Pd = ld2(d.ps, R.cd + i0), Rd = ld2(d.rho, R.cd + i0);
+            const double2 U = ld2(d.u, R.c + i0), V = ld2(d.v, R.c + i0), Vs = ld2(d.v, R.cs + i0);
+            const double2 W = ld2(d.w, R.c + i0), Wd = ld2(d.w, R.cd + i0); // w is re-read by the plane above
+            const double Uw = d.u[R.c + iw];
+            const bool ww = wx && h == 0, we = wx && h == hx - 1;
+            // x fluxes: face between the pair's cells, west of cell 0, east of cell 1
+            const double Fm = (1.0 - tr0 * rcp_nr(Rh.x + Rh.y)) * (P.y - P.x);
+            const double Fw = ww ? 0.0 : (1.0 - tr0 * rcp_nr(Rw + Rh.x)) * (P.x - Pw);
+            const double Fe = we ? 0.0 : (1.0 - tr0 * rcp_nr(Rh.y + Re)) * (Pe - P.y);
+            double f[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const double Pc = q ? P.y : P.x, Rc = q ? Rh.y : Rh.x;
+                const double pn = q ? Pn.y : Pn.x, rn = q ? Rn.y : Rn.x, ps = q ? Ps.y : Ps.x, rs = q ? Rs.y : Rs.x;
+                const double pu = q ? Pu.y : Pu.x, ru = q ? Ru.y : Ru.x, pd = q ? Pd.y : Pd.x, rd = q ? Rd.y : Rd.x;
+                const double Fn = R.wn ? 0.0 : (1.0 - tr0 * rcp_nr(Rc + rn)) * (pn - Pc);
+                const double Fs = R.ws ? 0.0 : (1.0 - tr0 * rcp_nr(rs + Rc)) * (Pc - ps);
+                const double Ft = R.wt ? 0.0 : (1.0 - rr0 * rcp_nr(Rc * rlo + ru * rhi)) * (pu - Pc) * idzc;
+                const double Fb = R.wb ? 0.0 : (1.0 - rr0 * rcp_nr(rd * rlob + Rc * rhib)) * (Pc - pd) * idzcb;
+                const double ue = q ? (we ? 0.0 : U.y) : U.x, uw = q ? U.x : (ww ? 0.0 : Uw);
+                const double vn = R.wn ? 0.0 : (q ? V.y : V.x), vs = R.ws ? 0.0 : (q ? Vs.y : Vs.x);
+                const double wt = R.wt ? 0.0 : (q ? W.y : W.x), wb = R.wb ? 0.0 : (q ? Wd.y : Wd.x);
+                const double fe = q ? Fe : Fm, fw = q ? Fm : Fw;
+                f[q] = cdiv * ((ue - uw) * d.idx + (vn - vs) * d.idy + (wt - wb) * idzf) + (fe - fw) * idx2 +
+                       (Fn - Fs) * idy2 + (Ft - Fb) * idzf;
+            }
+            const double2 v = double2{f[0], f[1]};
+            if (d.r) st_stream((double2 *)(d.f + R.c + i0), v); // refined form: the residual needs f
+            put(h, v);
+            amax = amax_nan(amax_nan(amax, f[0]), f[1]);
+        }
+    } else {
+        auto ld2 = [](const double *p, int o) { return *(const double2 *)(p + o); };
+#pragma unroll 1
+        for (int h = lane; h < hx; h += 64) {
+            const int i0 = 2 * h;
+            const int iw = h == 0 ? nx - 1 : i0 - 1, ie = h == hx - 1 ? 0 : i0 + 2;
+            const double2 P = ld2(d.po, R.c + i0);
+            const double Pw = d.po[R.c + iw], Pe = d.po[R.c + ie];
+            const double2 Pn = ld2(d.po, R.cn + i0), Ps = ld2(d.po, R.cs + i0);
+            const double2 Pu = ld2(d.po, R.cu + i0), Pd = ld2(d.po, R.cd + i0);
+            const double2 F = ld_stream((const double2 *)(d.f + R.c + i0));
+            const bool ww = wx && h == 0, we = wx && h == hx - 1;
+            const double gm = P.y - P.x;
+            const double gw = ww ? 0.0 : P.x - Pw, ge = we ? 0.0 : Pe - P.y;
+            double r[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const double Pc = q ? P.y : P.x;
+                const double gn = R.wn ? 0.0 : (q ? Pn.y : Pn.x) - Pc, gs = R.ws ? 0.0 : Pc - (q ? Ps.y : Ps.x);
+                const double Gt = R.wt ? 0.0 : ((q ? Pu.y : Pu.x) - Pc) * idzc;
+                const double Gb = R.wb ? 0.0 : (Pc - (q ? Pd.y : Pd.x)) * idzcb;
+                const double gee = q ? ge : gm, gww = q ? gm : gw;
+                r[q] = (q ? F.y : F.x) - ((gee - gww) * idx2 + (gn - gs) * idy2 + (Gt - Gb) * idzf);
+            }
+            put(h, double2{r[0], r[1]});
+            amax = amax_nan(amax_nan(amax, r[0]), r[1]);
+        }
+    }
+    return amax;
+}
+
+// Maximum of the fused stencil passes' per-wave partials into stats slot
+// sa (and sb when >= 0): workgroup wg of nwg takes every nwg-th block.
+__device__ __forceinline__ void pass_smax(const Dom &d, int sa, int sb, int wg, int nwg, char *smem)
+{
+    double *red = (double *)smem;
+    const int nt = sslots(d);
+    double a = 0.0;
+    for (int q0 = wg * NT; q0 < nt; q0 += 8 * nwg * NT) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = d.spart[min(q0 + u * nwg * NT + (int)threadIdx.x, nt - 1)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (q0 + u * nwg * NT + (int)threadIdx.x < nt) a = (v[u] != v[u] || v[u] > a) ? v[u] : a;
+    }
+    block_max2_to<NT>(d.stats + sa, a, sb >= 0 ? d.stats + sb : nullptr, a, red);
+}
+
 // ------------------------------------------------------------------ xfwd
 // Tile = (j tile, k): rows j0 .. j0+rows-1 of plane k of f (or r).  Real
 // FFT by a half-length complex FFT of z[n] = s[2n] + i s[2n+1] and the split
@@ -499,7 +639,8 @@ __device__ __forceinline__ void pass_xfwd(const Dom &d, int tile, char *smem)
     const int j0 = jt * d.tj;
     const int rows = min(d.tj, d.ny - j0);
     const int nx = d.nx, M = d.M, half = M / 2;
-    const double *src = (SRC == SRC_RHS ? d.f : d.r) + ((size_t)k * d.ny + j0) * nx;
+    constexpr bool ST = SRC == SRC_RHS_ST || SRC == SRC_RESID_ST;
+    const double *src = (SRC == SRC_RHS || SRC == SRC_RHS_ST ? d.f : d.r) + ((size_t)k * d.ny + j0) * nx;
     // LDS: the tile's rows, the FFT roots, the split twiddles (M/2 + 1)
     C *ltr = ltw + tw_half(d.fx.n);
     TwStage<T, NTH> tws;
@@ -552,12 +693,21 @@ __device__ __forceinline__ void pass_xfwd(const Dom &d, int tile, char *smem)
     constexpr int NW = NTH / 64;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const bool wv = WV && d.tj <= NW && wave_plan(d.fx);
+    if (ST && !wv) return; // the host enables the fused forms only on the wave path
     if (wv) {
         if (wid < rows) {
             C *row = buf + wid * ldr;
-            const double2 *sr = src2 + (size_t)wid * hx;
-            staged_copy_t<64, 8, double2>(
-                lane, hx, [&](int h) { return sr[h]; }, [&](int h, double2 s) { put_pair(row, h, s); });
+            if constexpr (ST) {
+                const double m = stencil_row<SRC>(d, j0 + wid, k, lane, [&](int h, double2 s) { put_pair(row, h, s); });
+                const double wm = wave_max1(m);
+                if (lane == 0) d.spart[tile * NW + wid] = wm;
+            } else {
+                const double2 *sr = src2 + (size_t)wid * hx;
+                staged_copy_t<64, 8, double2>(
+                    lane, hx, [&](int h) { return sr[h]; }, [&](int h, double2 s) { put_pair(row, h, s); });
+            }
+        } else if (ST && lane == 0 && wid < NW) {
+            d.spart[tile * NW + wid] = 0.0;
         }
         tws.put(ltw, d.fx);
         trs.put(ltr, (const C *)d.twr, M / 2 + 1);

@@ -40,7 +40,7 @@ struct HostTables {
 // Byte offsets of a single-domain step's workspace pieces inside one region
 // (each 256-byte aligned; r and ppart are used by the refined form only).
 struct WsLayout {
-    size_t s1 = 0, s2 = 0, f = 0, r = 0, stats = 0, psum = 0, xpart = 0, ppart = 0, total = 0;
+    size_t s1 = 0, s2 = 0, f = 0, r = 0, stats = 0, psum = 0, xpart = 0, ppart = 0, spart = 0, total = 0;
 };
 
 extern thread_local std::string g_err;
@@ -95,6 +95,9 @@ struct pcx_plan_s {
     double *psum = nullptr;
     double *ppart = nullptr;
     double *xpart = nullptr;
+    double *spart = nullptr;
+    bool fuse_rhs = false;          // RHS evaluated inside the forward x pass
+    bool fuse_resid = false;        // residual evaluated inside the forward x pass
     unsigned long long *stats = nullptr;
     size_t ws_bytes = 0;
     size_t lx = 0, ly = 0, lzs = 0;
