@@ -43,13 +43,17 @@ class OrDiag(C.Structure):
     ]
 
 
+SOURCES = ("oracle.c", "flow.c")
+
+
 def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc (plain C, no contraction, no fast-math)."""
-    src = os.path.join(_HERE, "oracle.c")
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+    srcs = [os.path.join(_HERE, s) for s in SOURCES]
+    stale = not os.path.exists(_LIB_PATH) or any(os.path.getmtime(_LIB_PATH) < os.path.getmtime(s) for s in srcs)
+    if force or stale:
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-ffp-contract=off",
-                               "-fno-fast-math", "-fPIC", "-shared", "-o", tmp, src, "-lm"])
+                               "-fno-fast-math", "-fPIC", "-shared", "-o", tmp] + srcs + ["-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -85,8 +89,28 @@ def lib():
         L.oracle_cyclic.argtypes = [C.c_int, _DP, _DP, _DP, _DP]
         L.oracle_eig.argtypes = [C.c_int, C.c_double, C.c_int, C.c_int]
         L.oracle_eig.restype = C.c_double
+        if hasattr(L, "oracle_acdi_rhs"):  # flow.c (a mutant build of oracle.c alone lacks it)
+            A, F = C.POINTER(OrAcdi), C.POINTER(OrFlow)
+            L.oracle_acdi_normals.argtypes = [G, A] + [_DP] * 5
+            L.oracle_acdi_flux.argtypes = [G, A] + [_DP] * 4
+            L.oracle_acdi_rhs.argtypes = [G, A] + [_DP] * 5
+            L.oracle_curvature.argtypes = [G, A, _DP, _DP]
+            L.oracle_momentum_rhs.argtypes = [G, F] + [_DP] * 7
+            L.oracle_rk3_coeffs.argtypes = [C.c_int, _DP, _DP, _DP]
+            L.oracle_flow_substep.argtypes = ([G, F, C.c_int, C.c_double] + [_DP] * 6 + [C.c_double] +
+                                              [_DP] * 9 + [C.POINTER(OrDiag)])
         _lib = L
     return _lib
+
+
+class OrAcdi(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("eps", C.c_double), ("eps_s", C.c_double)]
+
+
+class OrFlow(C.Structure):
+    _fields_ = [("rho1", C.c_double), ("rho2", C.c_double), ("mu1", C.c_double), ("mu2", C.c_double),
+                ("sigma", C.c_double), ("gx", C.c_double), ("gy", C.c_double), ("gz", C.c_double),
+                ("acdi", OrAcdi)]
 
 
 def _p(a: np.ndarray):
@@ -255,3 +279,73 @@ def cyclic(a, b, c, d):
 
 def eig(n, h, bc, l):
     return lib().oracle_eig(int(n), float(h), int(bc), int(l))
+
+
+# ----------------------------------------------------------------- flow.c
+# Phase-field transport (ACDI), momentum predictor and the Runge-Kutta
+# substep around the pressure-correction step ("Mathematical model",
+# "Methods and Implementation strategy"); readings in flow.c's header.
+
+def flow_params(rho1=1000.0, rho2=1.0, mu1=1e-2, mu2=1e-4, sigma=0.0, g=(0.0, 0.0, 0.0), gamma=1.0, eps=None,
+                eps_s=1e-100, dx=None):
+    """OrFlow with the ACDI thickness eps (default: 0.51 dx, dx required then)."""
+    if eps is None:
+        eps = 0.51 * dx
+    return OrFlow(rho1, rho2, mu1, mu2, sigma, g[0], g[1], g[2], OrAcdi(gamma, eps, eps_s))
+
+
+def acdi_normals(g, fl, phi):
+    """(psi, nx, ny, nz) at cell centres."""
+    outs = [np.empty(g.shape) for _ in range(4)]
+    _chk(lib().oracle_acdi_normals(g.cref, C.byref(fl.acdi), _p(_arr(phi)), *[_p(o) for o in outs]), "acdi_normals")
+    return tuple(outs)
+
+
+def acdi_flux(g, fl, phi):
+    """Regularization flux (ax, ay, az) on the +x/+y/+z faces."""
+    outs = [np.empty(g.shape) for _ in range(3)]
+    _chk(lib().oracle_acdi_flux(g.cref, C.byref(fl.acdi), _p(_arr(phi)), *[_p(o) for o in outs]), "acdi_flux")
+    return tuple(outs)
+
+
+def acdi_rhs(g, fl, phi, u, v, w):
+    """Right-hand side of the phase-field transport at cell centres."""
+    out = np.empty(g.shape)
+    ins = [_arr(a) for a in (phi, u, v, w)]
+    _chk(lib().oracle_acdi_rhs(g.cref, C.byref(fl.acdi), *[_p(a) for a in ins], _p(out)), "acdi_rhs")
+    return out
+
+
+def curvature(g, fl, phi):
+    out = np.empty(g.shape)
+    _chk(lib().oracle_curvature(g.cref, C.byref(fl.acdi), _p(_arr(phi)), _p(out)), "curvature")
+    return out
+
+
+def momentum_rhs(g, fl, phi, u, v, w):
+    """Momentum predictor right-hand side per unit mass (ru, rv, rw) on the faces."""
+    outs = [np.empty(g.shape) for _ in range(3)]
+    ins = [_arr(a) for a in (phi, u, v, w)]
+    _chk(lib().oracle_momentum_rhs(g.cref, C.byref(fl), *[_p(a) for a in ins], *[_p(o) for o in outs]),
+         "momentum_rhs")
+    return tuple(outs)
+
+
+def rk3_coeffs(s):
+    a, b, c = C.c_double(), C.c_double(), C.c_double()
+    _chk(lib().oracle_rk3_coeffs(int(s), C.byref(a), C.byref(b), C.byref(c)), "rk3_coeffs")
+    return a.value, b.value, c.value
+
+
+def flow_substep(g, fl, s, Dt, phi, u, v, w, p1, p2, r, h):
+    """One Runge-Kutta substep.  h = [hphi, hu, hv, hw] (previous substep's
+    right-hand sides, updated in place).  Returns (phi, u, v, w, p, diag)."""
+    ins = [_arr(a) for a in (phi, u, v, w, p1, p2)]
+    for a in h:
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    outs = [np.empty(g.shape) for _ in range(5)]
+    d = OrDiag()
+    rc = lib().oracle_flow_substep(g.cref, C.byref(fl), int(s), float(Dt), *[_p(a) for a in ins], float(r),
+                                   *[_p(a) for a in h], *[_p(o) for o in outs], C.byref(d))
+    _chk(rc, "flow_substep")
+    return (*outs, {k: getattr(d, k) for k, _ in OrDiag._fields_})
