@@ -10,6 +10,7 @@ import re
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpcx.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "pcx.h")
+HEADERS = [HEADER, os.path.join(os.path.dirname(HERE), "include", "pcx_flow.h")]
 
 PCX_OK, PCX_ERR_INVALID, PCX_ERR_UNSUPPORTED, PCX_ERR_NOMEM, PCX_ERR_HIP = 0, 1, 2, 3, 4
 PCX_ERR_NOT_CONVERGED, PCX_ERR_NONFINITE = 5, 6
@@ -40,6 +41,12 @@ class PcxReport(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class PcxFlowParams(C.Structure):
+    _fields_ = [("rho1", C.c_double), ("rho2", C.c_double), ("mu1", C.c_double), ("mu2", C.c_double),
+                ("sigma", C.c_double), ("gx", C.c_double), ("gy", C.c_double), ("gz", C.c_double),
+                ("gamma", C.c_double), ("eps", C.c_double), ("eps_s", C.c_double)]
+
+
 class PcxDomain(C.Structure):
     _fields_ = [("grid", PcxGrid), ("dt", C.c_double), ("rho0", C.c_double),
                 ("rho", C.c_void_p), ("p_star", C.c_void_p), ("u", C.c_void_p),
@@ -51,8 +58,8 @@ _lib = None
 
 
 def header_symbols():
-    """Function names declared in include/pcx.h."""
-    txt = open(HEADER).read()
+    """Function names declared in include/pcx.h and include/pcx_flow.h."""
+    txt = "".join(open(h).read() for h in HEADERS)
     return sorted(set(re.findall(r"\b(pcx_[a-z0-9_]+)\s*\(", txt)))
 
 
@@ -81,6 +88,11 @@ def lib():
         "pcx_step_noalloc": (st, [C.POINTER(PcxGrid), C.POINTER(PcxOptions), dbl, dbl] + [vp] * 9 +
                              [vp, C.POINTER(PcxReport)]),
         "pcx_noalloc_scratch_need": (st, [C.POINTER(PcxGrid), C.POINTER(PcxOptions), C.POINTER(C.c_size_t)]),
+        "pcx_flow_create": (st, [C.POINTER(PcxGrid), C.POINTER(PcxFlowParams), C.POINTER(PcxOptions), C.POINTER(vp)]),
+        "pcx_flow_destroy": (st, [vp]),
+        "pcx_flow_phase_rhs": (st, [vp] + [vp] * 5 + [vp]),
+        "pcx_flow_momentum_rhs": (st, [vp] + [vp] * 7 + [vp]),
+        "pcx_flow_substep": (st, [vp, i32, dbl] + [vp] * 6 + [dbl] + [vp] * 9 + [vp, C.POINTER(PcxReport)]),
         "pcx_refine_should_stop": (i32, [dbl, dbl, dbl, dbl, dbl]),
         "pcx_status_str": (C.c_char_p, [st]),
         "pcx_last_error": (C.c_char_p, []),
@@ -273,3 +285,59 @@ def rho_min(rho, stream=None):
     _check(lib().pcx_rho_min(C.c_void_p(rho.data_ptr()), rho.numel(), _stream_handle(stream), C.byref(out)),
            "pcx_rho_min")
     return out.value
+
+
+class Flow:
+    """pcx_flow: the Runge-Kutta substep around the pressure correction on
+    one grid.  Fields are torch float64 CUDA tensors of shape (nz, ny, nx)."""
+
+    def __init__(self, grid, rho1, rho2, mu1, mu2, sigma=0.0, g=(0.0, 0.0, 0.0), gamma=1.0, eps=None,
+                 eps_s=1e-100, precision="fp64"):
+        L = lib()
+        self.gs = grid
+        self._g = make_grid(grid)
+        if eps is None:
+            eps = 0.51 * grid.lx / grid.nx
+        self._p = PcxFlowParams(rho1, rho2, mu1, mu2, sigma, g[0], g[1], g[2], gamma, eps, eps_s)
+        self._o = make_options(precision)
+        h = C.c_void_p()
+        _check(L.pcx_flow_create(C.byref(self._g), C.byref(self._p), C.byref(self._o), C.byref(h)),
+               "pcx_flow_create")
+        self._L = L
+        self._h = h
+        self.shape = (grid.nz, grid.ny, grid.nx)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.pcx_flow_destroy(self._h)  # the library handle outlives module teardown
+            self._h = None
+
+    __del__ = close
+
+    def _ptrs(self, ts, names):
+        return [_ptr(t, self.shape, n) for t, n in zip(ts, names)]
+
+    def phase_rhs(self, phi, u, v, w, out=None, stream=None):
+        import torch
+        out = out if out is not None else torch.empty(self.shape, dtype=torch.float64, device=phi.device)
+        p = self._ptrs((phi, u, v, w, out), ("phi", "u", "v", "w", "rhs"))
+        _check(lib().pcx_flow_phase_rhs(self._h, *p, _stream_handle(stream)), "pcx_flow_phase_rhs")
+        return out
+
+    def momentum_rhs(self, phi, u, v, w, stream=None):
+        import torch
+        outs = [torch.empty(self.shape, dtype=torch.float64, device=phi.device) for _ in range(3)]
+        p = self._ptrs((phi, u, v, w, *outs), ("phi", "u", "v", "w", "ru", "rv", "rw"))
+        _check(lib().pcx_flow_momentum_rhs(self._h, *p, _stream_handle(stream)), "pcx_flow_momentum_rhs")
+        return tuple(outs)
+
+    def substep(self, s, Dt, phi, u, v, w, p1, p2, r, h, outs, stream=None, report=True):
+        """h = [hphi, hu, hv, hw] (updated in place); outs = [phi, u, v, w, p]."""
+        p = self._ptrs((phi, u, v, w, p1, p2), ("phi", "u", "v", "w", "p1", "p2"))
+        ph = self._ptrs(h, ("hphi", "hu", "hv", "hw"))
+        po = self._ptrs(outs, ("phi_out", "u_out", "v_out", "w_out", "p_out"))
+        rep = PcxReport()
+        st = lib().pcx_flow_substep(self._h, int(s), float(Dt), *p, float(r), *ph, *po, _stream_handle(stream),
+                                    C.byref(rep) if report else None)
+        _check(st, "pcx_flow_substep")
+        return rep.as_dict() if report else None

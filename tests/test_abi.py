@@ -128,3 +128,22 @@ def test_noalloc_sizes_and_rejections(L):
     g = P.make_grid(bad)
     o = P.make_options("fp64")
     assert L.pcx_step_noalloc(C.byref(g), C.byref(o), 1e-3, 1.0, *dummy, None, None) == P.PCX_ERR_UNSUPPORTED
+
+
+def test_flow_create_validation(L):
+    """pcx_flow_create rejects bad parameters on the host and reports a
+    missing device; the substep entry points reject NULL flows."""
+    gs = W.GridSpec(16, 16, 8, 1.0, 1.0, W.zf_uniform(8, 0.5))
+    g = P.make_grid(gs)
+    good = P.PcxFlowParams(1000.0, 1.0, 1e-2, 1e-4, 0.07, 0.0, 0.0, -9.81, 1.0, 0.04, 1e-100)
+    h = C.c_void_p()
+    for field, bad in (("rho1", 0.0), ("mu2", -1.0), ("eps", 0.0), ("gamma", -1.0), ("gz", float("nan"))):
+        p = P.PcxFlowParams(*[getattr(good, f) for f, _ in P.PcxFlowParams._fields_])
+        setattr(p, field, bad)
+        assert L.pcx_flow_create(C.byref(g), C.byref(p), None, C.byref(h)) == P.PCX_ERR_INVALID, field
+    assert L.pcx_flow_create(C.byref(g), None, None, C.byref(h)) == P.PCX_ERR_INVALID
+    st = L.pcx_flow_create(C.byref(g), C.byref(good), None, C.byref(h))
+    assert st in (P.PCX_OK, P.PCX_ERR_HIP)
+    if st == P.PCX_OK:
+        L.pcx_flow_destroy(h)
+    assert L.pcx_flow_phase_rhs(None, *[None] * 5, None) == P.PCX_ERR_INVALID
