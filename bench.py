@@ -329,6 +329,102 @@ def prof_batch(steps, warmup, ndom):
         log(f"prof batch {prec}: {warmup + steps} launches of {len(doms)} domains")
 
 
+# Algorithmic HBM bytes per cell of the substep kernels around the
+# projection: every field a kernel reads or writes, once (neighbours re-read
+# through the caches are overhead).
+FLOW_BYTES = {"normals": 8 + 32,          # phi -> psi, n
+              "flux": 32 + 32,            # phi, psi, n -> a (3 faces), kappa
+              "phase": 64 + 24,           # phi, u, v, w, a, h -> phi', h, rho'
+              "momentum": 104 + 56}       # phi, u, v, w, kappa, a, h (3), p1, p2 -> u* (3), h (3), p*
+
+
+def flow_setup(case):
+    """The two-phase state of a bubble channel: phi from its density
+    (phase 1 = gas, rho = 1000 - 999 phi), the velocity its pressure step
+    corrects (discretely solenoidal), zero pressures; gas/liquid
+    viscosities 1e-5 / 1e-3, sigma = 0.07, gravity -9.81 in z,
+    Gamma = 2 max |u|, eps = 0.51 dx."""
+    import torch
+    from paper_2502_04189_amd import pcx
+    gs = case.grid
+    dev = [torch.from_numpy(a).to("cuda") for a in case.fields()]
+    plan = pcx.Plan(gs, "fp64")
+    u, v, w, _, _ = plan.step(case.dt, case.rho0, *dev, report=False)
+    torch.cuda.synchronize()
+    plan.close()
+    phi = (1000.0 - dev[0]) / 999.0
+    del dev
+    st = [phi.contiguous(), u, v, w]
+    umax = float(max(u.abs().max(), v.abs().max(), w.abs().max()))
+    prm = dict(rho1=1.0, rho2=1000.0, mu1=1e-5, mu2=1e-3, sigma=0.07, g=(0.0, 0.0, -9.81), gamma=2.0 * umax,
+               eps=0.51 * gs.lx / gs.nx)
+    return st, prm, umax
+
+
+def flow_dt(gs, prm, umax):
+    """Step of the explicit substeps: the advective limit 0.5 h_min / max|u|
+    and the diffusive one of the ACDI term (diffusivity Gamma eps) and the
+    viscous term (max mu/rho): RK3 is stable on the negative real axis up to
+    about 2.5, the discrete Laplacian's largest eigenvalue is
+    sum_d 4/h_d^2, and half of that limit is taken."""
+    import numpy as np
+    hz = float(np.min(np.diff(gs.zf)))
+    hx, hy = gs.lx / gs.nx, gs.ly / gs.ny
+    nu = max(prm["mu1"] / prm["rho1"], prm["mu2"] / prm["rho2"])
+    lam = 4.0 / hx ** 2 + 4.0 / hy ** 2 + 4.0 / hz ** 2
+    return min(0.5 * min(hx, hy, hz) / umax, 1.25 / ((prm["gamma"] * prm["eps"] + nu) * lam))
+
+
+def run_flow(case, steps, warmup):
+    """Whole Runge-Kutta steps (three substeps: phase field, momentum
+    predictor, pressure-correction step) of the bubble channel."""
+    import torch
+    from paper_2502_04189_amd import pcx
+    gs = case.grid
+    st, prm, umax = flow_setup(case)
+    F = pcx.Flow(gs, **prm)
+    z = lambda: torch.zeros(gs.shape, dtype=torch.float64, device="cuda")
+    h = [z() for _ in range(4)]
+    Dt = flow_dt(gs, prm, umax)
+    dtprev, cur = None, 0
+
+    # ping-pong without allocation: state A -> B -> A ...
+    bufs = [st + [z()], [z() for _ in range(5)]]
+    pres = [z(), z(), z()]
+
+    def step_all(n):
+        nonlocal dtprev, cur
+        for _ in range(n):
+            for s in (1, 2, 3):
+                al = (8 / 15, 2 / 15, 1 / 3)[s - 1]
+                r = 0.0 if dtprev is None else al * Dt / dtprev
+                src, dst = bufs[cur], bufs[1 - cur]
+                # pressures: pres[0] newest, pres[1] previous; output into pres[2]
+                F.substep(s, Dt, *src[:4], pres[0], pres[1], r, h, dst[:4] + [pres[2]], report=False)
+                pres[:] = [pres[2], pres[0], pres[1]]
+                cur = 1 - cur
+                dtprev = al * Dt
+        return bufs[cur]
+
+    step_all(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    fin = step_all(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    phi = fin[0]
+    ok = bool(torch.isfinite(fin[1]).all()) and float(phi.min()) > -1e-6 and float(phi.max()) < 1 + 1e-6
+    F.close()
+    log(f"rk3 steps: {ms:.3f} ms per step of three substeps, phi in [{float(phi.min()):.3e}, {float(phi.max()):.6f}]")
+    cells = gs.cells
+    return {"ms_per_rk3_step": round(ms, 4), "ms_per_substep": round(ms / 3, 4),
+            "value": round(cells / (ms * 1e-3) / 1e6, 1), "unit": "Mpts/s (whole RK3 steps)",
+            "steps": steps, "Dt": Dt, "finite_and_bounded": ok,
+            "substep_kernel_bytes_per_cell": FLOW_BYTES}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -343,6 +439,9 @@ def main():
                     help="profiling mode: a few FP64 (or --prof-refined) steps plus a 1 GiB torch copy "
                          "that calibrates the HBM byte counters; prints no JSON")
     ap.add_argument("--prof-refined", action="store_true")
+    ap.add_argument("--no-flow", action="store_true")
+    ap.add_argument("--prof-flow", action="store_true",
+                    help="profiling mode: a few Runge-Kutta steps of the substep around the projection; no JSON")
     ap.add_argument("--prof-batch", action="store_true",
                     help="profiling mode: only the 192-domain batch, FP64 then refined (tuned shapes); "
                          "prints no JSON")
@@ -371,6 +470,12 @@ def main():
     assert rho0 == case.rho0
     outs = [torch.empty(gs.shape, dtype=torch.float64, device="cuda") for _ in range(4)]
     cells = gs.cells
+
+    if args.prof_flow:
+        del dev, outs
+        torch.cuda.empty_cache()
+        run_flow(case, args.steps, args.warmup)
+        return
 
     if args.prof:
         plan = pcx.Plan(gs, "fp32_refined" if args.prof_refined else "fp64", fixed_iters=3)
@@ -437,6 +542,11 @@ def main():
     # ---- batched form
     if not args.no_batch:
         res["batched"] = run_batch(args.steps, args.warmup, args.ndom)
+
+    # ---- whole Runge-Kutta steps around the projection (same workload)
+    if not args.no_flow:
+        res["rk3_substeps"] = run_flow(case, min(args.steps, 5), min(args.warmup, 1))
+        torch.cuda.empty_cache()
 
     res["reference_bandwidth"] = reference_bandwidth()
     if not args.no_cpu:

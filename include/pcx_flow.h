@@ -10,7 +10,8 @@
  * of each substep.
  *
  * Discretization (second order, staggered, the grid and field conventions
- * of pcx.h): psi = eps ln((phi + eps_s)/(1 - phi + eps_s)); n = grad psi /
+ * of pcx.h): psi = eps ln((q + eps_s)/(1 - q + eps_s)) with q = phi clamped
+ * to [0, 1]; n = grad psi /
  * |grad psi| at cell centres (central differences); on faces
  * a = gamma [eps grad phi - 1/4 (1 - tanh^2(psi_f/(2 eps))) n_f] with face
  * values by the mean in x, y and linear interpolation in z;

@@ -10,7 +10,7 @@
  * file.  Written for clarity, face by face, with no blocking or fusion.
  *
  * Discretization (the paper prints no equations; these are the readings):
- *   psi    = eps ln((phi + eps_s)/(1 - phi + eps_s))
+ *   psi    = eps ln((phi + eps_s)/(1 - phi + eps_s)), phi clamped to [0, 1]
  *   n      = grad psi / |grad psi| at cell centres, central differences
  *            (zero-gradient ghost cells across walls)
  *   a      = Gamma [eps grad phi - 1/4 (1 - tanh^2(psi_f/(2 eps))) n_f] on
@@ -154,7 +154,12 @@ static double hcell(const fgeo *m, int d, int k) { return d == 0 ? m->dx : (d ==
 static void psi_field(const fgeo *m, const or_acdi *a, const double *phi, double *psi)
 {
     const size_t n = (size_t)m->nx * m->ny * m->nz;
-    for (size_t c = 0; c < n; ++c) psi[c] = a->eps * log((phi[c] + a->eps_s) / (1.0 - phi[c] + a->eps_s));
+    for (size_t c = 0; c < n; ++c) {
+        /* the logarithm is defined for phi in [0, 1]; rounding can leave phi
+           a few ulps outside, so psi takes phi clamped to that range */
+        const double q = phi[c] < 0.0 ? 0.0 : (phi[c] > 1.0 ? 1.0 : phi[c]);
+        psi[c] = a->eps * log((q + a->eps_s) / (1.0 - q + a->eps_s));
+    }
 }
 
 static void normal_field(const fgeo *m, const double *psi, double *nx_, double *ny_, double *nz_)

@@ -31,6 +31,7 @@ struct FGrid {
 
 struct FParams {
     double rho1, rho2, mu1, mu2, sigma, g[3], gamma, eps, eps_s;
+    double ihe; // 1 / (2 eps)
 };
 
 __device__ __forceinline__ size_t at(const FGrid &G, int i, int j, int k)
@@ -90,236 +91,284 @@ __device__ __forceinline__ double dzc_at(const FGrid &G, int k)
     if (k >= nz - 1) return G.per[2] ? G.dzc[nz - 1] : G.dzf[nz - 1];
     return G.dzc[k];
 }
-// cell width in direction d at plane k; centre spacing s -> s+1 in d
-__device__ __forceinline__ double hcell(const FGrid &G, int d, int k) { return d < 2 ? G.h[d] : G.dzf[k]; }
-__device__ __forceinline__ double hcen(const FGrid &G, int d, int s) { return d < 2 ? G.h[d] : dzc_at(G, s); }
 
-// cell quantity on the +d face of (i, j, k): mean in x, y; linear in z
-template <int D>
-__device__ __forceinline__ double cface(const FGrid &G, const double *q, int i, int j, int k)
-{
-    const double q0 = cv(G, q, i, j, k);
-    if constexpr (D == 0) return 0.5 * (q0 + cv(G, q, i + 1, j, k));
-    else if constexpr (D == 1) return 0.5 * (q0 + cv(G, q, i, j + 1, k));
-    else {
-        const double q1 = cv(G, q, i, j, k + 1);
-        return (q0 * dzf_at(G, k + 1) + q1 * dzf_at(G, k)) / (2.0 * dzc_at(G, k));
+// ------------------------------------------------------------ accessors
+// The stencils below are written once against an accessor X that reads a
+// field at a small constant offset (a, b, c), each in {-1, 0, +1}, from the
+// thread's cell:
+//   Gen  applies the wrap / wall / ghost rules above to every access;
+//   Fast is for tiles whose stencils reach no wall: offsets precomputed per
+//        thread (periodic wrap folded in), z metrics of planes k-1..k+1 in
+//        registers, no branch per access.
+struct Gen {
+    const FGrid &G;
+    int i, j, k;
+    __device__ __forceinline__ double cv(const double *q, int a, int b, int c) const
+    {
+        return flow::cv(G, q, i + a, j + b, k + c);
     }
-}
-
-// the same for the linear map b0 + b1 q of the cell values (density or
-// viscosity of the phase indicator q), mapped cell by cell
-template <int D>
-__device__ __forceinline__ double cface_map(const FGrid &G, const double *q, double b0, double b1, int i, int j, int k)
-{
-    const double q0 = b0 + b1 * cv(G, q, i, j, k);
-    if constexpr (D == 0) return 0.5 * (q0 + (b0 + b1 * cv(G, q, i + 1, j, k)));
-    else if constexpr (D == 1) return 0.5 * (q0 + (b0 + b1 * cv(G, q, i, j + 1, k)));
-    else {
-        const double q1 = b0 + b1 * cv(G, q, i, j, k + 1);
-        return (q0 * dzf_at(G, k + 1) + q1 * dzf_at(G, k)) / (2.0 * dzc_at(G, k));
+    template <int C>
+    __device__ __forceinline__ double fv(const double *q, int a, int b, int c) const
+    {
+        return flow::fv<C>(G, q, i + a, j + b, k + c);
     }
-}
+    // is the +D face of the cell s steps along D a wall?
+    template <int D> __device__ __forceinline__ bool wall(int s) const
+    {
+        return wallf(G, D, (D == 0 ? i : (D == 1 ? j : k)) + s);
+    }
+    __device__ __forceinline__ double dzf(int s) const { return dzf_at(G, k + s); }
+    __device__ __forceinline__ double dzc(int s) const { return dzc_at(G, k + s); }
+    __device__ __forceinline__ double h(int d) const { return G.h[d]; }
+    // reciprocals: 1/h, 1/dzf(s), 1/dzc(s), 1/(dzc(0) + dzc(-1)), 1/(dzf(0) + dzf(1))
+    __device__ __forceinline__ double ih(int d) const { return 1.0 / G.h[d]; }
+    __device__ __forceinline__ double izf(int s) const { return 1.0 / dzf(s); }
+    __device__ __forceinline__ double izc(int s) const { return 1.0 / dzc(s); }
+    __device__ __forceinline__ double izc2() const { return 1.0 / (dzc(0) + dzc(-1)); }
+    __device__ __forceinline__ double izf2() const { return 1.0 / (dzf(0) + dzf(1)); }
+    __device__ __forceinline__ size_t idx(int a, int b, int c) const
+    {
+        return at(G, cwrap(G, 0, i + a), cwrap(G, 1, j + b), cwrap(G, 2, k + c));
+    }
+};
 
-template <int D>
-__device__ __forceinline__ double cgrad(const FGrid &G, const double *q, int i, int j, int k)
+struct Fast {
+    size_t c0;
+    long xm, xp, ym, yp, zm, zp;
+    double zf_m, zf_0, zf_p, zc_m, zc_0, hx, hy;
+    double ihx, ihy, izf_0, izf_p, izc_m, izc_0, izc2_, izf2_;
+    __device__ __forceinline__ Fast(const FGrid &G, int i, int j, int k)
+    {
+        const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
+        const long sy = nx, sz = (long)nx * ny;
+        c0 = at(G, i, j, k);
+        xm = i == 0 ? nx - 1 : -1;
+        xp = i == nx - 1 ? -(nx - 1) : 1;
+        ym = j == 0 ? (ny - 1) * sy : -sy;
+        yp = j == ny - 1 ? -(ny - 1) * sy : sy;
+        zm = k == 0 ? (nz - 1) * sz : -sz;
+        zp = k == nz - 1 ? -(nz - 1) * sz : sz;
+        zf_m = dzf_at(G, k - 1);
+        zf_0 = G.dzf[k];
+        zf_p = dzf_at(G, k + 1);
+        zc_m = dzc_at(G, k - 1);
+        zc_0 = dzc_at(G, k);
+        hx = G.h[0];
+        hy = G.h[1];
+        ihx = 1.0 / hx;
+        ihy = 1.0 / hy;
+        izf_0 = 1.0 / zf_0;
+        izf_p = 1.0 / zf_p;
+        izc_m = 1.0 / zc_m;
+        izc_0 = 1.0 / zc_0;
+        izc2_ = 1.0 / (zc_0 + zc_m);
+        izf2_ = 1.0 / (zf_0 + zf_p);
+    }
+    __device__ __forceinline__ long off(int a, int b, int c) const
+    {
+        return (a < 0 ? xm : (a > 0 ? xp : 0)) + (b < 0 ? ym : (b > 0 ? yp : 0)) + (c < 0 ? zm : (c > 0 ? zp : 0));
+    }
+    __device__ __forceinline__ double cv(const double *q, int a, int b, int c) const { return q[c0 + off(a, b, c)]; }
+    template <int C>
+    __device__ __forceinline__ double fv(const double *q, int a, int b, int c) const
+    {
+        return q[c0 + off(a, b, c)];
+    }
+    template <int D> __device__ __forceinline__ bool wall(int) const { return false; }
+    __device__ __forceinline__ double dzf(int s) const { return s < 0 ? zf_m : (s > 0 ? zf_p : zf_0); }
+    __device__ __forceinline__ double dzc(int s) const { return s < 0 ? zc_m : zc_0; }
+    __device__ __forceinline__ double h(int d) const { return d == 0 ? hx : hy; }
+    __device__ __forceinline__ double ih(int d) const { return d == 0 ? ihx : ihy; }
+    __device__ __forceinline__ double izf(int s) const { return s > 0 ? izf_p : izf_0; } // s in {0, 1}
+    __device__ __forceinline__ double izc(int s) const { return s < 0 ? izc_m : izc_0; }
+    __device__ __forceinline__ double izc2() const { return izc2_; }
+    __device__ __forceinline__ double izf2() const { return izf2_; }
+    __device__ __forceinline__ size_t idx(int a, int b, int c) const { return c0 + off(a, b, c); }
+};
+
+// offset (a, b, c) of s steps along direction D
+#define DOFF(D, s) ((D) == 0 ? (s) : 0), ((D) == 1 ? (s) : 0), ((D) == 2 ? (s) : 0)
+
+// cell width along D; centre spacing from the cell s steps along D to the next
+template <class X> __device__ __forceinline__ double ihcell(const X &x, int D) { return D < 2 ? x.ih(D) : x.izf(0); }
+template <class X> __device__ __forceinline__ double ihcen(const X &x, int D, int s) { return D < 2 ? x.ih(D) : x.izc(s); }
+
+// cell quantity b0 + b1 q on the +D face of the cell s steps along D: mean
+// in x, y, linear interpolation in z
+template <int D, class X>
+__device__ __forceinline__ double cface(const X &x, const double *q, int s, double b0 = 0.0, double b1 = 1.0)
 {
-    constexpr int oi = D == 0, oj = D == 1, ok = D == 2;
-    return (cv(G, q, i + oi, j + oj, k + ok) - cv(G, q, i, j, k)) / hcen(G, D, k);
+    const double q0 = b0 + b1 * x.cv(q, DOFF(D, s)), q1 = b0 + b1 * x.cv(q, DOFF(D, s + 1));
+    if constexpr (D < 2) return 0.5 * (q0 + q1);
+    else return (q0 * x.dzf(s + 1) + q1 * x.dzf(s)) * (0.5 * x.izc(s));
 }
 
+// difference quotient of a cell quantity across that face
+template <int D, class X> __device__ __forceinline__ double cgrad(const X &x, const double *q, int s)
+{
+    return (x.cv(q, DOFF(D, s + 1)) - x.cv(q, DOFF(D, s))) * ihcen(x, D, s);
+}
+
+// psi of phi clamped to [0, 1] (rounding can leave phi a few ulps outside,
+// where the logarithm is undefined)
 __device__ __forceinline__ double psi_of(const FParams &P, double phi)
 {
-    return P.eps * log((phi + P.eps_s) / (1.0 - phi + P.eps_s));
+    const double q = fmin(fmax(phi, 0.0), 1.0);
+    return P.eps * log((q + P.eps_s) / (1.0 - q + P.eps_s));
 }
 
 // ---------------------------------------------------------------- passes
 
-// psi and the unit normal grad psi / |grad psi| at cell (i, j, k)
-__device__ __forceinline__ void normal_cell(const FGrid &G, const FParams &P, const double *phi, int i, int j, int k,
-                                            double &psi, double &nx, double &ny, double &nz)
+// the unit normal grad psi / |grad psi| at the cell, from stored psi
+template <class X>
+__device__ __forceinline__ void normal_cell(const X &x, const double *psi, double &nx, double &ny, double &nz)
 {
-    psi = psi_of(P, cv(G, phi, i, j, k));
-    const double gx = (psi_of(P, cv(G, phi, i + 1, j, k)) - psi_of(P, cv(G, phi, i - 1, j, k))) / (2.0 * G.h[0]);
-    const double gy = (psi_of(P, cv(G, phi, i, j + 1, k)) - psi_of(P, cv(G, phi, i, j - 1, k))) / (2.0 * G.h[1]);
-    const double gz = (psi_of(P, cv(G, phi, i, j, k + 1)) - psi_of(P, cv(G, phi, i, j, k - 1))) /
-                      (dzc_at(G, k) + dzc_at(G, k - 1));
+    const double gx = (x.cv(psi, 1, 0, 0) - x.cv(psi, -1, 0, 0)) * (0.5 * x.ih(0));
+    const double gy = (x.cv(psi, 0, 1, 0) - x.cv(psi, 0, -1, 0)) * (0.5 * x.ih(1));
+    const double gz = (x.cv(psi, 0, 0, 1) - x.cv(psi, 0, 0, -1)) * x.izc2();
     const double m = sqrt(gx * gx + gy * gy + gz * gz);
     if (m > 0.0) {
-        nx = gx / m;
-        ny = gy / m;
-        nz = gz / m;
+        const double im = 1.0 / m;
+        nx = gx * im;
+        ny = gy * im;
+        nz = gz * im;
     } else {
         nx = ny = nz = 0.0;
     }
 }
 
-// regularization flux on the +D face of (i, j, k) (0 on a wall face)
-template <int D>
-__device__ __forceinline__ double flux_face(const FGrid &G, const FParams &P, const double *phi, const double *psi,
-                                            const double *nd, int i, int j, int k)
+// regularization flux on the +D face of the cell (0 on a wall face)
+template <int D, class X>
+__device__ __forceinline__ double flux_face(const X &x, const FParams &P, const double *phi, const double *psi,
+                                            const double *nd)
 {
-    const int s = D == 0 ? i : (D == 1 ? j : k);
-    if (wallf(G, D, s)) return 0.0;
-    const double t = tanh(cface<D>(G, psi, i, j, k) / (2.0 * P.eps));
-    return P.gamma * (P.eps * cgrad<D>(G, phi, i, j, k) - 0.25 * (1.0 - t * t) * cface<D>(G, nd, i, j, k));
+    if (x.template wall<D>(0)) return 0.0;
+    const double t = tanh(cface<D>(x, psi, 0) * P.ihe);
+    return P.gamma * (P.eps * cgrad<D>(x, phi, 0) - 0.25 * (1.0 - t * t) * cface<D>(x, nd, 0));
 }
 
-// face normal component D on the +D face (0 on a wall face)
-template <int D>
-__device__ __forceinline__ double nface(const FGrid &G, const double *nd, int i, int j, int k)
+// normal component D on the +D face of the cell s steps along D (0 on walls)
+template <int D, class X> __device__ __forceinline__ double nface(const X &x, const double *nd, int s)
 {
-    const int s = D == 0 ? i : (D == 1 ? j : k);
-    return wallf(G, D, s) ? 0.0 : cface<D>(G, nd, i, j, k);
+    return x.template wall<D>(s) ? 0.0 : cface<D>(x, nd, s);
 }
 
 // curvature -div n_f at the cell
-__device__ __forceinline__ double curvature_cell(const FGrid &G, const double *const n[3], int i, int j, int k)
+template <class X> __device__ __forceinline__ double curvature_cell(const X &x, const double *const n[3])
 {
-    const double sx = nface<0>(G, n[0], i, j, k) - (wallf(G, 0, i - 1) ? 0.0 : nface<0>(G, n[0], cwrap(G, 0, i - 1), j, k));
-    const double sy = nface<1>(G, n[1], i, j, k) - (wallf(G, 1, j - 1) ? 0.0 : nface<1>(G, n[1], i, cwrap(G, 1, j - 1), k));
-    const double sz = nface<2>(G, n[2], i, j, k) - (wallf(G, 2, k - 1) ? 0.0 : nface<2>(G, n[2], i, j, cwrap(G, 2, k - 1)));
-    return -(sx / G.h[0] + sy / G.h[1] + sz / G.dzf[k]);
+    const double sx = nface<0>(x, n[0], 0) - nface<0>(x, n[0], -1);
+    const double sy = nface<1>(x, n[1], 0) - nface<1>(x, n[1], -1);
+    const double sz = nface<2>(x, n[2], 0) - nface<2>(x, n[2], -1);
+    return -(sx * x.ih(0) + sy * x.ih(1) + sz * x.izf(0));
 }
 
-// net phase flux u phi_f - a through the +D face of (i, j, k), 0 on walls
-template <int D>
-__device__ __forceinline__ double jface(const FGrid &G, const double *phi, const double *vel, const double *ad, int i,
-                                        int j, int k)
+// net phase flux u phi_f - a through the +D face of the cell s steps along D
+template <int D, class X>
+__device__ __forceinline__ double jface(const X &x, const double *phi, const double *vel, const double *ad, int s)
 {
-    const int s = D == 0 ? i : (D == 1 ? j : k);
-    if (wallf(G, D, s)) return 0.0;
-    return fv<D>(G, vel, i, j, k) * cface<D>(G, phi, i, j, k) - ad[at(G, i, j, k)];
+    if (x.template wall<D>(s)) return 0.0;
+    return x.template fv<D>(vel, DOFF(D, s)) * cface<D>(x, phi, s) - ad[x.idx(DOFF(D, s))];
 }
 
 // -div(u phi_f - a) at the cell
-__device__ __forceinline__ double acdi_cell(const FGrid &G, const double *phi, const double *const vel[3],
-                                            const double *const a[3], int i, int j, int k)
+template <class X>
+__device__ __forceinline__ double acdi_cell(const X &x, const double *phi, const double *const vel[3],
+                                            const double *const a[3])
 {
-    double r = 0.0;
-    {
-        const double jp = jface<0>(G, phi, vel[0], a[0], i, j, k);
-        const double jm = wallf(G, 0, i - 1) ? 0.0 : jface<0>(G, phi, vel[0], a[0], cwrap(G, 0, i - 1), j, k);
-        r -= (jp - jm) / G.h[0];
-    }
-    {
-        const double jp = jface<1>(G, phi, vel[1], a[1], i, j, k);
-        const double jm = wallf(G, 1, j - 1) ? 0.0 : jface<1>(G, phi, vel[1], a[1], i, cwrap(G, 1, j - 1), k);
-        r -= (jp - jm) / G.h[1];
-    }
-    {
-        const double jp = jface<2>(G, phi, vel[2], a[2], i, j, k);
-        const double jm = wallf(G, 2, k - 1) ? 0.0 : jface<2>(G, phi, vel[2], a[2], i, j, cwrap(G, 2, k - 1));
-        r -= (jp - jm) / G.dzf[k];
-    }
+    double r = -(jface<0>(x, phi, vel[0], a[0], 0) - jface<0>(x, phi, vel[0], a[0], -1)) * x.ih(0);
+    r -= (jface<1>(x, phi, vel[1], a[1], 0) - jface<1>(x, phi, vel[1], a[1], -1)) * x.ih(1);
+    r -= (jface<2>(x, phi, vel[2], a[2], 0) - jface<2>(x, phi, vel[2], a[2], -1)) * x.izf(0);
     return r;
 }
 
-// mean of a cell quantity over the four cells around the edge touching the
-// +A and +B faces of (i, j, k)
-template <int A, int B>
-__device__ __forceinline__ double edge_mean(const FGrid &G, const double *q, double b0, double b1, int i, int j, int k)
+// mean of b0 + b1 q over the four cells around the edge touching the +A and
+// +B faces of the cell s steps along B
+template <int A, int B, class X>
+__device__ __forceinline__ double edge_mean(const X &x, const double *q, double b0, double b1, int s)
 {
     constexpr int ai = A == 0, aj = A == 1, ak = A == 2, bi = B == 0, bj = B == 1, bk = B == 2;
-    return 0.25 * ((b0 + b1 * cv(G, q, i, j, k)) + (b0 + b1 * cv(G, q, i + ai, j + aj, k + ak)) +
-                   (b0 + b1 * cv(G, q, i + bi, j + bj, k + bk)) +
-                   (b0 + b1 * cv(G, q, i + ai + bi, j + aj + bj, k + ak + bk)));
+    return 0.25 * ((b0 + b1 * x.cv(q, s * bi, s * bj, s * bk)) + (b0 + b1 * x.cv(q, ai + s * bi, aj + s * bj, ak + s * bk)) +
+                   (b0 + b1 * x.cv(q, (s + 1) * bi, (s + 1) * bj, (s + 1) * bk)) +
+                   (b0 + b1 * x.cv(q, ai + (s + 1) * bi, aj + (s + 1) * bj, ak + (s + 1) * bk)));
 }
 
 // component D of the regularization flux at the position of the +C face:
 // its own value when D == C, else the mean of the four D faces around
-template <int C, int D>
-__device__ __forceinline__ double a_at(const FGrid &G, const double *ad, int i, int j, int k)
+// (wall faces carry none)
+template <int C, int D, class X> __device__ __forceinline__ double a_at(const X &x, const double *ad)
 {
     if constexpr (C == D) {
-        return ad[at(G, i, j, k)];
+        return ad[x.idx(0, 0, 0)];
     } else {
         constexpr int ci = C == 0, cj = C == 1, ck = C == 2, di = D == 0, dj = D == 1, dk = D == 2;
-        const int ix[4][3] = {{i, j, k}, {i + ci, j + cj, k + ck}, {i - di, j - dj, k - dk},
-                              {i + ci - di, j + cj - dj, k + ck - dk}};
         double s = 0.0;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            int q[3] = {ix[t][0], ix[t][1], ix[t][2]};
-            if (wallf(G, D, q[D])) continue;
-#pragma unroll
-            for (int e = 0; e < 3; ++e) {
-                if (q[e] < 0) q[e] += G.n[e];
-                else if (q[e] >= G.n[e]) q[e] -= G.n[e];
-            }
-            s += ad[at(G, q[0], q[1], q[2])];
-        }
+        if (!x.template wall<D>(0)) s += ad[x.idx(0, 0, 0)] + ad[x.idx(ci, cj, ck)];
+        if (!x.template wall<D>(-1)) s += ad[x.idx(-di, -dj, -dk)] + ad[x.idx(ci - di, cj - dj, ck - dk)];
         return 0.25 * s;
     }
 }
 
-// Transverse (D != C) contribution to the advection, viscous stress and
-// regularization terms of component C on its +C face.
-template <int C, int D>
-__device__ __forceinline__ void mom_transverse(const FGrid &G, const FParams &P, const double *const vel[3],
-                                               const double *phi, int i, int j, int k, double q0, double hc,
-                                               double &adv, double &visc)
+// Transverse (D != C) contribution to the advection and viscous terms of
+// component C on its +C face.
+template <int C, int D, class X>
+__device__ __forceinline__ void mom_transverse(const X &x, const FParams &P, const double *const vel[3],
+                                               const double *phi, double q0, double ihc, double &adv, double &visc)
 {
     constexpr int ci = C == 0, cj = C == 1, ck = C == 2, di = D == 0, dj = D == 1, dk = D == 2;
     const double *q = vel[C], *p = vel[D];
-    const int sd = D == 0 ? i : (D == 1 ? j : k);
-    const double pu0 = fv<D>(G, p, i, j, k), pu1 = fv<D>(G, p, i + ci, j + cj, k + ck);
-    const double pd0 = fv<D>(G, p, i - di, j - dj, k - dk), pd1 = fv<D>(G, p, i + ci - di, j + cj - dj, k + ck - dk);
-    const double qu = fv<C>(G, q, i + di, j + dj, k + dk), qd = fv<C>(G, q, i - di, j - dj, k - dk);
-    const double hd = hcell(G, D, k);
-    adv += (0.5 * (pu0 + pu1) * 0.5 * (q0 + qu) - 0.5 * (pd0 + pd1) * 0.5 * (qd + q0)) / hd;
+    const double pu0 = x.template fv<D>(p, 0, 0, 0), pu1 = x.template fv<D>(p, ci, cj, ck);
+    const double pd0 = x.template fv<D>(p, -di, -dj, -dk), pd1 = x.template fv<D>(p, ci - di, cj - dj, ck - dk);
+    const double qu = x.template fv<C>(q, di, dj, dk), qd = x.template fv<C>(q, -di, -dj, -dk);
+    const double ihd = ihcell(x, D);
+    adv += (0.5 * (pu0 + pu1) * 0.5 * (q0 + qu) - 0.5 * (pd0 + pd1) * 0.5 * (qd + q0)) * ihd;
     const double m0 = P.mu2, m1 = P.mu1 - P.mu2;
-    const double muu = edge_mean<C, D>(G, phi, m0, m1, i, j, k);
-    const double mud = edge_mean<C, D>(G, phi, m0, m1, i - di, j - dj, k - dk);
-    const double tu = muu * ((qu - q0) / hcen(G, D, sd) + (pu1 - pu0) / hc);
-    const double td = mud * ((q0 - qd) / hcen(G, D, sd - 1) + (pd1 - pd0) / hc);
-    visc += (tu - td) / hd;
+    const double muu = edge_mean<C, D>(x, phi, m0, m1, 0);
+    const double mud = edge_mean<C, D>(x, phi, m0, m1, -1);
+    const double tu = muu * ((qu - q0) * ihcen(x, D, 0) + (pu1 - pu0) * ihc);
+    const double td = mud * ((q0 - qd) * ihcen(x, D, -1) + (pd1 - pd0) * ihc);
+    visc += (tu - td) * ihd;
 }
 
-template <int C, int D>
-__device__ __forceinline__ double mom_reg(const FGrid &G, const double *const vel[3], const double *const a[3], int i,
-                                          int j, int k)
+template <int C, int D, class X>
+__device__ __forceinline__ double mom_reg(const X &x, const double *const vel[3], const double *const a[3])
 {
     constexpr int di = D == 0, dj = D == 1, dk = D == 2;
     const double *q = vel[C];
-    const int sd = D == 0 ? i : (D == 1 ? j : k);
-    const double qp = fv<C>(G, q, i + di, j + dj, k + dk), qm = fv<C>(G, q, i - di, j - dj, k - dk);
-    double h;
-    if constexpr (C == D) h = (D < 2 ? 2.0 * G.h[D] : dzf_at(G, k) + dzf_at(G, k + 1));
-    else h = hcen(G, D, sd) + hcen(G, D, sd - 1);
-    return a_at<C, D>(G, a[D], i, j, k) * (qp - qm) / h;
+    const double qp = x.template fv<C>(q, di, dj, dk), qm = x.template fv<C>(q, -di, -dj, -dk);
+    double ih;
+    if constexpr (C == D) ih = D < 2 ? 0.5 * x.ih(D) : x.izf2();
+    else ih = D < 2 ? 0.5 * x.ih(D) : x.izc2();
+    return a_at<C, D>(x, a[D]) * (qp - qm) * ih;
 }
 
 // Momentum right-hand side per unit mass of component C on the +C face of
-// (i, j, k), which is not a wall face.
-template <int C>
-__device__ __forceinline__ double mom_face(const FGrid &G, const FParams &P, const double *phi, const double *kap,
-                                           const double *const vel[3], const double *const a[3], int i, int j, int k)
+// the cell, which is not a wall face.
+template <int C, class X>
+__device__ __forceinline__ double mom_face(const X &x, const FParams &P, const double *phi, const double *kap,
+                                           const double *const vel[3], const double *const a[3])
 {
     constexpr int ci = C == 0, cj = C == 1, ck = C == 2;
     const double *q = vel[C];
-    const int sc = C == 0 ? i : (C == 1 ? j : k);
-    const double q0 = fv<C>(G, q, i, j, k);
-    const double hc = hcen(G, C, sc);
+    const double q0 = x.template fv<C>(q, 0, 0, 0);
+    const double ihc = ihcen(x, C, 0);
     double adv, visc;
     {
-        const double qm = fv<C>(G, q, i - ci, j - cj, k - ck), qp = fv<C>(G, q, i + ci, j + cj, k + ck);
+        const double qm = x.template fv<C>(q, -ci, -cj, -ck), qp = x.template fv<C>(q, ci, cj, ck);
         const double cm = 0.5 * (qm + q0), cp = 0.5 * (q0 + qp);
-        adv = (cp * cp - cm * cm) / hc;
-        const double h1 = C < 2 ? G.h[C] : dzf_at(G, k + 1), h0 = C < 2 ? G.h[C] : G.dzf[k];
-        const double mu1 = P.mu2 + (P.mu1 - P.mu2) * cv(G, phi, i + ci, j + cj, k + ck);
-        const double mu0 = P.mu2 + (P.mu1 - P.mu2) * cv(G, phi, i, j, k);
-        const double tp = 2.0 * mu1 * (qp - q0) / h1;
-        const double tm = 2.0 * mu0 * (q0 - qm) / h0;
-        visc = (tp - tm) / hc;
+        adv = (cp * cp - cm * cm) * ihc;
+        const double ih1 = C < 2 ? x.ih(C) : x.izf(1), ih0 = C < 2 ? x.ih(C) : x.izf(0);
+        const double mu1 = P.mu2 + (P.mu1 - P.mu2) * x.cv(phi, ci, cj, ck);
+        const double mu0 = P.mu2 + (P.mu1 - P.mu2) * x.cv(phi, 0, 0, 0);
+        const double tp = 2.0 * mu1 * (qp - q0) * ih1;
+        const double tm = 2.0 * mu0 * (q0 - qm) * ih0;
+        visc = (tp - tm) * ihc;
     }
-    if constexpr (C != 0) mom_transverse<C, 0>(G, P, vel, phi, i, j, k, q0, hc, adv, visc);
-    if constexpr (C != 1) mom_transverse<C, 1>(G, P, vel, phi, i, j, k, q0, hc, adv, visc);
-    if constexpr (C != 2) mom_transverse<C, 2>(G, P, vel, phi, i, j, k, q0, hc, adv, visc);
-    const double reg = mom_reg<C, 0>(G, vel, a, i, j, k) + mom_reg<C, 1>(G, vel, a, i, j, k) +
-                       mom_reg<C, 2>(G, vel, a, i, j, k);
-    const double st = P.sigma * cface<C>(G, kap, i, j, k) * cgrad<C>(G, phi, i, j, k);
-    const double rf = cface_map<C>(G, phi, P.rho2, P.rho1 - P.rho2, i, j, k);
+    if constexpr (C != 0) mom_transverse<C, 0>(x, P, vel, phi, q0, ihc, adv, visc);
+    if constexpr (C != 1) mom_transverse<C, 1>(x, P, vel, phi, q0, ihc, adv, visc);
+    if constexpr (C != 2) mom_transverse<C, 2>(x, P, vel, phi, q0, ihc, adv, visc);
+    const double reg = mom_reg<C, 0>(x, vel, a) + mom_reg<C, 1>(x, vel, a) + mom_reg<C, 2>(x, vel, a);
+    const double st = P.sigma * cface<C>(x, kap, 0) * cgrad<C>(x, phi, 0);
+    const double rf = cface<C>(x, phi, 0, P.rho2, P.rho1 - P.rho2);
     return -adv + (visc + st + (P.rho1 - P.rho2) * reg) / rf + P.g[C];
 }
 

@@ -27,6 +27,7 @@ struct pcx_flow_s {
     double *tab = nullptr;           // dzf, dzc
     double *ws = nullptr;            // NWS fields
     unsigned long long *key = nullptr;
+    unsigned long long *part = nullptr; // per-workgroup minimum keys
     size_t ncell = 0;
     double *psi, *n[3], *a[3], *kap, *rho_new, *pstar, *us[3];
 };
@@ -38,6 +39,7 @@ static void flow_free(pcx_flow F)
     if (F->tab) (void)hipFree(F->tab);
     if (F->ws) (void)hipFree(F->ws);
     if (F->key) (void)hipFree(F->key);
+    if (F->part) (void)hipFree(F->part);
     delete F;
 }
 
@@ -91,7 +93,11 @@ extern "C" pcx_status pcx_flow_create(const pcx_grid *grid, const pcx_flow_param
     G.h[1] = grid->ly / ny;
     G.dzf = F->tab;
     G.dzc = F->tab + nz;
-    F->P = FParams{q.rho1, q.rho2, q.mu1, q.mu2, q.sigma, {q.gx, q.gy, q.gz}, q.gamma, q.eps, q.eps_s};
+    F->P = FParams{q.rho1, q.rho2, q.mu1, q.mu2, q.sigma, {q.gx, q.gy, q.gz}, q.gamma, q.eps, q.eps_s, 0.5 / q.eps};
+    if (hipMalloc(&F->part, (size_t)ngrid(G) * sizeof(unsigned long long)) != hipSuccess) {
+        flow_free(F);
+        return fail(PCX_ERR_NOMEM, "flow workspace allocation failed");
+    }
     double *w = F->ws;
     auto take = [&]() { double *p = w; w += F->ncell; return p; };
     F->psi = take();
@@ -130,6 +136,7 @@ static FArgs base_args(pcx_flow F, const double *phi, const double *u, const dou
     A.kap = F->kap;
     A.first = 1;
     A.rho_min_key = F->key;
+    A.rho_part = F->part;
     return A;
 }
 

@@ -15,6 +15,7 @@ constexpr int FT = 256, FTI = 64, FTJ = FT / FTI;
 struct FTile {
     int i, j, k;
     bool act;
+    bool fast; // no stencil of the tile reaches a wall (uniform over the workgroup)
 };
 
 __device__ __forceinline__ FTile ftile(const FGrid &G)
@@ -34,17 +35,37 @@ __device__ __forceinline__ FTile ftile(const FGrid &G)
     c.j = jt * FTJ + (threadIdx.x / FTI);
     c.k = k;
     c.act = c.i < G.n[0] && c.j < G.n[1];
+    // the stencils reach one cell (and one face) beyond the cell: a wall
+    // direction needs the tile within [1, n-3]
+    const int i0 = it * FTI, j0 = jt * FTJ;
+    c.fast = (G.per[0] || (i0 >= 1 && i0 + FTI - 1 <= G.n[0] - 3)) &&
+             (G.per[1] || (j0 >= 1 && j0 + FTJ - 1 <= G.n[1] - 3)) && (G.per[2] || (k >= 1 && k <= G.n[2] - 3));
     return c;
+}
+
+// runs body(accessor) with the branch-free interior accessor on tiles that
+// reach no wall, the general one elsewhere
+template <class Body> __device__ __forceinline__ void with_acc(const FGrid &G, const FTile &t, Body body)
+{
+    if (t.fast) body(Fast(G, t.i, t.j, t.k));
+    else body(Gen{G, t.i, t.j, t.k});
+}
+
+// psi of every cell (one logarithm per cell), then the normals from it
+__global__ __launch_bounds__(FT) void k_flow_psi(FArgs A)
+{
+    const size_t n = (size_t)A.G.n[0] * A.G.n[1] * A.G.n[2];
+    const size_t c = (size_t)blockIdx.x * FT + threadIdx.x;
+    if (c < n) A.psi[c] = psi_of(A.P, A.phi[c]);
 }
 
 __global__ __launch_bounds__(FT) void k_flow_normals(FArgs A)
 {
     const FTile t = ftile(A.G);
     if (!t.act) return;
-    double psi, nx, ny, nz;
-    normal_cell(A.G, A.P, A.phi, t.i, t.j, t.k, psi, nx, ny, nz);
+    double nx, ny, nz;
+    with_acc(A.G, t, [&](const auto &x) { normal_cell(x, A.psi, nx, ny, nz); });
     const size_t c = at(A.G, t.i, t.j, t.k);
-    A.psi[c] = psi;
     A.n[0][c] = nx;
     A.n[1][c] = ny;
     A.n[2][c] = nz;
@@ -55,10 +76,12 @@ __global__ __launch_bounds__(FT) void k_flow_flux(FArgs A)
     const FTile t = ftile(A.G);
     if (!t.act) return;
     const size_t c = at(A.G, t.i, t.j, t.k);
-    A.a[0][c] = flux_face<0>(A.G, A.P, A.phi, A.psi, A.n[0], t.i, t.j, t.k);
-    A.a[1][c] = flux_face<1>(A.G, A.P, A.phi, A.psi, A.n[1], t.i, t.j, t.k);
-    A.a[2][c] = flux_face<2>(A.G, A.P, A.phi, A.psi, A.n[2], t.i, t.j, t.k);
-    A.kap[c] = curvature_cell(A.G, A.n, t.i, t.j, t.k);
+    with_acc(A.G, t, [&](const auto &x) {
+        A.a[0][c] = flux_face<0>(x, A.P, A.phi, A.psi, A.n[0]);
+        A.a[1][c] = flux_face<1>(x, A.P, A.phi, A.psi, A.n[1]);
+        A.a[2][c] = flux_face<2>(x, A.P, A.phi, A.psi, A.n[2]);
+        A.kap[c] = curvature_cell(x, A.n);
+    });
 }
 
 // order-preserving key of a double for atomicMin
@@ -69,7 +92,9 @@ __device__ __forceinline__ unsigned long long fkey(double v)
 }
 
 // Phase-field right-hand side; with phi_out, the substep's update, the new
-// density and its minimum (one atomicMin per workgroup).
+// density and the minimum key of the workgroup's densities (one slot per
+// workgroup, reduced by k_flow_min: an atomic per workgroup on one address
+// would serialize half a million workgroups).
 __global__ __launch_bounds__(FT) void k_flow_phase(FArgs A)
 {
     __shared__ unsigned long long red[FT / 64];
@@ -78,7 +103,8 @@ __global__ __launch_bounds__(FT) void k_flow_phase(FArgs A)
     if (t.act) {
         const size_t c = at(A.G, t.i, t.j, t.k);
         const double *vel[3] = {A.u, A.v, A.w};
-        const double r = acdi_cell(A.G, A.phi, vel, A.a, t.i, t.j, t.k);
+        double r = 0.0;
+        with_acc(A.G, t, [&](const auto &x) { r = acdi_cell(x, A.phi, vel, A.a); });
         if (A.phi_out) {
             const double old = A.first ? 0.0 : A.hphi[c];
             const double q = A.phi[c] + A.Dt * (A.ga * r + A.ze * old);
@@ -100,42 +126,76 @@ __global__ __launch_bounds__(FT) void k_flow_phase(FArgs A)
     if (threadIdx.x == 0) {
         for (int i = 1; i < FT / 64; ++i) key = red[i] < key ? red[i] : key;
         key = red[0] < key ? red[0] : key;
-        atomicMin(A.rho_min_key, key);
+        A.rho_part[blockIdx.x] = key;
     }
 }
 
-template <int C>
-__device__ __forceinline__ void mom_one(const FArgs &A, const FTile &t, size_t c, double *hc, const double *qc,
-                                        double *qs)
+// minimum of the n workgroup keys into *rho_min_key (a few workgroups, one
+// atomic each)
+__global__ __launch_bounds__(FT) void k_flow_min(const unsigned long long *part, int n, unsigned long long *key_out)
+{
+    __shared__ unsigned long long red[FT / 64];
+    unsigned long long key = ~0ull;
+    for (int i = blockIdx.x * FT + threadIdx.x; i < n; i += gridDim.x * FT) key = part[i] < key ? part[i] : key;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long x = __shfl_xor(key, o, 64);
+        key = x < key ? x : key;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = key;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < FT / 64; ++i) key = red[i] < key ? red[i] : key;
+        key = red[0] < key ? red[0] : key;
+        atomicMin(key_out, key);
+    }
+}
+
+template <int C, class X>
+__device__ __forceinline__ double mom_rhs(const FArgs &A, const X &x, const FTile &t)
 {
     const int s = C == 0 ? t.i : (C == 1 ? t.j : t.k);
     const double *vel[3] = {A.u, A.v, A.w};
-    double m = 0.0;
-    if (!wallf(A.G, C, s)) m = mom_face<C>(A.G, A.P, A.phi, A.kap, vel, A.a, t.i, t.j, t.k);
+    return wallf(A.G, C, s) ? 0.0 : mom_face<C>(x, A.P, A.phi, A.kap, vel, A.a);
+}
+
+// this substep's right-hand side m into hc (the previous one read first)
+// and, with u*, the predictor (0 on a wall face: the correction ignores it)
+template <int C>
+__device__ __forceinline__ void mom_store(const FArgs &A, const FTile &t, size_t c, double m, double *hc,
+                                          const double *qc, double *qs)
+{
+    const int s = C == 0 ? t.i : (C == 1 ? t.j : t.k);
     if (qs) {
         const double old = A.first ? 0.0 : hc[c];
-        // the wall face of u* is written 0 (the correction ignores it)
         qs[c] = wallf(A.G, C, s) ? 0.0 : qc[c] + A.Dt * (A.ga * m + A.ze * old);
     }
     hc[c] = m;
 }
 
-// Momentum right-hand side of the three components; with u*, the
-// substep's predictor; with p*, the extrapolated pressure.
+// Momentum right-hand side of the three components (all loads before any
+// store); with u*, the substep's predictor; with p*, the extrapolated
+// pressure.
 __global__ __launch_bounds__(FT) void k_flow_momentum(FArgs A)
 {
     const FTile t = ftile(A.G);
     if (!t.act) return;
     const size_t c = at(A.G, t.i, t.j, t.k);
-    mom_one<0>(A, t, c, A.hu, A.u, A.us[0]);
-    mom_one<1>(A, t, c, A.hv, A.v, A.us[1]);
-    mom_one<2>(A, t, c, A.hw, A.w, A.us[2]);
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+    with_acc(A.G, t, [&](const auto &x) {
+        m0 = mom_rhs<0>(A, x, t);
+        m1 = mom_rhs<1>(A, x, t);
+        m2 = mom_rhs<2>(A, x, t);
+    });
+    mom_store<0>(A, t, c, m0, A.hu, A.u, A.us[0]);
+    mom_store<1>(A, t, c, m1, A.hv, A.v, A.us[1]);
+    mom_store<2>(A, t, c, m2, A.hw, A.w, A.us[2]);
     if (A.pstar) A.pstar[c] = (1.0 + A.r) * A.p1[c] - A.r * A.p2[c];
 }
 
 __global__ void k_flow_key_reset(unsigned long long *k) { *k = ~0ull; }
 
-static int ngrid(const FGrid &G)
+int ngrid(const FGrid &G)
 {
     const long nt = (long)((G.n[0] + FTI - 1) / FTI) * ((G.n[1] + FTJ - 1) / FTJ) * G.n[2];
     return (int)(((nt + 7) >> 3) << 3);
@@ -147,7 +207,14 @@ static int ngrid(const FGrid &G)
         return hipGetLastError();                                                    \
     } while (0)
 
-hipError_t launch_normals(const FArgs &A, hipStream_t s) { FLAUNCH(k_flow_normals, A, s); }
+hipError_t launch_normals(const FArgs &A, hipStream_t s)
+{
+    const size_t n = (size_t)A.G.n[0] * A.G.n[1] * A.G.n[2];
+    hipLaunchKernelGGL(k_flow_psi, dim3((unsigned)((n + FT - 1) / FT)), dim3(FT), 0, s, A);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    FLAUNCH(k_flow_normals, A, s);
+}
 hipError_t launch_flux(const FArgs &A, hipStream_t s) { FLAUNCH(k_flow_flux, A, s); }
 hipError_t launch_phase(const FArgs &A, hipStream_t s)
 {
@@ -156,7 +223,12 @@ hipError_t launch_phase(const FArgs &A, hipStream_t s)
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    FLAUNCH(k_flow_phase, A, s);
+    hipLaunchKernelGGL(k_flow_phase, dim3(ngrid(A.G)), dim3(FT), 0, s, A);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !A.phi_out) return e;
+    hipLaunchKernelGGL(k_flow_min, dim3(64), dim3(FT), 0, s, (const unsigned long long *)A.rho_part, ngrid(A.G),
+                       A.rho_min_key);
+    return hipGetLastError();
 }
 hipError_t launch_momentum(const FArgs &A, hipStream_t s) { FLAUNCH(k_flow_momentum, A, s); }
 

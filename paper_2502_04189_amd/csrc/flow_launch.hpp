@@ -19,6 +19,7 @@ struct FArgs {
     double *hphi, *hu, *hv, *hw;     // previous right-hand sides in, this substep's out
     double *phi_out, *us[3], *rho_new; // NULL: right-hand sides only
     unsigned long long *rho_min_key;
+    unsigned long long *rho_part;    // one key per workgroup of the phase pass (flow_grid of them)
     const double *p1, *p2;           // pressures of the two previous substeps
     double r;
     double *pstar;                   // NULL: no extrapolation
@@ -29,6 +30,8 @@ hipError_t launch_flux(const FArgs &A, hipStream_t s);
 hipError_t launch_phase(const FArgs &A, hipStream_t s);
 hipError_t launch_momentum(const FArgs &A, hipStream_t s);
 double key_to_double(unsigned long long k);
+// workgroups of a one-thread-per-cell launch over the grid
+int ngrid(const FGrid &G);
 
 } // namespace flow
 } // namespace pcx

@@ -164,3 +164,52 @@ def test_flow_taylor_green_on_the_gpu(pcx):
         F.close()
     _say(f"Taylor-Green errors {errs}")
     assert errs[0] < 2e-4 and errs[0] / errs[1] > 3.7
+
+
+def test_flow_bubble_channel_vs_oracle(pcx, orc):
+    """The benchmark's setup at 128^3: the bubble channel's phase field and
+    the velocity its pressure step corrects, gas/liquid properties, surface
+    tension and gravity; three substeps on the GPU against the oracle."""
+    import torch
+    c = W.channel_bubbles(128, 4, 1003, "channel128")
+    g = orc.Grid.from_workload(c.grid)
+    u, v, w, _, _ = orc.step(g, c.dt, c.rho0, *c.fields())
+    phi = (1000.0 - c.fields()[0]) / 999.0
+    umax = max(np.abs(u).max(), np.abs(v).max(), np.abs(w).max())
+    eps = 0.51 * c.grid.lx / c.grid.nx
+    prm = dict(rho1=1.0, rho2=1000.0, mu1=1e-5, mu2=1e-3, sigma=0.07, g=(0.0, 0.0, -9.81), gamma=2 * umax)
+    fl = orc.flow_params(eps=eps, **prm)
+    F = pcx.Flow(c.grid, eps=eps, **prm)
+    # the benchmark's step rule (advective and diffusive limits)
+    import bench
+    Dt = bench.flow_dt(c.grid, dict(prm, eps=eps), umax)
+    st_o, st_g = [phi, u, v, w], [to_dev(a) for a in (phi, u, v, w)]
+    ho = [np.zeros(c.grid.shape) for _ in range(4)]
+    hg = [torch.zeros(c.grid.shape, dtype=torch.float64, device="cuda") for _ in range(4)]
+    z = np.zeros(c.grid.shape)
+    po, pg = [z, z], [to_dev(z), to_dev(z)]
+    dtprev = None
+    for s in (1, 2, 3):
+        al = orc.rk3_coeffs(s)[2]
+        r = 0.0 if dtprev is None else al * Dt / dtprev
+        *outs_o, d = orc.flow_substep(g, fl, s, Dt, *st_o, po[0], po[1], r, ho)
+        outs_g = [torch.empty(c.grid.shape, dtype=torch.float64, device="cuda") for _ in range(5)]
+        rep = F.substep(s, Dt, *st_g, pg[0], pg[1], r, hg, outs_g)
+        got = [t.cpu().numpy() for t in outs_g]
+        e = {n: _rel(x, y) for n, x, y in zip(("phi", "u", "v", "w", "p"), got, outs_o)}
+        # divergence after the correction relative to the scale of the
+        # velocity differences, max|u|/h_min (with p* = 0 and a nearly
+        # solenoidal u*, f is small and the residual relative to ||f|| says
+        # little); the oracle's own value on the same inputs beside it
+        hmin = min(c.grid.lx / c.grid.nx, float(np.diff(c.grid.zf).min()))
+        uscale = max(np.abs(a).max() for a in got[1:4]) / hmin
+        _say(f"  channel substep {s}: errors {e}, phi in [{got[0].min():.3e}, {got[0].max():.9f}], "
+             f"max|Du| {rep['max_div_abs']:.3e} (relative to max|u|/h {rep['max_div_abs'] / uscale:.2e}; "
+             f"residual/||f|| {rep['max_div_rel']:.2e}, oracle's {d['max_div_rel']:.2e})")
+        assert max(e.values()) <= TOL
+        assert rep["max_div_abs"] <= 1e-12 * uscale
+        assert 0.0 <= got[0].min() + 1e-12 and got[0].max() <= 1.0
+        st_o, st_g = outs_o[:4], outs_g[:4]
+        po, pg = [outs_o[4], po[0]], [outs_g[4], pg[0]]
+        dtprev = al * Dt
+    F.close()
