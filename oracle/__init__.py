@@ -43,7 +43,7 @@ class OrDiag(C.Structure):
     ]
 
 
-SOURCES = ("oracle.c", "flow.c")
+SOURCES = ("oracle.c", "flow.c", "dirichlet.c")
 
 
 def build(force: bool = True) -> str:
@@ -89,6 +89,12 @@ def lib():
         L.oracle_cyclic.argtypes = [C.c_int, _DP, _DP, _DP, _DP]
         L.oracle_eig.argtypes = [C.c_int, C.c_double, C.c_int, C.c_int]
         L.oracle_eig.restype = C.c_double
+        if hasattr(L, "oracle_poisson_bc"):  # dirichlet.c
+            L.oracle_poisson_bc.argtypes = [G, _DP, _DP]
+            L.oracle_apply_L_bc.argtypes = [G, _DP, _DP]
+            L.oracle_eig_bc.argtypes = [C.c_int, C.c_double, C.c_int, C.c_int]
+            L.oracle_eig_bc.restype = C.c_double
+            L.oracle_has_dirichlet.argtypes = [G]
         if hasattr(L, "oracle_acdi_rhs"):  # flow.c (a mutant build of oracle.c alone lacks it)
             A, F = C.POINTER(OrAcdi), C.POINTER(OrFlow)
             L.oracle_acdi_normals.argtypes = [G, A] + [_DP] * 5
@@ -119,7 +125,8 @@ def _p(a: np.ndarray):
 
 
 class Grid:
-    """Grid/BC descriptor (bc: 0 periodic, 1 wall); zf holds nz+1 z faces."""
+    """Grid/BC descriptor (bc: 0 periodic, 1 wall, 2 Dirichlet -- the last
+    only for the *_bc Poisson functions); zf holds nz+1 z faces."""
 
     def __init__(self, nx, ny, nz, lx, ly, zf, bcx=0, bcy=0, bcz=1):
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
@@ -349,3 +356,25 @@ def flow_substep(g, fl, s, Dt, phi, u, v, w, p1, p2, r, h):
                                    *[_p(a) for a in h], *[_p(o) for o in outs], C.byref(d))
     _chk(rc, "flow_substep")
     return (*outs, {k: getattr(d, k) for k, _ in OrDiag._fields_})
+
+
+# ------------------------------------------------------------ dirichlet.c
+# Constant-coefficient Poisson solve with periodic, Neumann or homogeneous
+# Dirichlet directions (the direct solver of "Methods and Implementation
+# strategy" in its sine-transform variants); explicit eigenvector sums.
+
+def apply_L_bc(g, p):
+    out = np.empty(g.shape)
+    _chk(lib().oracle_apply_L_bc(g.cref, _p(_arr(p)), _p(out)), "apply_L_bc")
+    return out
+
+
+def poisson_bc(g, f):
+    """L p = f for a grid with a Dirichlet direction (non-singular)."""
+    out = np.empty(g.shape)
+    _chk(lib().oracle_poisson_bc(g.cref, _p(_arr(f)), _p(out)), "poisson_bc")
+    return out
+
+
+def eig_bc(n, h, bc, l):
+    return lib().oracle_eig_bc(int(n), float(h), int(bc), int(l))
