@@ -361,6 +361,39 @@ def flow_setup(case):
     return st, prm, umax
 
 
+def run_poisson(gs, steps, warmup):
+    """pcx_poisson_solve (FP64) on a random right-hand side: the benchmark's
+    own boundaries (x, y periodic, walls in z) and Dirichlet x and y (sine
+    transforms); spectral bytes per cell of the five passes: x 8 + sp,
+    y 2 sp, z 2 sp, y 2 sp, x sp + 8 (sp = 16 B of a complex mode per cell
+    pair, about 8 B per cell)."""
+    import torch
+    from paper_2502_04189_amd import pcx
+    from paper_2502_04189_amd import workloads as W
+    out = {}
+    f = torch.randn(gs.shape, dtype=torch.float64, device="cuda")
+    p = torch.empty_like(f)
+    for name, bc in (("periodic_x_y_wall_z", (gs.bcx, gs.bcy, gs.bcz)), ("dirichlet_x_y_wall_z", (2, 2, gs.bcz))):
+        g2 = W.GridSpec(gs.nx, gs.ny, gs.nz, gs.lx, gs.ly, gs.zf, *bc)
+        plan = pcx.Plan(g2, "fp64")
+        for _ in range(warmup):
+            plan.poisson_solve(f, p)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            plan.poisson_solve(f, p)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        sp = spectral_bytes(g2, 16) if bc[0] == 0 else gs.nx * gs.ny * gs.nz * 16
+        alg = 8 * gs.cells + sp + 6 * sp + sp + 8 * gs.cells
+        out[name] = {"ms": round(ms, 4), "alg_bytes": alg, "hbm_frac": round(alg / (ms * 1e-3) / 8e12, 4)}
+        plan.close()
+        log(f"poisson solve {name}: {ms:.3f} ms")
+    return out
+
+
 def flow_dt(gs, prm, umax):
     """Step of the explicit substeps: the advective limit 0.5 h_min / max|u|
     and the diffusive one of the ACDI term (diffusivity Gamma eps) and the
@@ -542,6 +575,11 @@ def main():
     # ---- batched form
     if not args.no_batch:
         res["batched"] = run_batch(args.steps, args.warmup, args.ndom)
+
+    # ---- the plan's Poisson solve alone at 512^3, with the benchmark's
+    # boundaries and with Dirichlet (sine-transform) x and y
+    res["poisson_solve"] = run_poisson(gs, args.steps, args.warmup)
+    torch.cuda.empty_cache()
 
     # ---- whole Runge-Kutta steps around the projection (same workload)
     if not args.no_flow:

@@ -53,8 +53,13 @@ typedef enum {
 } pcx_status;
 
 /* Boundary condition of a direction.  WALL: zero normal velocity and zero
- * normal pressure gradient (cosine transform in x/y, Neumann rows in z). */
-typedef enum { PCX_BC_PERIODIC = 0, PCX_BC_WALL = 1 } pcx_bc;
+ * normal pressure gradient (cosine transform in x/y, Neumann rows in z).
+ * DIRICHLET: p = 0 on the boundary faces (ghost value -p; sine transform in
+ * x/y, Dirichlet rows in z); accepted by pcx_plan_create for
+ * pcx_poisson_solve only -- pcx_step, the batch and the substep reject it
+ * (UNSUPPORTED), since what the velocity correction does on an open
+ * boundary is not part of the method. */
+typedef enum { PCX_BC_PERIODIC = 0, PCX_BC_WALL = 1, PCX_BC_DIRICHLET = 2 } pcx_bc;
 
 /* FP64: every pass in double precision.
  * FP32_REFINED: transforms and tridiagonal solves in single precision inside
@@ -138,6 +143,15 @@ pcx_status pcx_step(pcx_plan plan, double dt, double rho0,
                     void *stream, pcx_report *report);
 
 pcx_status pcx_plan_destroy(pcx_plan plan);
+
+/* The plan's constant-coefficient Poisson solve alone (the direct solver of
+ * the method: transforms in x and y, tridiagonal solves in z): L p = f for
+ * the 7-point operator with variable z spacing and the plan's boundary
+ * conditions.  With a Dirichlet direction L is non-singular and p is the
+ * solution; without one, the compatible part f - <f> is solved and <p> = 0.
+ * f and p: device FP64 [nz][ny][nx], p must not alias f.  FP64 plans only
+ * (else UNSUPPORTED).  Enqueues on stream. */
+pcx_status pcx_poisson_solve(pcx_plan plan, const double *f, double *p, void *stream);
 
 /* Per-pass device timing of a plan: when enabled, pcx_step records HIP
  * events on its stream between passes; pcx_plan_pass_times synchronizes on

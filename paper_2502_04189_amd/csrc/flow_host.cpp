@@ -53,6 +53,8 @@ extern "C" pcx_status pcx_flow_create(const pcx_grid *grid, const pcx_flow_param
     if (!prm) return fail(PCX_ERR_INVALID, "params is NULL");
     pcx_status st = validate_grid(grid);
     if (st != PCX_OK) return st;
+    if (grid->bc_x == PCX_BC_DIRICHLET || grid->bc_y == PCX_BC_DIRICHLET || grid->bc_z == PCX_BC_DIRICHLET)
+        return fail(PCX_ERR_UNSUPPORTED, "the substep takes periodic and wall boundaries only");
     const pcx_flow_params &q = *prm;
     if (!(q.rho1 > 0.0) || !(q.rho2 > 0.0) || !(q.mu1 >= 0.0) || !(q.mu2 >= 0.0) || !(q.sigma >= 0.0) ||
         !(q.gamma >= 0.0) || !(q.eps > 0.0) || !(q.eps_s >= 0.0) || !fin(q.rho1) || !fin(q.rho2) || !fin(q.mu1) ||

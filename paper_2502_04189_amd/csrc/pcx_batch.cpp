@@ -292,6 +292,8 @@ extern "C" pcx_status pcx_batch_create(const pcx_domain *domains, int32_t n, con
         const pcx_domain &dm = domains[i];
         pcx_status st = validate_grid(&dm.grid);
         if (st != PCX_OK) return fail(st, "domain " + std::to_string(i) + ": " + g_err);
+        if (dm.grid.bc_x == PCX_BC_DIRICHLET || dm.grid.bc_y == PCX_BC_DIRICHLET || dm.grid.bc_z == PCX_BC_DIRICHLET)
+            return fail(PCX_ERR_UNSUPPORTED, "domain " + std::to_string(i) + ": Dirichlet boundaries are for pcx_poisson_solve");
         if (!(dm.dt > 0.0) || !(dm.rho0 > 0.0)) return fail(PCX_ERR_INVALID, "domain " + std::to_string(i) + ": dt, rho0 must be > 0");
         const void *f[] = {dm.rho, dm.p_star, dm.u, dm.v, dm.w, dm.u_out, dm.v_out, dm.w_out, dm.p_out};
         for (const void *q : f)

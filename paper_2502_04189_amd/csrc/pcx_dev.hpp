@@ -27,7 +27,9 @@ constexpr int NSTAT = 64;     // reduction slots per domain
 constexpr int MAXIT = 12;     // max refinement solves tracked
 
 enum { PREC_F64 = 0, PREC_F32 = 1 };
-enum { BC_PER = 0, BC_WALL = 1 };
+// boundary conditions: periodic; wall (zero normal velocity, Neumann
+// pressure); homogeneous Dirichlet pressure (the solve alone)
+enum { BC_PER = 0, BC_WALL = 1, BC_DIR = 2 };
 // x-transform source: the stored f or r, or (the fused forms) f or r
 // evaluated by the stencil inside the x pass, never stored (f is still
 // stored in the refined form, whose residual needs it)
@@ -71,6 +73,7 @@ struct MGeo {
 struct Dom {
     int nx, ny, nz, nl, M;            // M = nx/2 (half-length complex FFT)
     int bcx, bcy, bcz;
+    int nosing;                       // a Dirichlet direction: no singular (0, 0) mode
     int tj, ntj;                      // x-pass rows per tile, j tiles
     int tk, ntk;                      // y-pass columns per tile, k tiles
     int zg, zlpw, nzt;                // z lanes per line, lines per WG, z tiles

@@ -115,7 +115,8 @@ pcx_status validate_grid(const pcx_grid *g)
     if (g->nx < 2 || g->ny < 2 || g->nz < 2) return fail(PCX_ERR_INVALID, "nx, ny, nz must be >= 2");
     if (!(g->lx > 0.0) || !(g->ly > 0.0)) return fail(PCX_ERR_INVALID, "lx and ly must be > 0");
     for (int b : {g->bc_x, g->bc_y, g->bc_z})
-        if (b != PCX_BC_PERIODIC && b != PCX_BC_WALL) return fail(PCX_ERR_INVALID, "unknown boundary condition");
+        if (b != PCX_BC_PERIODIC && b != PCX_BC_WALL && b != PCX_BC_DIRICHLET)
+            return fail(PCX_ERR_INVALID, "unknown boundary condition");
     if (g->nx % 2) return fail(PCX_ERR_INVALID, "nx must be even");
     if (g->bc_y == PCX_BC_PERIODIC && (g->ny % 2)) return fail(PCX_ERR_INVALID, "ny must be even in a periodic direction");
     for (int k = 0; k < g->nz; ++k)
@@ -147,7 +148,7 @@ void choose_shapes(const pcx_grid &g, int prec, const TuneParams *tp, Shapes &sh
     const size_t csz = prec == PREC_F64 ? 16 : 8;
     const long lds_cap = 80 * 1024;
     const int seg = prec == PREC_F64 ? 8 : 16;
-    const int nlx = g.bc_x == PCX_BC_WALL ? g.nx : M + 1;
+    const int nlx = g.bc_x != PCX_BC_PERIODIC ? g.nx : M + 1;
     int tj = pow2_floor(std::max(1, MAXPTS / std::max(M, 1)));
     tj = std::min(tj, pow2_floor(lds_cap / (long)(lds_line(nlx) * csz)));
     tj = std::min(tj, seg);
@@ -190,10 +191,11 @@ void make_domain(const pcx_grid &g, int prec, const Shapes &sh, const RadixChoic
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const int M = nx / 2;
     // x modes: half spectrum of a real FFT (periodic) or nx cosine modes (wall)
-    const int nl = g.bc_x == PCX_BC_WALL ? nx : M + 1;
+    const int nl = g.bc_x != PCX_BC_PERIODIC ? nx : M + 1;
     std::memset(&d, 0, sizeof(d));
     d.nx = nx; d.ny = ny; d.nz = nz; d.nl = nl; d.M = M;
     d.bcx = g.bc_x; d.bcy = g.bc_y; d.bcz = g.bc_z;
+    d.nosing = g.bc_x == PCX_BC_DIRICHLET || g.bc_y == PCX_BC_DIRICHLET || g.bc_z == PCX_BC_DIRICHLET;
     d.tj = sh.tj; d.ntj = (ny + sh.tj - 1) / sh.tj;
     d.tk = sh.tk; d.ntk = (nz + sh.tk - 1) / sh.tk;
     d.zg = sh.zg; d.zlpw = (NT / 64) * (64 / sh.zg);
@@ -256,22 +258,24 @@ void make_domain(const pcx_grid &g, int prec, const Shapes &sh, const RadixChoic
         za[k] = lo ? 1.0L / (dzf[k] * dzc[km]) : 0.0L;
         zcc[k] = hi ? 1.0L / (dzf[k] * dzc[k]) : 0.0L;
         zb[k] = -(za[k] + zcc[k]);
+        // Dirichlet z: ghost -p one cell width beyond the boundary face
+        if (g.bc_z == PCX_BC_DIRICHLET && !lo) zb[k] -= 2.0L / (dzf[k] * dzf[k]);
+        if (g.bc_z == PCX_BC_DIRICHLET && !hi) zb[k] -= 2.0L / (dzf[k] * dzf[k]);
     }
     const long double pi = 3.141592653589793238462643383279502884L;
     std::vector<long double> lamx(nl), lamy(ny);
     // eigenvalues of the second difference: periodic -(4/h^2) sin^2(pi l/n)
-    // (folded to min(l, n-l)), cell-centred Neumann -(4/h^2) sin^2(pi l/(2n))
-    for (int l = 0; l < nl; ++l) {
-        long double s = g.bc_x == PCX_BC_WALL ? sinl(pi * (long double)l / (2.0L * nx))
-                                              : sinl(pi * (long double)l / (long double)nx);
-        lamx[l] = -4.0L / ((long double)d.dx * d.dx) * s * s;
-    }
-    for (int m = 0; m < ny; ++m) {
-        long double s;
-        if (g.bc_y == PCX_BC_WALL) s = sinl(pi * (long double)m / (2.0L * ny));
-        else s = sinl(pi * (long double)std::min(m, ny - m) / (long double)ny);
-        lamy[m] = -4.0L / ((long double)d.dy * d.dy) * s * s;
-    }
+    // (folded to min(l, n-l)), cell-centred Neumann -(4/h^2) sin^2(pi l/(2n)),
+    // Dirichlet (sign-alternated cosine mode l = sine mode n-1-l)
+    // -(4/h^2) cos^2(pi l/(2n))
+    auto eig = [&](int bc, int n, int l) {
+        if (bc == PCX_BC_WALL) { long double s = sinl(pi * (long double)l / (2.0L * n)); return s * s; }
+        if (bc == PCX_BC_DIRICHLET) { long double c = cosl(pi * (long double)l / (2.0L * n)); return c * c; }
+        long double s = sinl(pi * (long double)std::min(l, n - l) / (long double)n);
+        return s * s;
+    };
+    for (int l = 0; l < nl; ++l) lamx[l] = -4.0L / ((long double)d.dx * d.dx) * eig(g.bc_x, nx, l);
+    for (int m = 0; m < ny; ++m) lamy[m] = -4.0L / ((long double)d.dy * d.dy) * eig(g.bc_y, ny, m);
 
     Blob b;
     auto addd = [&](const std::vector<long double> &v) { auto c = cast_vec<double>(v); return b.add(c.data(), c.size() * 8); };
@@ -292,8 +296,8 @@ void make_domain(const pcx_grid &g, int prec, const Shapes &sh, const RadixChoic
     size_t o_twx = addr(M, false);
     size_t o_twy = addr(ny, false);
     // cosine-transform twiddles exp(-i pi k / (2N)) = W_{4N}^k
-    size_t o_dcx = g.bc_x == PCX_BC_WALL ? addr(4 * nx, false) : 0;
-    size_t o_dcy = g.bc_y == PCX_BC_WALL ? addr(4 * ny, false) : 0;
+    size_t o_dcx = g.bc_x != PCX_BC_PERIODIC ? addr(4 * nx, false) : 0;
+    size_t o_dcy = g.bc_y != PCX_BC_PERIODIC ? addr(4 * ny, false) : 0;
 
     ht.o_dzf = o_dzf; ht.o_idzf = o_idzf; ht.o_idzc = o_idzc; ht.o_rzlo = o_rzlo; ht.o_rzhi = o_rzhi;
     ht.o_za = o_za; ht.o_zb = o_zb; ht.o_zc = o_zc; ht.o_dzfs = o_dzfs; ht.o_lx = o_lx; ht.o_ly = o_ly;
@@ -313,8 +317,8 @@ void bind_tables(Dom &d, const HostTables &ht, char *base)
     d.za = base + ht.o_za; d.zb = base + ht.o_zb; d.zc = base + ht.o_zc; d.dzf_s = base + ht.o_dzfs;
     d.lamx = base + ht.o_lx; d.lamy = base + ht.o_ly;
     d.twr = base + ht.o_twr;
-    d.dctx = d.bcx == BC_WALL ? base + ht.o_dcx : nullptr;
-    d.dcty = d.bcy == BC_WALL ? base + ht.o_dcy : nullptr;
+    d.dctx = d.bcx != BC_PER ? base + ht.o_dcx : nullptr;
+    d.dcty = d.bcy != BC_PER ? base + ht.o_dcy : nullptr;
     d.fx.tw = base + ht.o_twx;
     d.fy.tw = base + ht.o_twy;
 }
@@ -630,6 +634,9 @@ extern "C" pcx_status pcx_step(pcx_plan P, double dt, double rho0, const double 
                                double *v_out, double *w_out, double *p_out, void *stream, pcx_report *report)
 {
     if (!P) return fail(PCX_ERR_INVALID, "plan is NULL");
+    if (P->dom.nosing)
+        return fail(PCX_ERR_UNSUPPORTED, "the pressure-correction step has no rule for a Dirichlet boundary "
+                                         "(use pcx_poisson_solve)");
     if (!rho || !p_star || !u_in || !v_in || !w_in || !u_out || !v_out || !w_out || !p_out)
         return fail(PCX_ERR_INVALID, "NULL field pointer");
     if (!(dt > 0.0) || !(rho0 > 0.0) || !std::isfinite(dt) || !std::isfinite(rho0))
@@ -752,6 +759,24 @@ extern "C" pcx_status pcx_step(pcx_plan P, double dt, double rho0, const double 
     }
     if (P->prec == PREC_F32 && !r.converged) return fail(PCX_ERR_NOT_CONVERGED, "refinement did not reach rtol within max_iters");
     return PCX_OK;
+}
+
+// L p = f with the plan's boundary conditions (periodic, Neumann wall or
+// homogeneous Dirichlet per direction): the transforms and tridiagonal
+// solves of the step on a given right-hand side.  Without a Dirichlet
+// direction, the compatible part f - <f> is solved and <p> = 0.
+extern "C" pcx_status pcx_poisson_solve(pcx_plan P, const double *f, double *p, void *stream)
+{
+    if (!P || !f || !p) return fail(PCX_ERR_INVALID, "NULL argument");
+    if (f == p) return fail(PCX_ERR_INVALID, "p must not alias f");
+    if (P->prec != PREC_F64) return fail(PCX_ERR_UNSUPPORTED, "pcx_poisson_solve runs FP64 plans only");
+    hipStream_t s = (hipStream_t)stream;
+    Dom d = P->dom;
+    d.f = const_cast<double *>(f); // read only: the forward x pass reads its source
+    d.po = p;
+    HIPCHK(launch_zero(P->stats, NSTAT, s));
+    HIPCHK(launch_xfwd(d, P->prec, SRC_RHS, P->lx, s));
+    return solve_tail(P, d, 0, XOUT_STORE, s);
 }
 
 // ------------------------------------------------------------------ misc

@@ -647,7 +647,10 @@ __device__ __forceinline__ void pass_xfwd(const Dom &d, int tile, char *smem)
     TabStage<T, NTH> trs;
     tws.fetch(d.fx);
     trs.fetch((const C *)d.twr, M / 2 + 1);
-    const bool wx = d.bcx == BC_WALL;
+    const bool wx = d.bcx != BC_PER;
+    // Dirichlet x: the sine transform is the cosine one of (-1)^i s_i (its
+    // modes come out in reverse order, which only the eigenvalues see)
+    const T odd = d.bcx == BC_DIR ? T(-1) : T(1);
     const int hx = nx >> 1;
     const double2 *src2 = (const double2 *)src;
     const C *twr = ltr;
@@ -660,7 +663,7 @@ __device__ __forceinline__ void pass_xfwd(const Dom &d, int tile, char *smem)
         } else {
             int n1 = nx - 1 - h;
             ((T *)(row + pidx(h >> 1)))[h & 1] = (T)s.x;
-            ((T *)(row + pidx(n1 >> 1)))[n1 & 1] = (T)s.y;
+            ((T *)(row + pidx(n1 >> 1)))[n1 & 1] = odd * (T)s.y;
         }
     };
     // split of the half-length spectrum, l in [0, M/2]
@@ -774,9 +777,12 @@ __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
     const FastDiv dtk = d.dtk;
     const int ldc = lds_line(ny);
     C *ltw = buf + tk * ldc;
-    const bool wy = d.bcy == BC_WALL;
-    // wall y: cosine transform by reordering v[n] = c[2n], v[N-1-n] = c[2n+1]
+    const bool wy = d.bcy != BC_PER;
+    // wall y: cosine transform by reordering v[n] = c[2n], v[N-1-n] = c[2n+1];
+    // Dirichlet y: the same on (-1)^j c_j (forward) and for the result (inverse)
     auto pos = [&](int j) { return wy ? ((j & 1) ? ny - 1 - (j >> 1) : (j >> 1)) : j; };
+    const bool dy = d.bcy == BC_DIR;
+    auto sgn = [&](int j, C v) { return (dy && (j & 1)) ? C{-v.x, -v.y} : v; };
     C *s1 = (C *)d.s1;
     C *s2 = (C *)d.s2;
     const C *wd = (const C *)d.dcty;
@@ -796,7 +802,7 @@ __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
             const C *src = s1 + ((size_t)(k0 + wid) * nl + l) * ny;
             C *col = buf + wid * ldc;
             staged_copy_t<64, 8, C>(
-                lane, ny, [&](int j) { return ld_stream(src + j); }, [&](int j, C v) { col[pidx(pos(j))] = v; });
+                lane, ny, [&](int j) { return ld_stream(src + j); }, [&](int j, C v) { col[pidx(pos(j))] = sgn(j, v); });
         }
     } else if (!INV) {
         staged_copy<NTH, 8, C>(
@@ -807,7 +813,7 @@ __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
             },
             [&](int e, C v) {
                 const int c = (int)fdiv((uint32_t)e, d.dnyc), j = e - c * ny;
-                buf[c * ldc + pidx(pos(j))] = v;
+                buf[c * ldc + pidx(pos(j))] = sgn(j, v);
             });
     } else {
         staged_copy<NTH, 8, C>(
@@ -877,7 +883,7 @@ __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
                 C *dst = s1 + ((size_t)(k0 + wid) * nl + l) * ny;
                 // eight LDS reads in flight per lane, then the stores
                 staged_copy_t<64, 8, C>(
-                    lane, ny, [&](int j) { return col[pidx(pos(j))]; }, [&](int j, C v) { st_stream(dst + j, v); });
+                    lane, ny, [&](int j) { return sgn(j, col[pidx(pos(j))]); }, [&](int j, C v) { st_stream(dst + j, v); });
             }
         }
         if (INV) return;
@@ -917,7 +923,7 @@ __device__ __forceinline__ void pass_y(const Dom &d, int tile, char *smem)
             cols * ny,
             [&](int e) {
                 const int c = (int)fdiv((uint32_t)e, d.dnyc), j = e - c * ny;
-                return buf[c * ldc + pidx(pos(j))];
+                return sgn(j, buf[c * ldc + pidx(pos(j))]);
             },
             [&](int e, C v) {
                 const int c = (int)fdiv((uint32_t)e, d.dnyc), j = e - c * ny;
@@ -971,7 +977,7 @@ __device__ __forceinline__ void pass_z(const Dom &d, int tile, char *smem)
     const int gls = active ? gl : wl0;
     const long q = q0 + gls;
     const int l = (int)(q / d.ny), m = (int)(q - (long)l * d.ny);
-    const bool sing_line = (l == 0 && m == 0);
+    const bool sing_line = !d.nosing && l == 0 && m == 0;
     const T *za = (const T *)d.za, *zb = (const T *)d.zb, *zc = (const T *)d.zc, *dzf = (const T *)d.dzf_s;
     const T sh = ((const T *)d.lamx)[l] + ((const T *)d.lamy)[m];
     const T scale = (T)d.scale;
@@ -1198,7 +1204,8 @@ __device__ __forceinline__ void pass_xinv(const Dom &d, int tile, char *smem, in
     tws.put(ltw, d.fx);
     trs.put(ltr, (const C *)d.twr, M / 2 + 1);
     __syncthreads();
-    const bool wx = d.bcx == BC_WALL;
+    const bool wx = d.bcx != BC_PER;
+    const double odd = d.bcx == BC_DIR ? -1.0 : 1.0; // Dirichlet x: (-1)^i on the result
     const C *wd = (const C *)d.dctx;
     const C *twr = ltr;
     // inverse DCT-II: half spectrum of the reordered row,
@@ -1242,7 +1249,7 @@ __device__ __forceinline__ void pass_xinv(const Dom &d, int tile, char *smem, in
         }
         int n1 = nx - 1 - h;
         return double2{(double)((const T *)(row + pidx(h >> 1)))[h & 1],
-                       (double)((const T *)(row + pidx(n1 >> 1)))[n1 & 1]};
+                       odd * (double)((const T *)(row + pidx(n1 >> 1)))[n1 & 1]};
     };
     auto emit = [&](int e, double2 val, double2 old) {
         double2 pv = (MODE == XOUT_STORE) ? val : double2{(old.x - shift) + val.x, (old.y - shift) + val.y};

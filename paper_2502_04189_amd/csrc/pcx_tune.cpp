@@ -119,7 +119,7 @@ pcx_status autotune_class(const pcx_grid &g, int prec, hipStream_t s, TuneParams
     const size_t ncell = (size_t)g.nx * g.ny * g.nz;
     const int M = g.nx / 2;
     const size_t csz = prec == PREC_F64 ? 16 : 8;
-    const int nlx = g.bc_x == PCX_BC_WALL ? g.nx : M + 1;
+    const int nlx = g.bc_x != PCX_BC_PERIODIC ? g.nx : M + 1;
     const size_t nspec = (size_t)nlx * g.ny * g.nz;
     Scratch sc;
     std::vector<double> ones(ncell, 1.0);

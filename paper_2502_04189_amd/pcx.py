@@ -15,6 +15,7 @@ HEADERS = [HEADER, os.path.join(os.path.dirname(HERE), "include", "pcx_flow.h")]
 PCX_OK, PCX_ERR_INVALID, PCX_ERR_UNSUPPORTED, PCX_ERR_NOMEM, PCX_ERR_HIP = 0, 1, 2, 3, 4
 PCX_ERR_NOT_CONVERGED, PCX_ERR_NONFINITE = 5, 6
 PCX_FP64, PCX_FP32_REFINED = 0, 1
+PCX_BC_PERIODIC, PCX_BC_WALL, PCX_BC_DIRICHLET = 0, 1, 2
 
 _DP = C.POINTER(C.c_double)
 
@@ -85,6 +86,7 @@ def lib():
         "pcx_batch_reports": (st, [vp, C.POINTER(PcxReport)]),
         "pcx_batch_destroy": (st, [vp]),
         "pcx_rho_min": (st, [vp, C.c_int64, vp, _DP]),
+        "pcx_poisson_solve": (st, [vp, vp, vp, vp]),
         "pcx_step_noalloc": (st, [C.POINTER(PcxGrid), C.POINTER(PcxOptions), dbl, dbl] + [vp] * 9 +
                              [vp, C.POINTER(PcxReport)]),
         "pcx_noalloc_scratch_need": (st, [C.POINTER(PcxGrid), C.POINTER(PcxOptions), C.POINTER(C.c_size_t)]),
@@ -195,6 +197,14 @@ class Plan:
         if raise_on_status and st != PCX_OK:
             raise PcxError(st, "pcx_step")
         return outs[0], outs[1], outs[2], outs[3], (rep.as_dict() if report else None)
+
+    def poisson_solve(self, f, p=None, stream=None):
+        """pcx_poisson_solve: L p = f with the plan's boundary conditions."""
+        import torch
+        p = p if p is not None else torch.empty(self.shape, dtype=torch.float64, device=f.device)
+        _check(lib().pcx_poisson_solve(self._h, _ptr(f, self.shape, "f"), _ptr(p, self.shape, "p"),
+                                       _stream_handle(stream)), "pcx_poisson_solve")
+        return p
 
     def set_timing(self, on=True):
         _check(lib().pcx_plan_set_timing(self._h, 1 if on else 0), "pcx_plan_set_timing")
