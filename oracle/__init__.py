@@ -43,7 +43,7 @@ class OrDiag(C.Structure):
     ]
 
 
-SOURCES = ("oracle.c", "flow.c", "dirichlet.c")
+SOURCES = ("oracle.c", "flow.c", "dirichlet.c", "varcoef.c")
 
 
 def build(force: bool = True) -> str:
@@ -89,6 +89,12 @@ def lib():
         L.oracle_cyclic.argtypes = [C.c_int, _DP, _DP, _DP, _DP]
         L.oracle_eig.argtypes = [C.c_int, C.c_double, C.c_int, C.c_int]
         L.oracle_eig.restype = C.c_double
+        if hasattr(L, "oracle_varcoef_solve"):  # varcoef.c
+            I = C.POINTER(C.c_int)
+            L.oracle_varcoef_apply.argtypes = [G, _DP, _DP, _DP]
+            L.oracle_varcoef_solve.argtypes = [G, _DP, C.c_double, _DP, _DP, C.c_double, C.c_int, I, _DP]
+            L.oracle_varcoef_project.argtypes = ([G, C.c_double, _DP, C.c_double] + [_DP] * 7 +
+                                                 [C.c_double, C.c_int, I, _DP])
         if hasattr(L, "oracle_poisson_bc"):  # dirichlet.c
             L.oracle_poisson_bc.argtypes = [G, _DP, _DP]
             L.oracle_apply_L_bc.argtypes = [G, _DP, _DP]
@@ -378,3 +384,24 @@ def poisson_bc(g, f):
 
 def eig_bc(n, h, bc, l):
     return lib().oracle_eig_bc(int(n), float(h), int(bc), int(l))
+
+
+# -------------------------------------------------------------- varcoef.c
+# The variable-coefficient projection the splitting replaces ("Methods and
+# Implementation strategy"), for the splitting-error comparator.
+
+def varcoef_apply(g, rho, p):
+    out = np.empty(g.shape)
+    _chk(lib().oracle_varcoef_apply(g.cref, _p(_arr(rho)), _p(_arr(p)), _p(out)), "varcoef_apply")
+    return out
+
+
+def varcoef_project(g, dt, rho, rho0, u, v, w, tol=1e-12, maxit=2000):
+    """(u_out, v_out, w_out, p, iterations, relative residual)."""
+    ins = [_arr(a) for a in (rho, u, v, w)]
+    outs = [np.empty(g.shape) for _ in range(4)]
+    it, rr = C.c_int(), C.c_double()
+    rc = lib().oracle_varcoef_project(g.cref, float(dt), _p(ins[0]), float(rho0), *[_p(a) for a in ins[1:]],
+                                      *[_p(o) for o in outs], float(tol), int(maxit), C.byref(it), C.byref(rr))
+    _chk(rc, "varcoef_project")
+    return (*outs, it.value, rr.value)
