@@ -394,6 +394,42 @@ def run_poisson(gs, steps, warmup):
     return out
 
 
+def run_varcoef(case, dev, split_ms, tol=1e-10, maxit=4000):
+    """The variable-coefficient projection D((1/rho_f) G p) = D u*/dt that the
+    splitting replaces, by conjugate gradients preconditioned with the FP64
+    constant-coefficient solve, on the benchmark's own inputs: its time and
+    iterations against the split step's, and the split step's velocity
+    error relative to it with the workload's p* and with p* = its pressure
+    (where the splitting is exact).  One timed run (it takes seconds)."""
+    import torch
+    from paper_2502_04189_amd import pcx
+    gs = case.grid
+    rho, ps, u, v, w = dev
+    vc = pcx.VarCoef(gs)
+    outs = [torch.empty(gs.shape, dtype=torch.float64, device="cuda") for _ in range(4)]
+    vc.project(case.dt, case.rho0, rho, u, v, w, tol=tol, maxit=2, outs=outs)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    uo, vo, wo, p, it, rr, st = vc.project(case.dt, case.rho0, rho, u, v, w, tol=tol, maxit=maxit, outs=outs)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    vc.close()
+    plan = pcx.Plan(gs, "fp64")
+    so = [torch.empty_like(uo) for _ in range(4)]
+    err = {}
+    for name, pst in (("workload_pstar", ps), ("exact_pstar", p)):
+        plan.step(case.dt, case.rho0, rho, pst, u, v, w, *so, report=False)
+        torch.cuda.synchronize()
+        err[name] = max(float((a - b).abs().max() / b.abs().max()) for a, b in zip(so[:3], (uo, vo, wo)))
+    plan.close()
+    del so, outs
+    log(f"varcoef projection: {it} iterations, residual {rr:.2e}, {ms:.1f} ms; split errors {err}")
+    return {"tol": tol, "iterations": it, "rel_residual": rr, "converged": st == pcx.PCX_OK,
+            "ms": round(ms, 2), "ms_per_iteration": round(ms / max(it, 1), 3),
+            "split_step_ms": round(split_ms, 4), "cost_vs_split_step": round(ms / split_ms, 1),
+            "split_velocity_rel_error": err}
+
+
 def flow_dt(gs, prm, umax):
     """Step of the explicit substeps: the advective limit 0.5 h_min / max|u|
     and the diffusive one of the ACDI term (diffusivity Gamma eps) and the
@@ -473,6 +509,7 @@ def main():
                          "that calibrates the HBM byte counters; prints no JSON")
     ap.add_argument("--prof-refined", action="store_true")
     ap.add_argument("--no-flow", action="store_true")
+    ap.add_argument("--no-varcoef", action="store_true")
     ap.add_argument("--prof-flow", action="store_true",
                     help="profiling mode: a few Runge-Kutta steps of the substep around the projection; no JSON")
     ap.add_argument("--prof-batch", action="store_true",
@@ -550,6 +587,11 @@ def main():
         "roofline": roof,
     }
     del plan
+
+    # ---- the variable-coefficient projection the splitting replaces
+    if not args.no_varcoef:
+        res["varcoef_projection"] = run_varcoef(case, dev, ms)
+        torch.cuda.empty_cache()
 
     # ---- FP32 + FP64 refinement on the same inputs
     if not args.no_refined:

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libpcx.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["pcx_kernels.hip", "pcx_host.cpp", "pcx_batch.cpp", "pcx_tune.cpp", "pcx_noalloc.cpp",
-           "flow_kernels.hip", "flow_host.cpp"]
+           "flow_kernels.hip", "flow_host.cpp", "varcoef_kernels.hip", "varcoef_host.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # no packed FP32 instructions anywhere in the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

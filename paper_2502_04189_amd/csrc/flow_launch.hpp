@@ -4,7 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
-#include "flow_dev.hpp"
+#include "flow_tile.hpp"
 
 namespace pcx {
 namespace flow {
@@ -30,8 +30,6 @@ hipError_t launch_flux(const FArgs &A, hipStream_t s);
 hipError_t launch_phase(const FArgs &A, hipStream_t s);
 hipError_t launch_momentum(const FArgs &A, hipStream_t s);
 double key_to_double(unsigned long long k);
-// workgroups of a one-thread-per-cell launch over the grid
-int ngrid(const FGrid &G);
 
 } // namespace flow
 } // namespace pcx

@@ -10,7 +10,7 @@ import re
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpcx.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "pcx.h")
-HEADERS = [HEADER, os.path.join(os.path.dirname(HERE), "include", "pcx_flow.h")]
+HEADERS = [HEADER] + [os.path.join(os.path.dirname(HERE), "include", h) for h in ("pcx_flow.h", "pcx_varcoef.h")]
 
 PCX_OK, PCX_ERR_INVALID, PCX_ERR_UNSUPPORTED, PCX_ERR_NOMEM, PCX_ERR_HIP = 0, 1, 2, 3, 4
 PCX_ERR_NOT_CONVERGED, PCX_ERR_NONFINITE = 5, 6
@@ -59,7 +59,7 @@ _lib = None
 
 
 def header_symbols():
-    """Function names declared in include/pcx.h and include/pcx_flow.h."""
+    """Function names declared in the library's headers (include/*.h)."""
     txt = "".join(open(h).read() for h in HEADERS)
     return sorted(set(re.findall(r"\b(pcx_[a-z0-9_]+)\s*\(", txt)))
 
@@ -95,6 +95,11 @@ def lib():
         "pcx_flow_phase_rhs": (st, [vp] + [vp] * 5 + [vp]),
         "pcx_flow_momentum_rhs": (st, [vp] + [vp] * 7 + [vp]),
         "pcx_flow_substep": (st, [vp, i32, dbl] + [vp] * 6 + [dbl] + [vp] * 9 + [vp, C.POINTER(PcxReport)]),
+        "pcx_varcoef_create": (st, [C.POINTER(PcxGrid), C.POINTER(PcxOptions), C.POINTER(vp)]),
+        "pcx_varcoef_destroy": (st, [vp]),
+        "pcx_varcoef_apply": (st, [vp, vp, vp, vp, vp]),
+        "pcx_varcoef_project": (st, [vp, dbl, dbl] + [vp] * 4 + [dbl, i32] + [vp] * 4 +
+                                [vp, C.POINTER(i32), _DP]),
         "pcx_refine_should_stop": (i32, [dbl, dbl, dbl, dbl, dbl]),
         "pcx_status_str": (C.c_char_p, [st]),
         "pcx_last_error": (C.c_char_p, []),
@@ -351,3 +356,51 @@ class Flow:
                                     C.byref(rep) if report else None)
         _check(st, "pcx_flow_substep")
         return rep.as_dict() if report else None
+
+
+class VarCoef:
+    """pcx_varcoef: the variable-coefficient projection D((1/rho_f) G p) =
+    D u* / dt by preconditioned conjugate gradients, the comparator for the
+    splitting.  Fields are torch float64 CUDA tensors of shape (nz, ny, nx)."""
+
+    def __init__(self, grid, autotune=False):
+        L = lib()
+        self.gs = grid
+        self._g = make_grid(grid)
+        self._o = make_options("fp64", autotune=autotune)
+        h = C.c_void_p()
+        _check(L.pcx_varcoef_create(C.byref(self._g), C.byref(self._o), C.byref(h)), "pcx_varcoef_create")
+        self._L = L
+        self._h = h
+        self.shape = (grid.nz, grid.ny, grid.nx)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.pcx_varcoef_destroy(self._h)  # the library handle outlives module teardown
+            self._h = None
+
+    __del__ = close
+
+    def apply(self, rho, p, out=None, stream=None):
+        import torch
+        out = out if out is not None else torch.empty(self.shape, dtype=torch.float64, device=p.device)
+        _check(lib().pcx_varcoef_apply(self._h, _ptr(rho, self.shape, "rho"), _ptr(p, self.shape, "p"),
+                                       _ptr(out, self.shape, "out"), _stream_handle(stream)), "pcx_varcoef_apply")
+        return out
+
+    def project(self, dt, rho0, rho, u, v, w, tol=1e-12, maxit=1000, outs=None, stream=None, check=True):
+        """Returns (u_out, v_out, w_out, p_out, iterations, relative residual,
+        status); raises on an error status other than NOT_CONVERGED unless
+        check is False."""
+        import torch
+        if outs is None:
+            outs = [torch.empty(self.shape, dtype=torch.float64, device=u.device) for _ in range(4)]
+        ins = [_ptr(t, self.shape, n) for t, n in zip((rho, u, v, w), ("rho", "u", "v", "w"))]
+        po = [_ptr(t, self.shape, n) for t, n in zip(outs, ("u_out", "v_out", "w_out", "p_out"))]
+        it = C.c_int32()
+        rr = C.c_double()
+        st = lib().pcx_varcoef_project(self._h, float(dt), float(rho0), *ins, float(tol), int(maxit), *po,
+                                       _stream_handle(stream), C.byref(it), C.byref(rr))
+        if check and st not in (PCX_OK, PCX_ERR_NOT_CONVERGED):
+            _check(st, "pcx_varcoef_project")
+        return (*outs, it.value, rr.value, st)

@@ -147,3 +147,23 @@ def test_flow_create_validation(L):
     if st == P.PCX_OK:
         L.pcx_flow_destroy(h)
     assert L.pcx_flow_phase_rhs(None, *[None] * 5, None) == P.PCX_ERR_INVALID
+
+
+def test_varcoef_create_validation(L):
+    """pcx_varcoef_create rejects a Dirichlet grid and a non-FP64 precision on
+    the host and reports a missing device; the entry points reject NULL."""
+    h = C.c_void_p()
+    dg = P.make_grid(W.GridSpec(16, 16, 8, 1.0, 1.0, W.zf_uniform(8, 0.5), 2, 0, 1))
+    assert L.pcx_varcoef_create(C.byref(dg), None, C.byref(h)) == P.PCX_ERR_UNSUPPORTED
+    g = P.make_grid(W.GridSpec(16, 16, 8, 1.0, 1.0, W.zf_uniform(8, 0.5)))
+    o = P.make_options("fp32_refined")
+    assert L.pcx_varcoef_create(C.byref(g), C.byref(o), C.byref(h)) == P.PCX_ERR_UNSUPPORTED
+    assert L.pcx_varcoef_create(C.byref(g), None, None) == P.PCX_ERR_INVALID
+    st = L.pcx_varcoef_create(C.byref(g), None, C.byref(h))
+    assert st in (P.PCX_OK, P.PCX_ERR_HIP)
+    if st == P.PCX_OK:
+        L.pcx_varcoef_destroy(h)
+    assert L.pcx_varcoef_apply(None, None, None, None, None) == P.PCX_ERR_INVALID
+    it, rr = C.c_int32(), C.c_double()
+    assert L.pcx_varcoef_project(None, 1.0, 1.0, *[None] * 4, 1e-12, 10, *[None] * 4, None, C.byref(it),
+                                 C.byref(rr)) == P.PCX_ERR_INVALID

@@ -1,0 +1,180 @@
+"""GPU parity of the variable-coefficient projection (pcx_varcoef_*, the
+comparator for the splitting) with its oracle (oracle/varcoef.c): the
+operator D((1/rho_f) G p) element by element, the preconditioned conjugate
+gradient solve and the corrected velocity, and properties at a size the
+oracle's solve would take minutes on: divergence of the result, the
+constant-density limit (one iteration, equals pcx_step), and the split
+step given this pressure as p* reproducing it.
+
+Tolerances: the operator is a few roundings per cell, 1e-13 of max |out|.
+The two solves run the same iteration in a different rounding order; both
+stop at a relative residual <= tol in the volume-weighted norm, so each is
+within kappa tol of the exact solution with kappa <= rho_max / rho0 (the
+preconditioned operator's condition number, bounded by the density
+ratio): p agrees within 2 (rho_max / rho0) tol of max |p|, and a velocity
+component, whose correction is dt (1/rho_f) G p, within 2 dt / (rho0 h_min)
+times that bound on p (G amplifies a difference by at most 2 / h_min)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2502_04189_amd import workloads as W
+from tests.gpu_util import to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pcx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2502_04189_amd import pcx as P
+    P.lib()
+    return P
+
+
+# ragged x (96) and y (9) tiles, wall x with interior and wall tiles (192),
+# every boundary mix, stretched z
+CASES = [
+    ((96, 9, 12), (0, 1, 1), 1.3),
+    ((64, 8, 8), (1, 1, 0), 0.0),
+    ((192, 12, 7), (1, 1, 1), 1.2),
+    ((48, 18, 10), (1, 0, 1), 1.1),
+    ((32, 32, 32), (0, 0, 0), 0.0),
+]
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("dims,bc,stretch", CASES)
+def test_operator_vs_oracle(pcx, orc, dims, bc, stretch):
+    c = W.random_case(21, *dims, *bc, stretch=stretch)
+    g = orc.Grid.from_workload(c.grid)
+    p = np.random.default_rng(3).normal(size=c.grid.shape)
+    ref = orc.varcoef_apply(g, c.rho, p)
+    vc = pcx.VarCoef(c.grid)
+    got = vc.apply(to_dev(c.rho), to_dev(p)).cpu().numpy()
+    vc.close()
+    e = _rel(got, ref)
+    _say(f"varcoef apply {dims} bc {bc}: {e:.2e}")
+    assert e <= 1e-13
+
+
+@pytest.mark.parametrize("dims,bc,stretch", CASES)
+def test_projection_vs_oracle(pcx, orc, dims, bc, stretch):
+    c = W.random_case(23, *dims, *bc, stretch=stretch)
+    g = orc.Grid.from_workload(c.grid)
+    tol = 1e-13
+    ref = orc.varcoef_project(g, c.dt, c.rho, c.rho0, c.u, c.v, c.w, tol=tol, maxit=2000)
+    vc = pcx.VarCoef(c.grid)
+    uo, vo, wo, p, it, rr, st = vc.project(c.dt, c.rho0, to_dev(c.rho), to_dev(c.u), to_dev(c.v), to_dev(c.w),
+                                           tol=tol, maxit=2000)
+    got = [t.cpu().numpy() for t in (uo, vo, wo, p)]
+    vc.close()
+    bound = 2.0 * (c.rho.max() / c.rho0) * tol
+    hmin = min(c.grid.dx, c.grid.dy, float(np.diff(c.grid.zf).min()))
+    dp = bound * np.abs(ref[3]).max()
+    bounds = [2.0 * c.dt / (c.rho0 * hmin) * dp / np.abs(r).max() for r in ref[:3]] + [bound]
+    errs = [_rel(a, b) for a, b in zip(got, ref[:4])]
+    _say(f"varcoef project {dims} bc {bc}: iters {it} (oracle {ref[4]}), res {rr:.2e}, "
+         f"errors u v w p {' '.join(f'{e:.2e}' for e in errs)}, bounds {' '.join(f'{b:.1e}' for b in bounds)}")
+    assert st == pcx.PCX_OK and rr <= tol
+    assert abs(it - ref[4]) <= 2
+    assert all(e <= b for e, b in zip(errs, bounds))
+
+
+def _bubble_case(n=128, ratio=1000.0):
+    return W.random_case(31, n, n, n, 0, 0, 1, stretch=1.4, nbub=6, ratio=ratio)
+
+
+def test_projection_is_divergence_free_at_128(pcx, orc):
+    import torch
+    c = _bubble_case()
+    vc = pcx.VarCoef(c.grid)
+    uo, vo, wo, p, it, rr, st = vc.project(c.dt, c.rho0, to_dev(c.rho), to_dev(c.u), to_dev(c.v), to_dev(c.w),
+                                           tol=1e-12, maxit=3000)
+    torch.cuda.synchronize()
+    vc.close()
+    g = orc.Grid.from_workload(c.grid)
+    d0 = np.abs(orc.div(g, c.u, c.v, c.w)).max()
+    d = np.abs(orc.div(g, uo.cpu().numpy(), vo.cpu().numpy(), wo.cpu().numpy())).max()
+    _say(f"varcoef 128^3: iters {it}, res {rr:.2e}, max|D u| {d:.2e} (input {d0:.2e})")
+    assert st == pcx.PCX_OK and d <= 1e-10 * d0
+
+
+def test_constant_density_is_one_iteration_and_the_split_step(pcx):
+    c = _bubble_case(64)
+    rho = np.full(c.grid.shape, 3.0)
+    vc = pcx.VarCoef(c.grid)
+    dev = [to_dev(a) for a in (rho, c.pstar, c.u, c.v, c.w)]
+    uo, vo, wo, p, it, rr, st = vc.project(c.dt, 3.0, dev[0], *dev[2:], tol=1e-12)
+    vc.close()
+    plan = pcx.Plan(c.grid, "fp64")
+    ref = plan.step(c.dt, 3.0, *dev)
+    plan.close()
+    errs = [_rel(a.cpu().numpy(), b.cpu().numpy()) for a, b in zip((uo, vo, wo, p), ref[:4])]
+    _say(f"constant density: iters {it}, errors {errs}")
+    assert it == 1 and max(errs) <= 1e-12
+
+
+def test_split_step_with_this_pressure_reproduces_it(pcx):
+    """p* = the variable-coefficient pressure makes the splitting exact."""
+    c = _bubble_case(96)
+    vc = pcx.VarCoef(c.grid)
+    rho, u, v, w = [to_dev(a) for a in (c.rho, c.u, c.v, c.w)]
+    uo, vo, wo, p, it, rr, st = vc.project(c.dt, c.rho0, rho, u, v, w, tol=1e-13, maxit=3000)
+    vc.close()
+    plan = pcx.Plan(c.grid, "fp64")
+    su, sv, sw, sp, _ = plan.step(c.dt, c.rho0, rho, p, u, v, w)
+    su0 = plan.step(c.dt, c.rho0, rho, to_dev(c.pstar), u, v, w)[0]
+    plan.close()
+    errs = [_rel(a.cpu().numpy(), b.cpu().numpy()) for a, b in zip((su, sv, sw, sp), (uo, vo, wo, p))]
+    split = _rel(su0.cpu().numpy(), uo.cpu().numpy())
+    _say(f"exact p*: iters {it}, errors {errs}; with another p*: {split:.2e}")
+    assert st == pcx.PCX_OK and max(errs) <= 1e-9
+    assert split > 1e-6
+
+
+def test_maxit_and_zero_input(pcx):
+    import torch
+    c = _bubble_case(32)
+    vc = pcx.VarCoef(c.grid)
+    rho = to_dev(c.rho)
+    uo, vo, wo, p, it, rr, st = vc.project(c.dt, c.rho0, rho, to_dev(c.u), to_dev(c.v), to_dev(c.w), tol=1e-14,
+                                           maxit=2)
+    # (conjugate gradients minimize the error's energy norm: the residual's
+    # 2-norm need not fall monotonically, so it is only checked to be finite)
+    assert st == pcx.PCX_ERR_NOT_CONVERGED and it == 2 and 1e-14 < rr < float("inf")
+    assert all(torch.isfinite(t).all().item() for t in (uo, vo, wo, p))
+    z = torch.zeros(c.grid.shape, dtype=torch.float64, device="cuda")
+    uo, vo, wo, p, it, rr, st = vc.project(c.dt, c.rho0, rho, z, z, z)
+    assert st == pcx.PCX_OK and it == 0 and rr == 0.0
+    assert all(float(t.abs().max()) == 0.0 for t in (uo, vo, wo, p))
+    vc.close()
+
+
+def test_rejections(pcx):
+    import torch
+    c = _bubble_case(32)
+    vc = pcx.VarCoef(c.grid)
+    a = [torch.zeros(c.grid.shape, dtype=torch.float64, device="cuda") for _ in range(8)]
+    for kw in ({"tol": -1.0}, {"maxit": 0}):
+        with pytest.raises(pcx.PcxError):
+            vc.project(c.dt, 1.0, *a[:4], outs=a[4:], **kw)
+    with pytest.raises(pcx.PcxError):
+        vc.project(c.dt, 1.0, *a[:4], outs=[a[4], a[5], a[6], a[1]])  # p_out aliases u
+    with pytest.raises(pcx.PcxError):
+        vc.project(0.0, 1.0, *a[:4], outs=a[4:])
+    vc.close()
+    gs = W.GridSpec(16, 16, 8, 1.0, 1.0, W.zf_uniform(8, 1.0), 2, 0, 1)
+    with pytest.raises(pcx.PcxError):
+        pcx.VarCoef(gs)
