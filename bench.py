@@ -101,13 +101,9 @@ def summarize_passes(passes, steps):
 
 
 def src_hash():
-    """Hash of the HIP sources (same definition as in the profile summaries)."""
-    import glob
-    import hashlib
-    h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2502_04189_amd", "csrc", "*"))):
-        h.update(open(f, "rb").read())
-    return h.hexdigest()[:16]
+    """Hash of the step's HIP sources (csrc/pcx_*), as in the profile summaries."""
+    from paper_2502_04189_amd.profsum import src_hash as h
+    return h("pcx_")
 
 
 # pass name -> kernel-name prefix in the rocprofv3 summaries
@@ -510,6 +506,8 @@ def main():
     ap.add_argument("--prof-refined", action="store_true")
     ap.add_argument("--no-flow", action="store_true")
     ap.add_argument("--no-varcoef", action="store_true")
+    ap.add_argument("--prof-varcoef", action="store_true",
+                    help="profiling mode: one variable-coefficient projection of the workload; no JSON")
     ap.add_argument("--prof-flow", action="store_true",
                     help="profiling mode: a few Runge-Kutta steps of the substep around the projection; no JSON")
     ap.add_argument("--prof-batch", action="store_true",
@@ -528,6 +526,7 @@ def main():
 
     if args.prof_batch:
         prof_batch(args.steps, args.warmup, args.ndom)
+        log("prof mode done")
         return
 
     t0 = time.perf_counter()
@@ -541,10 +540,19 @@ def main():
     outs = [torch.empty(gs.shape, dtype=torch.float64, device="cuda") for _ in range(4)]
     cells = gs.cells
 
+    if args.prof_varcoef:
+        plan = pcx.Plan(gs, "fp64")
+        ms, _, _ = time_plan(plan, dev, case.dt, rho0, 2, 1, outs)
+        plan.close()
+        run_varcoef(case, dev, ms)
+        log("prof mode done")
+        return
+
     if args.prof_flow:
         del dev, outs
         torch.cuda.empty_cache()
         run_flow(case, args.steps, args.warmup)
+        log("prof mode done")
         return
 
     if args.prof:

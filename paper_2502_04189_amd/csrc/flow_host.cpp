@@ -22,6 +22,7 @@ struct pcx_flow_s {
     pcx_grid grid;
     std::vector<double> zf;
     FGrid G;
+    TilePlan tp;
     FParams P;
     pcx_plan plan = nullptr;
     double *tab = nullptr;           // dzf, dzc
@@ -96,7 +97,8 @@ extern "C" pcx_status pcx_flow_create(const pcx_grid *grid, const pcx_flow_param
     G.dzf = F->tab;
     G.dzc = F->tab + nz;
     F->P = FParams{q.rho1, q.rho2, q.mu1, q.mu2, q.sigma, {q.gx, q.gy, q.gz}, q.gamma, q.eps, q.eps_s, 0.5 / q.eps};
-    if (hipMalloc(&F->part, (size_t)ngrid(G) * sizeof(unsigned long long)) != hipSuccess) {
+    F->tp = tile_plan(G);
+    if (hipMalloc(&F->part, (size_t)F->tp.nslots * sizeof(unsigned long long)) != hipSuccess) {
         flow_free(F);
         return fail(PCX_ERR_NOMEM, "flow workspace allocation failed");
     }
@@ -163,9 +165,9 @@ extern "C" pcx_status pcx_flow_phase_rhs(pcx_flow F, const double *phi, const do
     hipStream_t s = (hipStream_t)stream;
     FArgs A = base_args(F, phi, u, v, w);
     A.hphi = rhs;
-    FCHK(launch_normals(A, s));
-    FCHK(launch_flux(A, s));
-    FCHK(launch_phase(A, s));
+    FCHK(launch_normals(A, F->tp, s));
+    FCHK(launch_flux(A, F->tp, s));
+    FCHK(launch_phase(A, F->tp, s));
     return PCX_OK;
 }
 
@@ -179,9 +181,9 @@ extern "C" pcx_status pcx_flow_momentum_rhs(pcx_flow F, const double *phi, const
     hipStream_t s = (hipStream_t)stream;
     FArgs A = base_args(F, phi, u, v, w);
     A.hu = ru; A.hv = rv; A.hw = rw;
-    FCHK(launch_normals(A, s));
-    FCHK(launch_flux(A, s));
-    FCHK(launch_momentum(A, s));
+    FCHK(launch_normals(A, F->tp, s));
+    FCHK(launch_flux(A, F->tp, s));
+    FCHK(launch_momentum(A, F->tp, s));
     return PCX_OK;
 }
 
@@ -215,11 +217,11 @@ extern "C" pcx_status pcx_flow_substep(pcx_flow F, int32_t sub, double Dt, const
     A.rho_new = F->rho_new;
     A.p1 = p1; A.p2 = p2; A.r = r;
     A.pstar = F->pstar;
-    FCHK(launch_normals(A, s));
-    FCHK(launch_flux(A, s));
+    FCHK(launch_normals(A, F->tp, s));
+    FCHK(launch_flux(A, F->tp, s));
     // both passes read the state at the start of the substep only
-    FCHK(launch_momentum(A, s));
-    FCHK(launch_phase(A, s));
+    FCHK(launch_momentum(A, F->tp, s));
+    FCHK(launch_phase(A, F->tp, s));
     unsigned long long key = 0;
     FCHK(hipMemcpyAsync(&key, F->key, sizeof(key), hipMemcpyDeviceToHost, s));
     FCHK(hipStreamSynchronize(s));

@@ -1,7 +1,9 @@
 // flow_kernels.hip -- kernels of the Runge-Kutta substep around the pressure
 // correction: normals, regularization flux and curvature, phase-field
-// update, momentum predictor.  One thread per cell on the XCD-grouped
-// plane tiles of flow_tile.hpp.
+// update, momentum predictor.  One thread per cell on the plane tiles of
+// flow_tile.hpp: each stencil kernel is instantiated with the interior
+// accessor (FAST) for the interior box and with the general one for the
+// boxes along the walls.
 #include "flow_launch.hpp"
 #include "flow_tile.hpp"
 
@@ -16,24 +18,24 @@ __global__ __launch_bounds__(FT) void k_flow_psi(FArgs A)
     if (c < n) A.psi[c] = psi_of(A.P, A.phi[c]);
 }
 
-__global__ __launch_bounds__(FT) void k_flow_normals(FArgs A)
+template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_normals(TileBox b, int, FArgs A)
 {
-    const FTile t = ftile(A.G);
+    const FTile t = btile(A.G, b);
     if (!t.act) return;
     double nx, ny, nz;
-    with_acc(A.G, t, [&](const auto &x) { normal_cell(x, A.psi, nx, ny, nz); });
+    with_acc<FAST>(A.G, t, [&](const auto &x) { normal_cell(x, A.psi, nx, ny, nz); });
     const size_t c = at(A.G, t.i, t.j, t.k);
     A.n[0][c] = nx;
     A.n[1][c] = ny;
     A.n[2][c] = nz;
 }
 
-__global__ __launch_bounds__(FT) void k_flow_flux(FArgs A)
+template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_flux(TileBox b, int, FArgs A)
 {
-    const FTile t = ftile(A.G);
+    const FTile t = btile(A.G, b);
     if (!t.act) return;
     const size_t c = at(A.G, t.i, t.j, t.k);
-    with_acc(A.G, t, [&](const auto &x) {
+    with_acc<FAST>(A.G, t, [&](const auto &x) {
         A.a[0][c] = flux_face<0>(x, A.P, A.phi, A.psi, A.n[0]);
         A.a[1][c] = flux_face<1>(x, A.P, A.phi, A.psi, A.n[1]);
         A.a[2][c] = flux_face<2>(x, A.P, A.phi, A.psi, A.n[2]);
@@ -52,16 +54,16 @@ __device__ __forceinline__ unsigned long long fkey(double v)
 // density and the minimum key of the workgroup's densities (one slot per
 // workgroup, reduced by k_flow_min: an atomic per workgroup on one address
 // would serialize half a million workgroups).
-__global__ __launch_bounds__(FT) void k_flow_phase(FArgs A)
+template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_phase(TileBox b, int slot0, FArgs A)
 {
     __shared__ unsigned long long red[FT / 64];
-    const FTile t = ftile(A.G);
+    const FTile t = btile(A.G, b);
     unsigned long long key = ~0ull;
     if (t.act) {
         const size_t c = at(A.G, t.i, t.j, t.k);
         const double *vel[3] = {A.u, A.v, A.w};
         double r = 0.0;
-        with_acc(A.G, t, [&](const auto &x) { r = acdi_cell(x, A.phi, vel, A.a); });
+        with_acc<FAST>(A.G, t, [&](const auto &x) { r = acdi_cell(x, A.phi, vel, A.a); });
         if (A.phi_out) {
             const double old = A.first ? 0.0 : A.hphi[c];
             const double q = A.phi[c] + A.Dt * (A.ga * r + A.ze * old);
@@ -83,7 +85,7 @@ __global__ __launch_bounds__(FT) void k_flow_phase(FArgs A)
     if (threadIdx.x == 0) {
         for (int i = 1; i < FT / 64; ++i) key = red[i] < key ? red[i] : key;
         key = red[0] < key ? red[0] : key;
-        A.rho_part[blockIdx.x] = key;
+        A.rho_part[slot0 + blockIdx.x] = key;
     }
 }
 
@@ -132,14 +134,15 @@ __device__ __forceinline__ void mom_store(const FArgs &A, const FTile &t, size_t
 
 // Momentum right-hand side of the three components (all loads before any
 // store); with u*, the substep's predictor; with p*, the extrapolated
-// pressure.
-__global__ __launch_bounds__(FT) void k_flow_momentum(FArgs A)
+// pressure.  (One kernel per component, each needing about half of these
+// loads, took 13 % longer in all.)
+template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_momentum(TileBox b, int, FArgs A)
 {
-    const FTile t = ftile(A.G);
+    const FTile t = btile(A.G, b);
     if (!t.act) return;
     const size_t c = at(A.G, t.i, t.j, t.k);
     double m0 = 0.0, m1 = 0.0, m2 = 0.0;
-    with_acc(A.G, t, [&](const auto &x) {
+    with_acc<FAST>(A.G, t, [&](const auto &x) {
         m0 = mom_rhs<0>(A, x, t);
         m1 = mom_rhs<1>(A, x, t);
         m2 = mom_rhs<2>(A, x, t);
@@ -152,36 +155,35 @@ __global__ __launch_bounds__(FT) void k_flow_momentum(FArgs A)
 
 __global__ void k_flow_key_reset(unsigned long long *k) { *k = ~0ull; }
 
-#define FLAUNCH(fn, A, s)                                                            \
-    do {                                                                             \
-        hipLaunchKernelGGL(fn, dim3(ngrid((A).G)), dim3(FT), 0, (s), (A));           \
-        return hipGetLastError();                                                    \
-    } while (0)
-
-hipError_t launch_normals(const FArgs &A, hipStream_t s)
+hipError_t launch_normals(const FArgs &A, const TilePlan &tp, hipStream_t s)
 {
     const size_t n = (size_t)A.G.n[0] * A.G.n[1] * A.G.n[2];
     hipLaunchKernelGGL(k_flow_psi, dim3((unsigned)((n + FT - 1) / FT)), dim3(FT), 0, s, A);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    FLAUNCH(k_flow_normals, A, s);
+    return FLOW_LAUNCH_PLAN(tp, k_flow_normals, s, A);
 }
-hipError_t launch_flux(const FArgs &A, hipStream_t s) { FLAUNCH(k_flow_flux, A, s); }
-hipError_t launch_phase(const FArgs &A, hipStream_t s)
+hipError_t launch_flux(const FArgs &A, const TilePlan &tp, hipStream_t s)
+{
+    return FLOW_LAUNCH_PLAN(tp, k_flow_flux, s, A);
+}
+hipError_t launch_phase(const FArgs &A, const TilePlan &tp, hipStream_t s)
 {
     if (A.phi_out) {
         hipLaunchKernelGGL(k_flow_key_reset, dim3(1), dim3(1), 0, s, A.rho_min_key);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_flow_phase, dim3(ngrid(A.G)), dim3(FT), 0, s, A);
-    hipError_t e = hipGetLastError();
+    hipError_t e = FLOW_LAUNCH_PLAN(tp, k_flow_phase, s, A);
     if (e != hipSuccess || !A.phi_out) return e;
-    hipLaunchKernelGGL(k_flow_min, dim3(64), dim3(FT), 0, s, (const unsigned long long *)A.rho_part, ngrid(A.G),
+    hipLaunchKernelGGL(k_flow_min, dim3(64), dim3(FT), 0, s, (const unsigned long long *)A.rho_part, tp.nslots,
                        A.rho_min_key);
     return hipGetLastError();
 }
-hipError_t launch_momentum(const FArgs &A, hipStream_t s) { FLAUNCH(k_flow_momentum, A, s); }
+hipError_t launch_momentum(const FArgs &A, const TilePlan &tp, hipStream_t s)
+{
+    return FLOW_LAUNCH_PLAN(tp, k_flow_momentum, s, A);
+}
 
 double key_to_double(unsigned long long k)
 {

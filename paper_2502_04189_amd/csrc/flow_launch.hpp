@@ -19,16 +19,16 @@ struct FArgs {
     double *hphi, *hu, *hv, *hw;     // previous right-hand sides in, this substep's out
     double *phi_out, *us[3], *rho_new; // NULL: right-hand sides only
     unsigned long long *rho_min_key;
-    unsigned long long *rho_part;    // one key per workgroup of the phase pass (flow_grid of them)
+    unsigned long long *rho_part;    // one key per workgroup of the phase pass (TilePlan::nslots)
     const double *p1, *p2;           // pressures of the two previous substeps
     double r;
     double *pstar;                   // NULL: no extrapolation
 };
 
-hipError_t launch_normals(const FArgs &A, hipStream_t s);
-hipError_t launch_flux(const FArgs &A, hipStream_t s);
-hipError_t launch_phase(const FArgs &A, hipStream_t s);
-hipError_t launch_momentum(const FArgs &A, hipStream_t s);
+hipError_t launch_normals(const FArgs &A, const TilePlan &tp, hipStream_t s);
+hipError_t launch_flux(const FArgs &A, const TilePlan &tp, hipStream_t s);
+hipError_t launch_phase(const FArgs &A, const TilePlan &tp, hipStream_t s);
+hipError_t launch_momentum(const FArgs &A, const TilePlan &tp, hipStream_t s);
 double key_to_double(unsigned long long k);
 
 } // namespace flow

@@ -1,8 +1,16 @@
 // flow_tile.hpp -- tiling of the one-thread-per-cell stencil launches of
 // the substep and of the variable-coefficient projection: 256-thread
-// workgroups of 64 x 4 cells of one plane; consecutive workgroups go to
-// different XCDs, so the launch hands XCD x a contiguous range of tiles (its
-// planes), and a tile's y and z neighbours are mostly in that XCD's L2.
+// workgroups of 64 x 4 cells of one plane.
+//
+// The tiles of a grid are split into boxes (ranges of x tiles, y tiles and
+// planes): one interior box whose stencils reach no wall, run by a kernel
+// instantiated with the branch-free interior accessor only, and up to six
+// boxes around it, run by the same kernel instantiated with the general
+// accessor.  Kept apart, the interior kernel gets the register budget of its
+// own short code (the general accessor's wall cases raised the register
+// count and cut occupancy for every tile).  Within a launch consecutive
+// workgroups go to different XCDs, so XCD x gets a contiguous range of the
+// box's tiles in the order below.
 #pragma once
 
 #include "flow_dev.hpp"
@@ -12,52 +20,126 @@ namespace flow {
 
 constexpr int FT = 256, FTI = 64, FTJ = FT / FTI;
 
-struct FTile {
-    int i, j, k;
-    bool act;
-    bool fast; // no stencil of the tile reaches a wall (uniform over the workgroup)
+// tiles [it0, it0 + nit) x [jt0, jt0 + njt) x planes [k0, k0 + nk)
+struct TileBox {
+    int it0, jt0, k0, nit, njt, nk;
 };
 
-__device__ __forceinline__ FTile ftile(const FGrid &G)
+__host__ __device__ inline long box_tiles(const TileBox &b) { return (long)b.nit * b.njt * b.nk; }
+
+// workgroups of a launch over a box (a multiple of 8, the XCD count)
+inline int box_grid(const TileBox &b)
 {
-    const int ti = (G.n[0] + FTI - 1) / FTI, tj = (G.n[1] + FTJ - 1) / FTJ;
-    const long nt = (long)ti * tj * G.n[2];
-    const long per = (nt + 7) >> 3;
+    const long n = box_tiles(b);
+    return (int)(((n + 7) >> 3) << 3);
+}
+
+// The launches of one grid: box b runs with the interior accessor when
+// fast[b]; its workgroups own partial-result slots [slot0[b], slot0[b] +
+// box_grid(box[b])); nslots in all.
+struct TilePlan {
+    int n;
+    TileBox box[7];
+    bool fast[7];
+    int slot0[7];
+    int nslots;
+};
+
+// Tile boxes of a grid.  The stencils reach one cell (and one face) beyond
+// their cell, so a wall direction's interior tiles lie within [1, n-3]: x
+// tiles it >= 1 with (it + 1) FTI <= nx - 2, likewise y, planes 1 .. nz-3.
+inline TilePlan tile_plan(const FGrid &G)
+{
+    const int ti = (G.n[0] + FTI - 1) / FTI, tj = (G.n[1] + FTJ - 1) / FTJ, nz = G.n[2];
+    const int it0 = G.per[0] ? 0 : 1, it1 = G.per[0] ? ti : (G.n[0] - 2) / FTI;
+    const int jt0 = G.per[1] ? 0 : 1, jt1 = G.per[1] ? tj : (G.n[1] - 2) / FTJ;
+    const int k0 = G.per[2] ? 0 : 1, k1 = G.per[2] ? nz : nz - 2;
+    TilePlan p{};
+    auto add = [&](TileBox b, bool fast) {
+        if (b.nit <= 0 || b.njt <= 0 || b.nk <= 0) return;
+        p.box[p.n] = b;
+        p.fast[p.n] = fast;
+        p.slot0[p.n] = p.nslots;
+        p.nslots += box_grid(b);
+        ++p.n;
+    };
+    if (it1 <= it0 || jt1 <= jt0 || k1 <= k0) {
+        add(TileBox{0, 0, 0, ti, tj, nz}, false);
+        return p;
+    }
+    add(TileBox{it0, jt0, k0, it1 - it0, jt1 - jt0, k1 - k0}, true);
+    add(TileBox{0, 0, 0, ti, tj, k0}, false);                            // planes below
+    add(TileBox{0, 0, k1, ti, tj, nz - k1}, false);                      // planes above
+    add(TileBox{0, 0, k0, ti, jt0, k1 - k0}, false);                     // rows south
+    add(TileBox{0, jt1, k0, ti, tj - jt1, k1 - k0}, false);              // rows north
+    add(TileBox{0, jt0, k0, it0, jt1 - jt0, k1 - k0}, false);            // columns west
+    add(TileBox{it1, jt0, k0, ti - it1, jt1 - jt0, k1 - k0}, false);     // columns east
+    return p;
+}
+
+struct FTile {
+    int i, j, k;
+    bool act; // the thread's cell is in the grid
+};
+
+// Order of the tiles within a box: chunks of TKC planes; within a chunk, x
+// tiles fastest, then planes, then y tiles.  A tile's z neighbours are then
+// nit tiles away in the launch order and its y neighbours nit * TKC tiles
+// away, inside the window of workgroups an XCD runs at once, so the planes
+// and rows a tile re-reads are still in that XCD's L2 (ordered plane by
+// plane, the next plane of the same tile came a whole plane of tiles later
+// and every z neighbour was fetched again).
+constexpr int TKC = 16;
+
+// the thread's cell in the launch over box b (act false past the box or the grid)
+__device__ __forceinline__ FTile btile(const FGrid &G, const TileBox &b)
+{
+    const long n = box_tiles(b);
+    const long per = (n + 7) >> 3;
     const long t = (long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
     FTile c;
     c.act = false;
     c.i = c.j = c.k = 0;
-    if (t >= nt) return c;
-    const int k = (int)(t / ((long)ti * tj));
-    const int r = (int)(t - (long)k * ti * tj);
-    const int jt = r / ti, it = r - jt * ti;
-    c.i = it * FTI + (threadIdx.x % FTI);
-    c.j = jt * FTJ + (threadIdx.x / FTI);
-    c.k = k;
+    if (t >= n) return c;
+    const long chunk = (long)b.nit * b.njt * TKC;
+    const int kc = (int)(t / chunk);
+    const int rem = (int)(t - (long)kc * chunk);
+    const int kb = kc * TKC;
+    const int nkc = b.nk - kb < TKC ? b.nk - kb : TKC; // planes in this chunk
+    const int ii = rem % b.nit;
+    const int q = rem / b.nit;
+    const int kk = q % nkc, jj = q / nkc;
+    c.i = (b.it0 + ii) * FTI + (threadIdx.x % FTI);
+    c.j = (b.jt0 + jj) * FTJ + (threadIdx.x / FTI);
+    c.k = b.k0 + kb + kk;
     c.act = c.i < G.n[0] && c.j < G.n[1];
-    // the stencils reach one cell (and one face) beyond the cell: a wall
-    // direction needs the tile within [1, n-3]
-    const int i0 = it * FTI, j0 = jt * FTJ;
-    c.fast = (G.per[0] || (i0 >= 1 && i0 + FTI - 1 <= G.n[0] - 3)) &&
-             (G.per[1] || (j0 >= 1 && j0 + FTJ - 1 <= G.n[1] - 3)) && (G.per[2] || (k >= 1 && k <= G.n[2] - 3));
     return c;
 }
 
-// runs body(accessor) with the branch-free interior accessor on tiles that
-// reach no wall, the general one elsewhere
-template <class Body> __device__ __forceinline__ void with_acc(const FGrid &G, const FTile &t, Body body)
+// runs body(accessor): the interior accessor in the FAST instantiation, the
+// general one otherwise
+template <bool FAST, class Body> __device__ __forceinline__ void with_acc(const FGrid &G, const FTile &t, Body body)
 {
-    if (t.fast) body(Fast(G, t.i, t.j, t.k));
+    if constexpr (FAST) body(Fast(G, t.i, t.j, t.k));
     else body(Gen{G, t.i, t.j, t.k});
 }
 
-// workgroups of a one-thread-per-cell tile launch over the grid (a multiple
-// of 8, the XCD count)
-inline int ngrid(const FGrid &G)
-{
-    const long nt = (long)((G.n[0] + FTI - 1) / FTI) * ((G.n[1] + FTJ - 1) / FTJ) * G.n[2];
-    return (int)(((nt + 7) >> 3) << 3);
-}
+// Launches kernel<true> on the interior box and kernel<false> on the others;
+// every kernel takes (box, first slot, args...).
+#define FLOW_LAUNCH_PLAN(TP, KERNEL, STREAM, ...)                                                          \
+    ([&]() -> hipError_t {                                                                                \
+        for (int b_ = 0; b_ < (TP).n; ++b_) {                                                             \
+            if ((TP).fast[b_])                                                                            \
+                hipLaunchKernelGGL(KERNEL<true>, dim3(box_grid((TP).box[b_])), dim3(FT), 0, (STREAM),     \
+                                   (TP).box[b_], (TP).slot0[b_], __VA_ARGS__);                            \
+            else                                                                                          \
+                hipLaunchKernelGGL(KERNEL<false>, dim3(box_grid((TP).box[b_])), dim3(FT), 0, (STREAM),    \
+                                   (TP).box[b_], (TP).slot0[b_], __VA_ARGS__);                            \
+            const hipError_t e_ = hipGetLastError();                                                      \
+            if (e_ != hipSuccess) return e_;                                                              \
+        }                                                                                                 \
+        return hipSuccess;                                                                                \
+    }())
 
 } // namespace flow
 } // namespace pcx

@@ -19,6 +19,7 @@ using namespace pcx::vc;
 struct pcx_varcoef_s {
     std::vector<double> zf;
     flow::FGrid G;
+    flow::TilePlan tp;
     pcx_plan plan = nullptr;
     double *tab = nullptr; // dzf, dzc
     double *ws = nullptr;  // r, z, d, q
@@ -81,7 +82,8 @@ extern "C" pcx_status pcx_varcoef_create(const pcx_grid *grid, const pcx_options
     G.h[0] = grid->lx / nx;
     G.h[1] = grid->ly / ny;
     V->ncell = (size_t)nx * ny * nz;
-    const int nb = flow::ngrid(G);
+    V->tp = flow::tile_plan(G);
+    const int nb = V->tp.nslots;
     const size_t nred = 2 * (size_t)nb + 2 * RED_WG + NSC;
     if (hipMalloc(&V->tab, t.size() * sizeof(double)) != hipSuccess ||
         hipMalloc(&V->ws, 4 * V->ncell * sizeof(double)) != hipSuccess ||
@@ -122,7 +124,7 @@ extern "C" pcx_status pcx_varcoef_apply(pcx_varcoef V, const double *rho, const 
 {
     if (!V || !rho || !p || !out) return fail(PCX_ERR_INVALID, "NULL argument");
     if (out == rho || out == p) return fail(PCX_ERR_INVALID, "out aliases an input");
-    VCHK(launch_apply(V->G, rho, p, out, 1.0, nullptr, (hipStream_t)stream));
+    VCHK(launch_apply(V->G, V->tp, rho, p, out, 1.0, nullptr, (hipStream_t)stream));
     return PCX_OK;
 }
 
@@ -158,9 +160,9 @@ extern "C" pcx_status pcx_varcoef_project(pcx_varcoef V, double dt, double rho0,
     const VRed &R = V->R;
     double *p = p_out;
     // r = -(D u*)/dt minus its mean; bnorm = its norm
-    VCHK(launch_rhs(G, u, v, w, 1.0 / dt, V->r, R, s));
+    VCHK(launch_rhs(G, V->tp, u, v, w, 1.0 / dt, V->r, R, s));
     VCHK(red_scal(R, MODE_MEAN, s));
-    VCHK(launch_center(G, V->r, R, s));
+    VCHK(launch_center(G, V->tp, V->r, R, s));
     VCHK(red_scal(R, MODE_BNORM, s));
     VCHK(hipMemsetAsync(p, 0, V->ncell * sizeof(double), s));
     double res = 0.0;
@@ -171,12 +173,12 @@ extern "C" pcx_status pcx_varcoef_project(pcx_varcoef V, double dt, double rho0,
         // z = -rho0 L^-1 r (the solve; the factor is folded into the kernels)
         st = pcx_poisson_solve(V->plan, V->r, V->z, stream);
         if (st != PCX_OK) return st;
-        VCHK(launch_dinit(G, V->r, V->z, V->d, rho0, R, s));
+        VCHK(launch_dinit(G, V->tp, V->r, V->z, V->d, rho0, R, s));
         VCHK(red_scal(R, MODE_RZ, s));
         while (it < maxit) {
-            VCHK(launch_apply(G, rho, V->d, V->q, -1.0, &R, s));
+            VCHK(launch_apply(G, V->tp, rho, V->d, V->q, -1.0, &R, s));
             VCHK(red_scal(R, MODE_ALPHA, s));
-            VCHK(launch_update(G, p, V->d, V->r, V->q, R, s));
+            VCHK(launch_update(G, V->tp, p, V->d, V->r, V->q, R, s));
             VCHK(red_scal(R, MODE_RES, s));
             ++it;
             st = read_sc(V, S_RES, s, &res);
@@ -191,16 +193,16 @@ extern "C" pcx_status pcx_varcoef_project(pcx_varcoef V, double dt, double rho0,
             // mode); the dot pass removes it from r itself
             st = pcx_poisson_solve(V->plan, V->r, V->z, stream);
             if (st != PCX_OK) return st;
-            VCHK(launch_dot(G, V->r, V->z, rho0, R, s));
+            VCHK(launch_dot(G, V->tp, V->r, V->z, rho0, R, s));
             VCHK(red_scal(R, MODE_BETA, s));
-            VCHK(launch_dupd(G, V->z, V->d, rho0, R, s));
+            VCHK(launch_dupd(G, V->tp, V->z, V->d, rho0, R, s));
         }
     }
     // correction with p (its gradient does not see the mean), then the gauge
-    VCHK(launch_pmean(G, p, R, s));
+    VCHK(launch_pmean(G, V->tp, p, R, s));
     VCHK(red_scal(R, MODE_PMEAN, s));
-    VCHK(launch_correct(G, rho, p, u, v, w, dt, u_out, v_out, w_out, s));
-    VCHK(launch_pshift(G, p, R, s));
+    VCHK(launch_correct(G, V->tp, rho, p, u, v, w, dt, u_out, v_out, w_out, s));
+    VCHK(launch_pshift(G, V->tp, p, R, s));
     if (iters) *iters = it;
     if (relres) *relres = res;
     if (res > tol) return fail(PCX_ERR_NOT_CONVERGED, "maxit reached before tol");

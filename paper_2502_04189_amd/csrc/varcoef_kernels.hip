@@ -2,7 +2,8 @@
 // D((1/rho_f) G p) = (D u*) / dt solved by preconditioned conjugate gradients
 // (the preconditioner is the constant-coefficient solve of the plan, run by
 // the host between these kernels).  Stencil and vector kernels run one
-// thread per cell on the XCD-grouped plane tiles of flow_tile.hpp; the inner
+// thread per cell on the plane tiles of flow_tile.hpp (the stencils with the
+// interior accessor on the interior box, the general one elsewhere); the inner
 // products are volume-weighted (the dzf factor; dx dy is common to all cells
 // and cancels in every ratio the iteration takes) and are reduced in a fixed
 // order, so a run is deterministic.  The iteration's scalars stay in device
@@ -43,12 +44,12 @@ __device__ __forceinline__ void block_sum2(double &a, double &b)
     }
 }
 
-__device__ __forceinline__ void put2(const VRed &R, double a, double b)
+__device__ __forceinline__ void put2(const VRed &R, int slot0, double a, double b)
 {
     block_sum2(a, b);
     if (threadIdx.x == 0) {
-        R.part[blockIdx.x] = a;
-        R.part[R.nb + blockIdx.x] = b;
+        R.part[slot0 + blockIdx.x] = a;
+        R.part[R.nb + slot0 + blockIdx.x] = b;
     }
 }
 
@@ -77,40 +78,43 @@ __device__ __forceinline__ double div_cell(const X &x, const double *u, const do
 }
 
 // out = sign D((1/rho_f) G p); with R, partial sums of dzf p out
-__global__ __launch_bounds__(FT) void k_vc_apply(FGrid G, const double *rho, const double *p, double *out,
+template <bool FAST>
+__global__ __launch_bounds__(FT) void k_vc_apply(TileBox bx, int slot0, FGrid G, const double *rho, const double *p, double *out,
                                                  double sign, VRed R, int want)
 {
-    const FTile t = ftile(G);
+    const FTile t = btile(G, bx);
     double a = 0.0;
     if (t.act) {
         double q = 0.0;
-        with_acc(G, t, [&](const auto &x) { q = sign * vdiv_cell(x, rho, p); });
+        with_acc<FAST>(G, t, [&](const auto &x) { q = sign * vdiv_cell(x, rho, p); });
         const size_t c = at(G, t.i, t.j, t.k);
         out[c] = q;
         a = G.dzf[t.k] * p[c] * q;
     }
-    if (want) put2(R, a, 0.0);
+    if (want) put2(R, slot0, a, 0.0);
 }
 
 // r = -(D u) / dt; partial sum of dzf r
-__global__ __launch_bounds__(FT) void k_vc_rhs(FGrid G, const double *u, const double *v, const double *w,
+template <bool FAST>
+__global__ __launch_bounds__(FT) void k_vc_rhs(TileBox bx, int slot0, FGrid G, const double *u, const double *v, const double *w,
                                                double idt, double *r, VRed R)
 {
-    const FTile t = ftile(G);
+    const FTile t = btile(G, bx);
     double a = 0.0;
     if (t.act) {
         double q = 0.0;
-        with_acc(G, t, [&](const auto &x) { q = -div_cell(x, u, v, w) * idt; });
+        with_acc<FAST>(G, t, [&](const auto &x) { q = -div_cell(x, u, v, w) * idt; });
         r[at(G, t.i, t.j, t.k)] = q;
         a = G.dzf[t.k] * q;
     }
-    put2(R, a, 0.0);
+    put2(R, slot0, a, 0.0);
 }
 
 // r -= m; partial sum of dzf r^2
-__global__ __launch_bounds__(FT) void k_vc_center(FGrid G, double *r, VRed R)
+template <bool FAST>
+__global__ __launch_bounds__(FT) void k_vc_center(TileBox bx, int slot0, FGrid G, double *r, VRed R)
 {
-    const FTile t = ftile(G);
+    const FTile t = btile(G, bx);
     double a = 0.0;
     if (t.act) {
         const size_t c = at(G, t.i, t.j, t.k);
@@ -118,14 +122,15 @@ __global__ __launch_bounds__(FT) void k_vc_center(FGrid G, double *r, VRed R)
         r[c] = q;
         a = G.dzf[t.k] * q * q;
     }
-    put2(R, a, 0.0);
+    put2(R, slot0, a, 0.0);
 }
 
 // d = -rho0 z (z: the constant-coefficient solve of r); partial dzf r d
-__global__ __launch_bounds__(FT) void k_vc_dinit(FGrid G, const double *r, const double *z, double *d, double rho0,
+template <bool FAST>
+__global__ __launch_bounds__(FT) void k_vc_dinit(TileBox bx, int slot0, FGrid G, const double *r, const double *z, double *d, double rho0,
                                                  VRed R)
 {
-    const FTile t = ftile(G);
+    const FTile t = btile(G, bx);
     double a = 0.0;
     if (t.act) {
         const size_t c = at(G, t.i, t.j, t.k);
@@ -133,14 +138,15 @@ __global__ __launch_bounds__(FT) void k_vc_dinit(FGrid G, const double *r, const
         d[c] = q;
         a = G.dzf[t.k] * r[c] * q;
     }
-    put2(R, a, 0.0);
+    put2(R, slot0, a, 0.0);
 }
 
 // p += alpha d; r -= alpha q; partial sums of dzf r and dzf r^2
-__global__ __launch_bounds__(FT) void k_vc_update(FGrid G, double *p, const double *d, double *r, const double *q,
+template <bool FAST>
+__global__ __launch_bounds__(FT) void k_vc_update(TileBox bx, int slot0, FGrid G, double *p, const double *d, double *r, const double *q,
                                                   VRed R)
 {
-    const FTile t = ftile(G);
+    const FTile t = btile(G, bx);
     double a = 0.0, b = 0.0;
     if (t.act) {
         const size_t c = at(G, t.i, t.j, t.k);
@@ -152,13 +158,14 @@ __global__ __launch_bounds__(FT) void k_vc_update(FGrid G, double *p, const doub
         a = wz * rr;
         b = wz * rr * rr;
     }
-    put2(R, a, b);
+    put2(R, slot0, a, b);
 }
 
 // r -= m (the mean the residual drifted by); partial dzf r (-rho0 z)
-__global__ __launch_bounds__(FT) void k_vc_dot(FGrid G, double *r, const double *z, double rho0, VRed R)
+template <bool FAST>
+__global__ __launch_bounds__(FT) void k_vc_dot(TileBox bx, int slot0, FGrid G, double *r, const double *z, double rho0, VRed R)
 {
-    const FTile t = ftile(G);
+    const FTile t = btile(G, bx);
     double a = 0.0;
     if (t.act) {
         const size_t c = at(G, t.i, t.j, t.k);
@@ -166,43 +173,47 @@ __global__ __launch_bounds__(FT) void k_vc_dot(FGrid G, double *r, const double 
         r[c] = rr;
         a = G.dzf[t.k] * rr * (-rho0 * z[c]);
     }
-    put2(R, a, 0.0);
+    put2(R, slot0, a, 0.0);
 }
 
 // d = -rho0 z + beta d
-__global__ __launch_bounds__(FT) void k_vc_dupd(FGrid G, const double *z, double *d, double rho0, VRed R)
+template <bool FAST>
+__global__ __launch_bounds__(FT) void k_vc_dupd(TileBox bx, int slot0, FGrid G, const double *z, double *d, double rho0, VRed R)
 {
-    const FTile t = ftile(G);
+    const FTile t = btile(G, bx);
     if (!t.act) return;
     const size_t c = at(G, t.i, t.j, t.k);
     d[c] = -rho0 * z[c] + R.sc[S_BETA] * d[c];
 }
 
-__global__ __launch_bounds__(FT) void k_vc_pmean(FGrid G, const double *p, VRed R)
+template <bool FAST>
+__global__ __launch_bounds__(FT) void k_vc_pmean(TileBox bx, int slot0, FGrid G, const double *p, VRed R)
 {
-    const FTile t = ftile(G);
+    const FTile t = btile(G, bx);
     double a = 0.0;
     if (t.act) a = G.dzf[t.k] * p[at(G, t.i, t.j, t.k)];
-    put2(R, a, 0.0);
+    put2(R, slot0, a, 0.0);
 }
 
-__global__ __launch_bounds__(FT) void k_vc_pshift(FGrid G, double *p, VRed R)
+template <bool FAST>
+__global__ __launch_bounds__(FT) void k_vc_pshift(TileBox bx, int slot0, FGrid G, double *p, VRed R)
 {
-    const FTile t = ftile(G);
+    const FTile t = btile(G, bx);
     if (!t.act) return;
     p[at(G, t.i, t.j, t.k)] -= R.sc[S_PMEAN];
 }
 
 // u_out = u - dt (1/rho_f) G p on the +face of each direction, 0 on a wall face
-__global__ __launch_bounds__(FT) void k_vc_correct(FGrid G, const double *rho, const double *p, const double *u,
+template <bool FAST>
+__global__ __launch_bounds__(FT) void k_vc_correct(TileBox bx, int slot0, FGrid G, const double *rho, const double *p, const double *u,
                                                    const double *v, const double *w, double dt, double *uo,
                                                    double *vo, double *wo)
 {
-    const FTile t = ftile(G);
+    const FTile t = btile(G, bx);
     if (!t.act) return;
     const size_t c = at(G, t.i, t.j, t.k);
     double gx = 0.0, gy = 0.0, gz = 0.0;
-    with_acc(G, t, [&](const auto &x) {
+    with_acc<FAST>(G, t, [&](const auto &x) {
         gx = bflux<0>(x, rho, p, 0);
         gy = bflux<1>(x, rho, p, 0);
         gz = bflux<2>(x, rho, p, 0);
@@ -268,66 +279,62 @@ __global__ __launch_bounds__(FT) void k_vc_scal(VRed R, int mode)
     }
 }
 
-static dim3 grid_of(const FGrid &G) { return dim3((unsigned)ngrid(G)); }
-
-#define VLAUNCH(...)                                                                                             \
-    do {                                                                                                         \
-        hipLaunchKernelGGL(__VA_ARGS__);                                                                         \
-        return hipGetLastError();                                                                                \
-    } while (0)
-
-hipError_t launch_apply(const FGrid &G, const double *rho, const double *p, double *out, double sign,
-                        const VRed *R, hipStream_t s)
+hipError_t launch_apply(const FGrid &G, const TilePlan &tp, const double *rho, const double *p, double *out,
+                        double sign, const VRed *R, hipStream_t s)
 {
-    VRed r0{};
-    VLAUNCH(k_vc_apply, grid_of(G), dim3(FT), 0, s, G, rho, p, out, sign, R ? *R : r0, R ? 1 : 0);
+    const VRed r0{};
+    return FLOW_LAUNCH_PLAN(tp, k_vc_apply, s, G, rho, p, out, sign, R ? *R : r0, R ? 1 : 0);
 }
-hipError_t launch_rhs(const FGrid &G, const double *u, const double *v, const double *w, double idt, double *r,
-                      const VRed &R, hipStream_t s)
+hipError_t launch_rhs(const FGrid &G, const TilePlan &tp, const double *u, const double *v, const double *w,
+                      double idt, double *r, const VRed &R, hipStream_t s)
 {
-    VLAUNCH(k_vc_rhs, grid_of(G), dim3(FT), 0, s, G, u, v, w, idt, r, R);
+    return FLOW_LAUNCH_PLAN(tp, k_vc_rhs, s, G, u, v, w, idt, r, R);
 }
-hipError_t launch_center(const FGrid &G, double *r, const VRed &R, hipStream_t s)
+hipError_t launch_center(const FGrid &G, const TilePlan &tp, double *r, const VRed &R, hipStream_t s)
 {
-    VLAUNCH(k_vc_center, grid_of(G), dim3(FT), 0, s, G, r, R);
+    return FLOW_LAUNCH_PLAN(tp, k_vc_center, s, G, r, R);
 }
-hipError_t launch_dinit(const FGrid &G, const double *r, const double *z, double *d, double rho0, const VRed &R,
-                        hipStream_t s)
+hipError_t launch_dinit(const FGrid &G, const TilePlan &tp, const double *r, const double *z, double *d, double rho0,
+                        const VRed &R, hipStream_t s)
 {
-    VLAUNCH(k_vc_dinit, grid_of(G), dim3(FT), 0, s, G, r, z, d, rho0, R);
+    return FLOW_LAUNCH_PLAN(tp, k_vc_dinit, s, G, r, z, d, rho0, R);
 }
-hipError_t launch_update(const FGrid &G, double *p, const double *d, double *r, const double *q, const VRed &R,
-                         hipStream_t s)
+hipError_t launch_update(const FGrid &G, const TilePlan &tp, double *p, const double *d, double *r, const double *q,
+                         const VRed &R, hipStream_t s)
 {
-    VLAUNCH(k_vc_update, grid_of(G), dim3(FT), 0, s, G, p, d, r, q, R);
+    return FLOW_LAUNCH_PLAN(tp, k_vc_update, s, G, p, d, r, q, R);
 }
-hipError_t launch_dot(const FGrid &G, double *r, const double *z, double rho0, const VRed &R, hipStream_t s)
+hipError_t launch_dot(const FGrid &G, const TilePlan &tp, double *r, const double *z, double rho0, const VRed &R,
+                      hipStream_t s)
 {
-    VLAUNCH(k_vc_dot, grid_of(G), dim3(FT), 0, s, G, r, z, rho0, R);
+    return FLOW_LAUNCH_PLAN(tp, k_vc_dot, s, G, r, z, rho0, R);
 }
-hipError_t launch_dupd(const FGrid &G, const double *z, double *d, double rho0, const VRed &R, hipStream_t s)
+hipError_t launch_dupd(const FGrid &G, const TilePlan &tp, const double *z, double *d, double rho0, const VRed &R,
+                       hipStream_t s)
 {
-    VLAUNCH(k_vc_dupd, grid_of(G), dim3(FT), 0, s, G, z, d, rho0, R);
+    return FLOW_LAUNCH_PLAN(tp, k_vc_dupd, s, G, z, d, rho0, R);
 }
-hipError_t launch_pmean(const FGrid &G, const double *p, const VRed &R, hipStream_t s)
+hipError_t launch_pmean(const FGrid &G, const TilePlan &tp, const double *p, const VRed &R, hipStream_t s)
 {
-    VLAUNCH(k_vc_pmean, grid_of(G), dim3(FT), 0, s, G, p, R);
+    return FLOW_LAUNCH_PLAN(tp, k_vc_pmean, s, G, p, R);
 }
-hipError_t launch_correct(const FGrid &G, const double *rho, const double *p, const double *u, const double *v,
-                          const double *w, double dt, double *uo, double *vo, double *wo, hipStream_t s)
+hipError_t launch_correct(const FGrid &G, const TilePlan &tp, const double *rho, const double *p, const double *u,
+                          const double *v, const double *w, double dt, double *uo, double *vo, double *wo,
+                          hipStream_t s)
 {
-    VLAUNCH(k_vc_correct, grid_of(G), dim3(FT), 0, s, G, rho, p, u, v, w, dt, uo, vo, wo);
+    return FLOW_LAUNCH_PLAN(tp, k_vc_correct, s, G, rho, p, u, v, w, dt, uo, vo, wo);
 }
-hipError_t launch_pshift(const FGrid &G, double *p, const VRed &R, hipStream_t s)
+hipError_t launch_pshift(const FGrid &G, const TilePlan &tp, double *p, const VRed &R, hipStream_t s)
 {
-    VLAUNCH(k_vc_pshift, grid_of(G), dim3(FT), 0, s, G, p, R);
+    return FLOW_LAUNCH_PLAN(tp, k_vc_pshift, s, G, p, R);
 }
 hipError_t red_scal(const VRed &R, int mode, hipStream_t s)
 {
     hipLaunchKernelGGL(k_vc_red, dim3(RED_WG), dim3(FT), 0, s, R);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    VLAUNCH(k_vc_scal, dim3(1), dim3(FT), 0, s, R, mode);
+    hipLaunchKernelGGL(k_vc_scal, dim3(1), dim3(FT), 0, s, R, mode);
+    return hipGetLastError();
 }
 
 } // namespace vc

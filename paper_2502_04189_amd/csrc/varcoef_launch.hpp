@@ -27,8 +27,9 @@ enum {
 constexpr int RED_WG = 256;
 
 // Reductions: every partial-writing kernel stores the two sums of its
-// workgroup b at part[b] and part[nb + b] (nb = flow::ngrid(G)); red_scal
-// sums them in a fixed order into the scalar slots.
+// workgroup b (numbered over the launches of the tile plan) at part[b] and
+// part[nb + b] (nb = TilePlan::nslots); red_scal sums them in a fixed order
+// into the scalar slots.
 struct VRed {
     double *part; // 2 nb
     double *lvl;  // 2 RED_WG
@@ -38,21 +39,26 @@ struct VRed {
 
 using flow::FGrid;
 
-hipError_t launch_apply(const FGrid &G, const double *rho, const double *p, double *out, double sign,
-                        const VRed *R, hipStream_t s);
-hipError_t launch_rhs(const FGrid &G, const double *u, const double *v, const double *w, double idt, double *r,
-                      const VRed &R, hipStream_t s);
-hipError_t launch_center(const FGrid &G, double *r, const VRed &R, hipStream_t s);
-hipError_t launch_dinit(const FGrid &G, const double *r, const double *z, double *d, double rho0, const VRed &R,
-                        hipStream_t s);
-hipError_t launch_update(const FGrid &G, double *p, const double *d, double *r, const double *q, const VRed &R,
-                         hipStream_t s);
-hipError_t launch_dot(const FGrid &G, double *r, const double *z, double rho0, const VRed &R, hipStream_t s);
-hipError_t launch_dupd(const FGrid &G, const double *z, double *d, double rho0, const VRed &R, hipStream_t s);
-hipError_t launch_pmean(const FGrid &G, const double *p, const VRed &R, hipStream_t s);
-hipError_t launch_correct(const FGrid &G, const double *rho, const double *p, const double *u, const double *v,
-                          const double *w, double dt, double *uo, double *vo, double *wo, hipStream_t s);
-hipError_t launch_pshift(const FGrid &G, double *p, const VRed &R, hipStream_t s);
+using flow::TilePlan;
+
+hipError_t launch_apply(const FGrid &G, const TilePlan &tp, const double *rho, const double *p, double *out,
+                        double sign, const VRed *R, hipStream_t s);
+hipError_t launch_rhs(const FGrid &G, const TilePlan &tp, const double *u, const double *v, const double *w,
+                      double idt, double *r, const VRed &R, hipStream_t s);
+hipError_t launch_center(const FGrid &G, const TilePlan &tp, double *r, const VRed &R, hipStream_t s);
+hipError_t launch_dinit(const FGrid &G, const TilePlan &tp, const double *r, const double *z, double *d, double rho0,
+                        const VRed &R, hipStream_t s);
+hipError_t launch_update(const FGrid &G, const TilePlan &tp, double *p, const double *d, double *r, const double *q,
+                         const VRed &R, hipStream_t s);
+hipError_t launch_dot(const FGrid &G, const TilePlan &tp, double *r, const double *z, double rho0, const VRed &R,
+                      hipStream_t s);
+hipError_t launch_dupd(const FGrid &G, const TilePlan &tp, const double *z, double *d, double rho0, const VRed &R,
+                       hipStream_t s);
+hipError_t launch_pmean(const FGrid &G, const TilePlan &tp, const double *p, const VRed &R, hipStream_t s);
+hipError_t launch_correct(const FGrid &G, const TilePlan &tp, const double *rho, const double *p, const double *u,
+                          const double *v, const double *w, double dt, double *uo, double *vo, double *wo,
+                          hipStream_t s);
+hipError_t launch_pshift(const FGrid &G, const TilePlan &tp, double *p, const VRed &R, hipStream_t s);
 // the two-level reduction of the partials and the scalar step `mode`
 hipError_t red_scal(const VRed &R, int mode, hipStream_t s);
 
