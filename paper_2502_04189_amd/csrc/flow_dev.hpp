@@ -195,8 +195,8 @@ template <class X> __device__ __forceinline__ double ihcen(const X &x, int D, in
 
 // cell quantity b0 + b1 q on the +D face of the cell s steps along D: mean
 // in x, y, linear interpolation in z
-template <int D, class X>
-__device__ __forceinline__ double cface(const X &x, const double *q, int s, double b0 = 0.0, double b1 = 1.0)
+template <int D, class X, class Q>
+__device__ __forceinline__ double cface(const X &x, Q q, int s, double b0 = 0.0, double b1 = 1.0)
 {
     const double q0 = b0 + b1 * x.cv(q, DOFF(D, s)), q1 = b0 + b1 * x.cv(q, DOFF(D, s + 1));
     if constexpr (D < 2) return 0.5 * (q0 + q1);
@@ -204,7 +204,7 @@ __device__ __forceinline__ double cface(const X &x, const double *q, int s, doub
 }
 
 // difference quotient of a cell quantity across that face
-template <int D, class X> __device__ __forceinline__ double cgrad(const X &x, const double *q, int s)
+template <int D, class X, class Q> __device__ __forceinline__ double cgrad(const X &x, Q q, int s)
 {
     return (x.cv(q, DOFF(D, s + 1)) - x.cv(q, DOFF(D, s))) * ihcen(x, D, s);
 }
@@ -216,6 +216,44 @@ __device__ __forceinline__ double psi_of(const FParams &P, double phi)
     const double q = fmin(fmax(phi, 0.0), 1.0);
     return P.eps * log((q + P.eps_s) / (1.0 - q + P.eps_s));
 }
+
+// The three velocity components as the momentum stencils take them (get<C>()
+// is component C): device pointers, or the workgroup-staged copies below.
+struct PVel {
+    const double *u, *v, *w;
+    template <int C> __device__ __forceinline__ const double *get() const { return C == 0 ? u : (C == 1 ? v : w); }
+};
+
+// A field staged in the workgroup's LDS (F: its place in the stage)
+template <int F> struct SField {};
+struct SVel {
+    template <int C> __device__ __forceinline__ SField<C> get() const { return {}; }
+};
+
+// Stage of an interior tile: u, v, w, phi (F = 0..3) over the tile and a
+// one-cell halo in x, y and z.
+constexpr int SLX = 64 + 2, SLY = 4 + 2, SPL = SLX * SLY, SFLD = 3 * SPL, SNF = 4;
+
+// Interior accessor whose staged fields come from LDS and all others from
+// memory (as Fast).  l0 is the thread's cell in the stage's middle plane.
+struct LdsAcc : Fast {
+    const double *st;
+    int l0;
+    __device__ __forceinline__ LdsAcc(const FGrid &G, int i, int j, int k, const double *stage, int l)
+        : Fast(G, i, j, k), st(stage), l0(l)
+    {
+    }
+    using Fast::cv;
+    using Fast::fv;
+    template <int F> __device__ __forceinline__ double cv(SField<F>, int a, int b, int c) const
+    {
+        return st[F * SFLD + l0 + c * SPL + b * SLX + a];
+    }
+    template <int C, int F> __device__ __forceinline__ double fv(SField<F> q, int a, int b, int c) const
+    {
+        return cv(q, a, b, c);
+    }
+};
 
 // ---------------------------------------------------------------- passes
 
@@ -243,8 +281,12 @@ __device__ __forceinline__ double flux_face(const X &x, const FParams &P, const 
                                             const double *nd)
 {
     if (x.template wall<D>(0)) return 0.0;
-    const double t = tanh(cface<D>(x, psi, 0) * P.ihe);
-    return P.gamma * (P.eps * cgrad<D>(x, phi, 0) - 0.25 * (1.0 - t * t) * cface<D>(x, nd, 0));
+    // (1 - tanh^2 z) / 4 = y / (1 + y)^2 with y = exp(-2 |z|): one
+    // exponential instead of a hyperbolic tangent, and no cancellation
+    // where tanh z is near +-1
+    const double y = exp(-2.0 * fabs(cface<D>(x, psi, 0) * P.ihe));
+    const double w = y / ((1.0 + y) * (1.0 + y));
+    return P.gamma * (P.eps * cgrad<D>(x, phi, 0) - w * cface<D>(x, nd, 0));
 }
 
 // normal component D on the +D face of the cell s steps along D (0 on walls)
@@ -283,8 +325,8 @@ __device__ __forceinline__ double acdi_cell(const X &x, const double *phi, const
 
 // mean of b0 + b1 q over the four cells around the edge touching the +A and
 // +B faces of the cell s steps along B
-template <int A, int B, class X>
-__device__ __forceinline__ double edge_mean(const X &x, const double *q, double b0, double b1, int s)
+template <int A, int B, class X, class Q>
+__device__ __forceinline__ double edge_mean(const X &x, Q q, double b0, double b1, int s)
 {
     constexpr int ai = A == 0, aj = A == 1, ak = A == 2, bi = B == 0, bj = B == 1, bk = B == 2;
     return 0.25 * ((b0 + b1 * x.cv(q, s * bi, s * bj, s * bk)) + (b0 + b1 * x.cv(q, ai + s * bi, aj + s * bj, ak + s * bk)) +
@@ -310,12 +352,13 @@ template <int C, int D, class X> __device__ __forceinline__ double a_at(const X 
 
 // Transverse (D != C) contribution to the advection and viscous terms of
 // component C on its +C face.
-template <int C, int D, class X>
-__device__ __forceinline__ void mom_transverse(const X &x, const FParams &P, const double *const vel[3],
-                                               const double *phi, double q0, double ihc, double &adv, double &visc)
+template <int C, int D, class X, class V, class PH>
+__device__ __forceinline__ void mom_transverse(const X &x, const FParams &P, const V &vel, PH phi, double q0,
+                                               double ihc, double &adv, double &visc)
 {
     constexpr int ci = C == 0, cj = C == 1, ck = C == 2, di = D == 0, dj = D == 1, dk = D == 2;
-    const double *q = vel[C], *p = vel[D];
+    const auto q = vel.template get<C>();
+    const auto p = vel.template get<D>();
     const double pu0 = x.template fv<D>(p, 0, 0, 0), pu1 = x.template fv<D>(p, ci, cj, ck);
     const double pd0 = x.template fv<D>(p, -di, -dj, -dk), pd1 = x.template fv<D>(p, ci - di, cj - dj, ck - dk);
     const double qu = x.template fv<C>(q, di, dj, dk), qd = x.template fv<C>(q, -di, -dj, -dk);
@@ -329,11 +372,11 @@ __device__ __forceinline__ void mom_transverse(const X &x, const FParams &P, con
     visc += (tu - td) * ihd;
 }
 
-template <int C, int D, class X>
-__device__ __forceinline__ double mom_reg(const X &x, const double *const vel[3], const double *const a[3])
+template <int C, int D, class X, class V>
+__device__ __forceinline__ double mom_reg(const X &x, const V &vel, const double *const a[3])
 {
     constexpr int di = D == 0, dj = D == 1, dk = D == 2;
-    const double *q = vel[C];
+    const auto q = vel.template get<C>();
     const double qp = x.template fv<C>(q, di, dj, dk), qm = x.template fv<C>(q, -di, -dj, -dk);
     double ih;
     if constexpr (C == D) ih = D < 2 ? 0.5 * x.ih(D) : x.izf2();
@@ -343,12 +386,12 @@ __device__ __forceinline__ double mom_reg(const X &x, const double *const vel[3]
 
 // Momentum right-hand side per unit mass of component C on the +C face of
 // the cell, which is not a wall face.
-template <int C, class X>
-__device__ __forceinline__ double mom_face(const X &x, const FParams &P, const double *phi, const double *kap,
-                                           const double *const vel[3], const double *const a[3])
+template <int C, class X, class V, class PH>
+__device__ __forceinline__ double mom_face(const X &x, const FParams &P, PH phi, const double *kap, const V &vel,
+                                           const double *const a[3])
 {
     constexpr int ci = C == 0, cj = C == 1, ck = C == 2;
-    const double *q = vel[C];
+    const auto q = vel.template get<C>();
     const double q0 = x.template fv<C>(q, 0, 0, 0);
     const double ihc = ihcen(x, C, 0);
     double adv, visc;

@@ -79,7 +79,8 @@ inline TilePlan tile_plan(const FGrid &G)
 
 struct FTile {
     int i, j, k;
-    bool act; // the thread's cell is in the grid
+    bool act;   // the thread's cell is in the grid
+    bool valid; // the workgroup has a tile (uniform over the workgroup)
 };
 
 // Order of the tiles within a box: chunks of TKC planes; within a chunk, x
@@ -99,8 +100,9 @@ __device__ __forceinline__ FTile btile(const FGrid &G, const TileBox &b)
     const long t = (long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
     FTile c;
     c.act = false;
+    c.valid = t < n;
     c.i = c.j = c.k = 0;
-    if (t >= n) return c;
+    if (!c.valid) return c;
     const long chunk = (long)b.nit * b.njt * TKC;
     const int kc = (int)(t / chunk);
     const int rem = (int)(t - (long)kc * chunk);
