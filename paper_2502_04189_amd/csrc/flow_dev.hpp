@@ -224,30 +224,42 @@ struct PVel {
     template <int C> __device__ __forceinline__ const double *get() const { return C == 0 ? u : (C == 1 ? v : w); }
 };
 
-// A field staged in the workgroup's LDS (F: its place in the stage)
+// pointer triple with get<C>() (the regularization flux components)
+using PVec = PVel;
+
+// A field staged for the workgroup (F: its place in the stage: 0..3 in LDS,
+// 4.. in registers, see LdsAcc)
 template <int F> struct SField {};
-struct SVel {
-    template <int C> __device__ __forceinline__ SField<C> get() const { return {}; }
+// staged u, v, w (the velocity) and a (the regularization flux) components
+template <int F0> struct SVec {
+    template <int C> __device__ __forceinline__ SField<F0 + C> get() const { return {}; }
 };
+using SVel = SVec<0>;
 
-// Stage of an interior tile: u, v, w, phi (F = 0..3) over the tile and a
-// one-cell halo in x, y and z.
-constexpr int SLX = 64 + 2, SLY = 4 + 2, SPL = SLX * SLY, SFLD = 3 * SPL, SNF = 4;
+// Stage of an interior tile: u, v, w, phi (F = 0..3) in LDS over the tile
+// and a one-cell halo in x, y and z; a_x, a_y, a_z and kappa (F = 4..7) in
+// registers, each thread its own 3 x 3 x 3 neighbourhood (the loads of the
+// values no stencil reads are dead and removed by the compiler).
+constexpr int SLX = 64 + 2, SLY = 4 + 2, SPL = SLX * SLY, SFLD = 3 * SPL, SNF = 4, SNR = 4;
 
-// Interior accessor whose staged fields come from LDS and all others from
-// memory (as Fast).  l0 is the thread's cell in the stage's middle plane.
+// Interior accessor whose staged fields come from the stage and all others
+// from memory (as Fast).  l0 is the thread's cell in the LDS stage's middle
+// plane; rg[f][n] the register stage, n = 9 (c + 1) + 3 (b + 1) + a + 1.
 struct LdsAcc : Fast {
     const double *st;
     int l0;
-    __device__ __forceinline__ LdsAcc(const FGrid &G, int i, int j, int k, const double *stage, int l)
-        : Fast(G, i, j, k), st(stage), l0(l)
+    const double (*rg)[27];
+    __device__ __forceinline__ LdsAcc(const FGrid &G, int i, int j, int k, const double *stage, int l,
+                                      const double (*regs)[27])
+        : Fast(G, i, j, k), st(stage), l0(l), rg(regs)
     {
     }
     using Fast::cv;
     using Fast::fv;
     template <int F> __device__ __forceinline__ double cv(SField<F>, int a, int b, int c) const
     {
-        return st[F * SFLD + l0 + c * SPL + b * SLX + a];
+        if constexpr (F < SNF) return st[F * SFLD + l0 + c * SPL + b * SLX + a];
+        else return rg[F - SNF][9 * (c + 1) + 3 * (b + 1) + a + 1];
     }
     template <int C, int F> __device__ __forceinline__ double fv(SField<F> q, int a, int b, int c) const
     {
@@ -337,15 +349,15 @@ __device__ __forceinline__ double edge_mean(const X &x, Q q, double b0, double b
 // component D of the regularization flux at the position of the +C face:
 // its own value when D == C, else the mean of the four D faces around
 // (wall faces carry none)
-template <int C, int D, class X> __device__ __forceinline__ double a_at(const X &x, const double *ad)
+template <int C, int D, class X, class Q> __device__ __forceinline__ double a_at(const X &x, Q ad)
 {
     if constexpr (C == D) {
-        return ad[x.idx(0, 0, 0)];
+        return x.cv(ad, 0, 0, 0);
     } else {
         constexpr int ci = C == 0, cj = C == 1, ck = C == 2, di = D == 0, dj = D == 1, dk = D == 2;
         double s = 0.0;
-        if (!x.template wall<D>(0)) s += ad[x.idx(0, 0, 0)] + ad[x.idx(ci, cj, ck)];
-        if (!x.template wall<D>(-1)) s += ad[x.idx(-di, -dj, -dk)] + ad[x.idx(ci - di, cj - dj, ck - dk)];
+        if (!x.template wall<D>(0)) s += x.cv(ad, 0, 0, 0) + x.cv(ad, ci, cj, ck);
+        if (!x.template wall<D>(-1)) s += x.cv(ad, -di, -dj, -dk) + x.cv(ad, ci - di, cj - dj, ck - dk);
         return 0.25 * s;
     }
 }
@@ -372,8 +384,8 @@ __device__ __forceinline__ void mom_transverse(const X &x, const FParams &P, con
     visc += (tu - td) * ihd;
 }
 
-template <int C, int D, class X, class V>
-__device__ __forceinline__ double mom_reg(const X &x, const V &vel, const double *const a[3])
+template <int C, int D, class X, class V, class AV>
+__device__ __forceinline__ double mom_reg(const X &x, const V &vel, const AV &a)
 {
     constexpr int di = D == 0, dj = D == 1, dk = D == 2;
     const auto q = vel.template get<C>();
@@ -381,14 +393,13 @@ __device__ __forceinline__ double mom_reg(const X &x, const V &vel, const double
     double ih;
     if constexpr (C == D) ih = D < 2 ? 0.5 * x.ih(D) : x.izf2();
     else ih = D < 2 ? 0.5 * x.ih(D) : x.izc2();
-    return a_at<C, D>(x, a[D]) * (qp - qm) * ih;
+    return a_at<C, D>(x, a.template get<D>()) * (qp - qm) * ih;
 }
 
 // Momentum right-hand side per unit mass of component C on the +C face of
 // the cell, which is not a wall face.
-template <int C, class X, class V, class PH>
-__device__ __forceinline__ double mom_face(const X &x, const FParams &P, PH phi, const double *kap, const V &vel,
-                                           const double *const a[3])
+template <int C, class X, class V, class PH, class KP, class AV>
+__device__ __forceinline__ double mom_face(const X &x, const FParams &P, PH phi, KP kap, const V &vel, const AV &a)
 {
     constexpr int ci = C == 0, cj = C == 1, ck = C == 2;
     const auto q = vel.template get<C>();

@@ -110,25 +110,31 @@ __global__ __launch_bounds__(FT) void k_flow_min(const unsigned long long *part,
     }
 }
 
-template <int C, class X, class V, class PH>
-__device__ __forceinline__ double mom_rhs(const FArgs &A, const X &x, const FTile &t, const V &vel, PH phi)
+template <int C, class X, class V, class PH, class KP, class AV>
+__device__ __forceinline__ double mom_rhs(const FArgs &A, const X &x, const FTile &t, const V &vel, PH phi, KP kap,
+                                          const AV &a)
 {
     const int s = C == 0 ? t.i : (C == 1 ? t.j : t.k);
-    return wallf(A.G, C, s) ? 0.0 : mom_face<C>(x, A.P, phi, A.kap, vel, A.a);
+    return wallf(A.G, C, s) ? 0.0 : mom_face<C>(x, A.P, phi, kap, vel, a);
 }
 
 // this substep's right-hand side m into hc (the previous one read first)
 // and, with u*, the predictor (0 on a wall face: the correction ignores it)
+// (old: the previous right-hand side, qv: the velocity component at c)
+template <int C>
+__device__ __forceinline__ void mom_put(const FArgs &A, const FTile &t, size_t c, double m, double old, double qv,
+                                        double *hc, double *qs)
+{
+    const int s = C == 0 ? t.i : (C == 1 ? t.j : t.k);
+    if (qs) qs[c] = wallf(A.G, C, s) ? 0.0 : qv + A.Dt * (A.ga * m + A.ze * old);
+    hc[c] = m;
+}
 template <int C>
 __device__ __forceinline__ void mom_store(const FArgs &A, const FTile &t, size_t c, double m, double *hc,
                                           const double *qc, double *qs)
 {
-    const int s = C == 0 ? t.i : (C == 1 ? t.j : t.k);
-    if (qs) {
-        const double old = A.first ? 0.0 : hc[c];
-        qs[c] = wallf(A.G, C, s) ? 0.0 : qc[c] + A.Dt * (A.ga * m + A.ze * old);
-    }
-    hc[c] = m;
+    const double old = qs && !A.first ? hc[c] : 0.0;
+    mom_put<C>(A, t, c, m, old, qs ? qc[c] : 0.0, hc, qs);
 }
 
 static_assert(SLX == FTI + 2 && SLY == FTJ + 2, "stage shape follows the tile shape");
@@ -181,31 +187,63 @@ template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_momentum(TileB
     const FTile t = btile(A.G, b);
     double m0 = 0.0, m1 = 0.0, m2 = 0.0;
     if constexpr (FAST) {
+        // hu, hv, hw are read and written in place: each thread reads and
+        // writes only its own cell
         __shared__ double st[SNF * SFLD];
         if (!t.valid) return; // uniform over the workgroup
         const int tx = threadIdx.x % FTI, ty = threadIdx.x / FTI;
         stage_fields(A, t.i - tx, t.j - ty, t.k, st);
+        // register stage: issued with the LDS stage's loads, before the
+        // barrier (threads past the grid read their clamped cell)
+        double rg[SNR][27];
+        {
+            const Fast f(A.G, t.act ? t.i : A.G.n[0] - 1, t.act ? t.j : A.G.n[1] - 1, t.k);
+            const double *src[SNR] = {A.a[0], A.a[1], A.a[2], A.kap};
+#pragma unroll
+            for (int q = 0; q < SNR; ++q)
+#pragma unroll
+                for (int n = 0; n < 27; ++n) rg[q][n] = src[q][f.idx(n % 3 - 1, (n / 3) % 3 - 1, n / 9 - 1)];
+        }
+        // the cell's previous right-hand sides and pressures, loaded with the
+        // stages
+        const size_t cc = at(A.G, t.act ? t.i : A.G.n[0] - 1, t.act ? t.j : A.G.n[1] - 1, t.k);
+        double old[3] = {0.0, 0.0, 0.0}, pp1 = 0.0, pp2 = 0.0;
+        if (!A.first) {
+            if (A.us[0]) old[0] = A.hu[cc];
+            if (A.us[1]) old[1] = A.hv[cc];
+            if (A.us[2]) old[2] = A.hw[cc];
+        }
+        if (A.pstar) {
+            pp1 = A.p1[cc];
+            pp2 = A.p2[cc];
+        }
         __syncthreads();
         if (!t.act) return;
-        const LdsAcc x(A.G, t.i, t.j, t.k, st, SPL + (ty + 1) * SLX + tx + 1);
+        const LdsAcc x(A.G, t.i, t.j, t.k, st, SPL + (ty + 1) * SLX + tx + 1, rg);
         const SVel vel;
-        m0 = mom_rhs<0>(A, x, t, vel, SField<3>{});
-        m1 = mom_rhs<1>(A, x, t, vel, SField<3>{});
-        m2 = mom_rhs<2>(A, x, t, vel, SField<3>{});
+        const SVec<4> av;
+        m0 = mom_rhs<0>(A, x, t, vel, SField<3>{}, SField<7>{}, av);
+        m1 = mom_rhs<1>(A, x, t, vel, SField<3>{}, SField<7>{}, av);
+        m2 = mom_rhs<2>(A, x, t, vel, SField<3>{}, SField<7>{}, av);
+        mom_put<0>(A, t, cc, m0, old[0], x.cv(SField<0>{}, 0, 0, 0), A.hu, A.us[0]);
+        mom_put<1>(A, t, cc, m1, old[1], x.cv(SField<1>{}, 0, 0, 0), A.hv, A.us[1]);
+        mom_put<2>(A, t, cc, m2, old[2], x.cv(SField<2>{}, 0, 0, 0), A.hw, A.us[2]);
+        if (A.pstar) A.pstar[cc] = (1.0 + A.r) * pp1 - A.r * pp2;
     } else {
         if (!t.act) return;
         const PVel vel{A.u, A.v, A.w};
+        const PVec av{A.a[0], A.a[1], A.a[2]};
         with_acc<false>(A.G, t, [&](const auto &x) {
-            m0 = mom_rhs<0>(A, x, t, vel, A.phi);
-            m1 = mom_rhs<1>(A, x, t, vel, A.phi);
-            m2 = mom_rhs<2>(A, x, t, vel, A.phi);
+            m0 = mom_rhs<0>(A, x, t, vel, A.phi, A.kap, av);
+            m1 = mom_rhs<1>(A, x, t, vel, A.phi, A.kap, av);
+            m2 = mom_rhs<2>(A, x, t, vel, A.phi, A.kap, av);
         });
+        const size_t c = at(A.G, t.i, t.j, t.k);
+        mom_store<0>(A, t, c, m0, A.hu, A.u, A.us[0]);
+        mom_store<1>(A, t, c, m1, A.hv, A.v, A.us[1]);
+        mom_store<2>(A, t, c, m2, A.hw, A.w, A.us[2]);
+        if (A.pstar) A.pstar[c] = (1.0 + A.r) * A.p1[c] - A.r * A.p2[c];
     }
-    const size_t c = at(A.G, t.i, t.j, t.k);
-    mom_store<0>(A, t, c, m0, A.hu, A.u, A.us[0]);
-    mom_store<1>(A, t, c, m1, A.hv, A.v, A.us[1]);
-    mom_store<2>(A, t, c, m2, A.hw, A.w, A.us[2]);
-    if (A.pstar) A.pstar[c] = (1.0 + A.r) * A.p1[c] - A.r * A.p2[c];
 }
 
 __global__ void k_flow_key_reset(unsigned long long *k) { *k = ~0ull; }
