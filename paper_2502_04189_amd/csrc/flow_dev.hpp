@@ -228,7 +228,7 @@ struct PVel {
 using PVec = PVel;
 
 // A field staged for the workgroup (F: its place in the stage: 0..3 in LDS,
-// 4.. in registers, see LdsAcc)
+// the others in registers, see StageAcc)
 template <int F> struct SField {};
 // staged u, v, w (the velocity) and a (the regularization flux) components
 template <int F0> struct SVec {
@@ -242,15 +242,16 @@ using SVel = SVec<0>;
 // values no stencil reads are dead and removed by the compiler).
 constexpr int SLX = 64 + 2, SLY = 4 + 2, SPL = SLX * SLY, SFLD = 3 * SPL, SNF = 4, SNR = 4;
 
-// Interior accessor whose staged fields come from the stage and all others
-// from memory (as Fast).  l0 is the thread's cell in the LDS stage's middle
-// plane; rg[f][n] the register stage, n = 9 (c + 1) + 3 (b + 1) + a + 1.
-struct LdsAcc : Fast {
+// Interior accessor whose staged fields come from the stages and all others
+// from memory (as Fast): fields F < NL from the LDS stage (l0: the thread's
+// cell in its middle plane), the others from the register stage rg[F - NL]
+// (rg[f][n]: offset (a, b, c) at n = 9 (c + 1) + 3 (b + 1) + a + 1).
+template <int NL> struct StageAcc : Fast {
     const double *st;
     int l0;
     const double (*rg)[27];
-    __device__ __forceinline__ LdsAcc(const FGrid &G, int i, int j, int k, const double *stage, int l,
-                                      const double (*regs)[27])
+    __device__ __forceinline__ StageAcc(const FGrid &G, int i, int j, int k, const double *stage, int l,
+                                        const double (*regs)[27])
         : Fast(G, i, j, k), st(stage), l0(l), rg(regs)
     {
     }
@@ -258,8 +259,8 @@ struct LdsAcc : Fast {
     using Fast::fv;
     template <int F> __device__ __forceinline__ double cv(SField<F>, int a, int b, int c) const
     {
-        if constexpr (F < SNF) return st[F * SFLD + l0 + c * SPL + b * SLX + a];
-        else return rg[F - SNF][9 * (c + 1) + 3 * (b + 1) + a + 1];
+        if constexpr (F < NL) return st[F * SFLD + l0 + c * SPL + b * SLX + a];
+        else return rg[F - NL][9 * (c + 1) + 3 * (b + 1) + a + 1];
     }
     template <int C, int F> __device__ __forceinline__ double fv(SField<F> q, int a, int b, int c) const
     {
@@ -270,8 +271,8 @@ struct LdsAcc : Fast {
 // ---------------------------------------------------------------- passes
 
 // the unit normal grad psi / |grad psi| at the cell, from stored psi
-template <class X>
-__device__ __forceinline__ void normal_cell(const X &x, const double *psi, double &nx, double &ny, double &nz)
+template <class X, class PS>
+__device__ __forceinline__ void normal_cell(const X &x, PS psi, double &nx, double &ny, double &nz)
 {
     const double gx = (x.cv(psi, 1, 0, 0) - x.cv(psi, -1, 0, 0)) * (0.5 * x.ih(0));
     const double gy = (x.cv(psi, 0, 1, 0) - x.cv(psi, 0, -1, 0)) * (0.5 * x.ih(1));
@@ -288,9 +289,8 @@ __device__ __forceinline__ void normal_cell(const X &x, const double *psi, doubl
 }
 
 // regularization flux on the +D face of the cell (0 on a wall face)
-template <int D, class X>
-__device__ __forceinline__ double flux_face(const X &x, const FParams &P, const double *phi, const double *psi,
-                                            const double *nd)
+template <int D, class X, class PH, class PS, class ND>
+__device__ __forceinline__ double flux_face(const X &x, const FParams &P, PH phi, PS psi, ND nd)
 {
     if (x.template wall<D>(0)) return 0.0;
     // (1 - tanh^2 z) / 4 = y / (1 + y)^2 with y = exp(-2 |z|): one
@@ -302,36 +302,44 @@ __device__ __forceinline__ double flux_face(const X &x, const FParams &P, const 
 }
 
 // normal component D on the +D face of the cell s steps along D (0 on walls)
-template <int D, class X> __device__ __forceinline__ double nface(const X &x, const double *nd, int s)
+template <int D, class X, class ND> __device__ __forceinline__ double nface(const X &x, ND nd, int s)
 {
     return x.template wall<D>(s) ? 0.0 : cface<D>(x, nd, s);
 }
 
 // curvature -div n_f at the cell
-template <class X> __device__ __forceinline__ double curvature_cell(const X &x, const double *const n[3])
+template <class X, class NV> __device__ __forceinline__ double curvature_cell(const X &x, const NV &n)
 {
-    const double sx = nface<0>(x, n[0], 0) - nface<0>(x, n[0], -1);
-    const double sy = nface<1>(x, n[1], 0) - nface<1>(x, n[1], -1);
-    const double sz = nface<2>(x, n[2], 0) - nface<2>(x, n[2], -1);
+    const auto n0 = n.template get<0>();
+    const auto n1 = n.template get<1>();
+    const auto n2 = n.template get<2>();
+    const double sx = nface<0>(x, n0, 0) - nface<0>(x, n0, -1);
+    const double sy = nface<1>(x, n1, 0) - nface<1>(x, n1, -1);
+    const double sz = nface<2>(x, n2, 0) - nface<2>(x, n2, -1);
     return -(sx * x.ih(0) + sy * x.ih(1) + sz * x.izf(0));
 }
 
 // net phase flux u phi_f - a through the +D face of the cell s steps along D
-template <int D, class X>
-__device__ __forceinline__ double jface(const X &x, const double *phi, const double *vel, const double *ad, int s)
+template <int D, class X, class PH, class VD, class AD>
+__device__ __forceinline__ double jface(const X &x, PH phi, VD vel, AD ad, int s)
 {
     if (x.template wall<D>(s)) return 0.0;
-    return x.template fv<D>(vel, DOFF(D, s)) * cface<D>(x, phi, s) - ad[x.idx(DOFF(D, s))];
+    return x.template fv<D>(vel, DOFF(D, s)) * cface<D>(x, phi, s) - x.cv(ad, DOFF(D, s));
 }
 
 // -div(u phi_f - a) at the cell
-template <class X>
-__device__ __forceinline__ double acdi_cell(const X &x, const double *phi, const double *const vel[3],
-                                            const double *const a[3])
+template <class X, class PH, class V, class AV>
+__device__ __forceinline__ double acdi_cell(const X &x, PH phi, const V &vel, const AV &a)
 {
-    double r = -(jface<0>(x, phi, vel[0], a[0], 0) - jface<0>(x, phi, vel[0], a[0], -1)) * x.ih(0);
-    r -= (jface<1>(x, phi, vel[1], a[1], 0) - jface<1>(x, phi, vel[1], a[1], -1)) * x.ih(1);
-    r -= (jface<2>(x, phi, vel[2], a[2], 0) - jface<2>(x, phi, vel[2], a[2], -1)) * x.izf(0);
+    const auto u = vel.template get<0>();
+    const auto v = vel.template get<1>();
+    const auto w = vel.template get<2>();
+    const auto a0 = a.template get<0>();
+    const auto a1 = a.template get<1>();
+    const auto a2 = a.template get<2>();
+    double r = -(jface<0>(x, phi, u, a0, 0) - jface<0>(x, phi, u, a0, -1)) * x.ih(0);
+    r -= (jface<1>(x, phi, v, a1, 0) - jface<1>(x, phi, v, a1, -1)) * x.ih(1);
+    r -= (jface<2>(x, phi, w, a2, 0) - jface<2>(x, phi, w, a2, -1)) * x.izf(0);
     return r;
 }
 

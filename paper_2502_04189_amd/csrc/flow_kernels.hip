@@ -10,6 +10,20 @@
 namespace pcx {
 namespace flow {
 
+// register stage of the listed fields: each thread's 3 x 3 x 3 neighbourhood
+// (loads whose values no stencil reads are removed by the compiler), all
+// issued before the first use; threads past the grid read a clamped cell
+template <int N>
+__device__ __forceinline__ void stage_regs(const FGrid &G, const FTile &t, const double *const (&src)[N],
+                                           double (&rg)[N][27])
+{
+    const Fast f(G, t.act ? t.i : G.n[0] - 1, t.act ? t.j : G.n[1] - 1, t.k);
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+#pragma unroll
+        for (int n = 0; n < 27; ++n) rg[q][n] = src[q][f.idx(n % 3 - 1, (n / 3) % 3 - 1, n / 9 - 1)];
+}
+
 // psi of every cell (one logarithm per cell), then the normals from it
 __global__ __launch_bounds__(FT) void k_flow_psi(FArgs A)
 {
@@ -23,7 +37,14 @@ template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_normals(TileBo
     const FTile t = btile(A.G, b);
     if (!t.act) return;
     double nx, ny, nz;
-    with_acc<FAST>(A.G, t, [&](const auto &x) { normal_cell(x, A.psi, nx, ny, nz); });
+    if constexpr (FAST) {
+        double rg[1][27];
+        const double *const src[1] = {A.psi};
+        stage_regs<1>(A.G, t, src, rg);
+        normal_cell(StageAcc<0>(A.G, t.i, t.j, t.k, nullptr, 0, rg), SField<0>{}, nx, ny, nz);
+    } else {
+        with_acc<false>(A.G, t, [&](const auto &x) { normal_cell(x, A.psi, nx, ny, nz); });
+    }
     const size_t c = at(A.G, t.i, t.j, t.k);
     A.n[0][c] = nx;
     A.n[1][c] = ny;
@@ -35,12 +56,26 @@ template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_flux(TileBox b
     const FTile t = btile(A.G, b);
     if (!t.act) return;
     const size_t c = at(A.G, t.i, t.j, t.k);
-    with_acc<FAST>(A.G, t, [&](const auto &x) {
-        A.a[0][c] = flux_face<0>(x, A.P, A.phi, A.psi, A.n[0]);
-        A.a[1][c] = flux_face<1>(x, A.P, A.phi, A.psi, A.n[1]);
-        A.a[2][c] = flux_face<2>(x, A.P, A.phi, A.psi, A.n[2]);
-        A.kap[c] = curvature_cell(x, A.n);
-    });
+    if constexpr (FAST) {
+        // phi, psi, n_x, n_y, n_z from registers, loaded up front
+        double rg[5][27];
+        const double *const src[5] = {A.phi, A.psi, A.n[0], A.n[1], A.n[2]};
+        stage_regs<5>(A.G, t, src, rg);
+        const StageAcc<0> x(A.G, t.i, t.j, t.k, nullptr, 0, rg);
+        const SVec<2> n;
+        A.a[0][c] = flux_face<0>(x, A.P, SField<0>{}, SField<1>{}, SField<2>{});
+        A.a[1][c] = flux_face<1>(x, A.P, SField<0>{}, SField<1>{}, SField<3>{});
+        A.a[2][c] = flux_face<2>(x, A.P, SField<0>{}, SField<1>{}, SField<4>{});
+        A.kap[c] = curvature_cell(x, n);
+    } else {
+        const PVec n{A.n[0], A.n[1], A.n[2]};
+        with_acc<false>(A.G, t, [&](const auto &x) {
+            A.a[0][c] = flux_face<0>(x, A.P, A.phi, A.psi, A.n[0]);
+            A.a[1][c] = flux_face<1>(x, A.P, A.phi, A.psi, A.n[1]);
+            A.a[2][c] = flux_face<2>(x, A.P, A.phi, A.psi, A.n[2]);
+            A.kap[c] = curvature_cell(x, n);
+        });
+    }
 }
 
 // order-preserving key of a double for atomicMin
@@ -61,9 +96,18 @@ template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_phase(TileBox 
     unsigned long long key = ~0ull;
     if (t.act) {
         const size_t c = at(A.G, t.i, t.j, t.k);
-        const double *vel[3] = {A.u, A.v, A.w};
         double r = 0.0;
-        with_acc<FAST>(A.G, t, [&](const auto &x) { r = acdi_cell(x, A.phi, vel, A.a); });
+        if constexpr (FAST) {
+            // phi, u, v, w, a_x, a_y, a_z from registers, loaded up front
+            double rg[7][27];
+            const double *const src[7] = {A.phi, A.u, A.v, A.w, A.a[0], A.a[1], A.a[2]};
+            stage_regs<7>(A.G, t, src, rg);
+            r = acdi_cell(StageAcc<0>(A.G, t.i, t.j, t.k, nullptr, 0, rg), SField<0>{}, SVec<1>{}, SVec<4>{});
+        } else {
+            const PVel vel{A.u, A.v, A.w};
+            const PVec av{A.a[0], A.a[1], A.a[2]};
+            with_acc<false>(A.G, t, [&](const auto &x) { r = acdi_cell(x, A.phi, vel, av); });
+        }
         if (A.phi_out) {
             const double old = A.first ? 0.0 : A.hphi[c];
             const double q = A.phi[c] + A.Dt * (A.ga * r + A.ze * old);
@@ -196,14 +240,8 @@ template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_momentum(TileB
         // register stage: issued with the LDS stage's loads, before the
         // barrier (threads past the grid read their clamped cell)
         double rg[SNR][27];
-        {
-            const Fast f(A.G, t.act ? t.i : A.G.n[0] - 1, t.act ? t.j : A.G.n[1] - 1, t.k);
-            const double *src[SNR] = {A.a[0], A.a[1], A.a[2], A.kap};
-#pragma unroll
-            for (int q = 0; q < SNR; ++q)
-#pragma unroll
-                for (int n = 0; n < 27; ++n) rg[q][n] = src[q][f.idx(n % 3 - 1, (n / 3) % 3 - 1, n / 9 - 1)];
-        }
+        const double *const rsrc[SNR] = {A.a[0], A.a[1], A.a[2], A.kap};
+        stage_regs<SNR>(A.G, t, rsrc, rg);
         // the cell's previous right-hand sides and pressures, loaded with the
         // stages
         const size_t cc = at(A.G, t.act ? t.i : A.G.n[0] - 1, t.act ? t.j : A.G.n[1] - 1, t.k);
@@ -219,7 +257,7 @@ template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_momentum(TileB
         }
         __syncthreads();
         if (!t.act) return;
-        const LdsAcc x(A.G, t.i, t.j, t.k, st, SPL + (ty + 1) * SLX + tx + 1, rg);
+        const StageAcc<SNF> x(A.G, t.i, t.j, t.k, st, SPL + (ty + 1) * SLX + tx + 1, rg);
         const SVel vel;
         const SVec<4> av;
         m0 = mom_rhs<0>(A, x, t, vel, SField<3>{}, SField<7>{}, av);
