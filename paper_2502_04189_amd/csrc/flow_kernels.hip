@@ -10,20 +10,6 @@
 namespace pcx {
 namespace flow {
 
-// register stage of the listed fields: each thread's 3 x 3 x 3 neighbourhood
-// (loads whose values no stencil reads are removed by the compiler), all
-// issued before the first use; threads past the grid read a clamped cell
-template <int N>
-__device__ __forceinline__ void stage_regs(const FGrid &G, const FTile &t, const double *const (&src)[N],
-                                           double (&rg)[N][27])
-{
-    const Fast f(G, t.act ? t.i : G.n[0] - 1, t.act ? t.j : G.n[1] - 1, t.k);
-#pragma unroll
-    for (int q = 0; q < N; ++q)
-#pragma unroll
-        for (int n = 0; n < 27; ++n) rg[q][n] = src[q][f.idx(n % 3 - 1, (n / 3) % 3 - 1, n / 9 - 1)];
-}
-
 // psi of every cell (one logarithm per cell), then the normals from it
 __global__ __launch_bounds__(FT) void k_flow_psi(FArgs A)
 {

@@ -126,6 +126,20 @@ template <bool FAST, class Body> __device__ __forceinline__ void with_acc(const 
     else body(Gen{G, t.i, t.j, t.k});
 }
 
+// register stage of the listed fields: each thread's 3 x 3 x 3 neighbourhood
+// (loads whose values no stencil reads are removed by the compiler), all
+// issued before the first use; threads past the grid read a clamped cell
+template <int N>
+__device__ __forceinline__ void stage_regs(const FGrid &G, const FTile &t, const double *const (&src)[N],
+                                           double (&rg)[N][27])
+{
+    const Fast f(G, t.act ? t.i : G.n[0] - 1, t.act ? t.j : G.n[1] - 1, t.k);
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+#pragma unroll
+        for (int n = 0; n < 27; ++n) rg[q][n] = src[q][f.idx(n % 3 - 1, (n / 3) % 3 - 1, n / 9 - 1)];
+}
+
 // Launches kernel<true> on the interior box and kernel<false> on the others;
 // every kernel takes (box, first slot, args...).
 #define FLOW_LAUNCH_PLAN(TP, KERNEL, STREAM, ...)                                                          \

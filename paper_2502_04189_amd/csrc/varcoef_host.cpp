@@ -84,6 +84,11 @@ extern "C" pcx_status pcx_varcoef_create(const pcx_grid *grid, const pcx_options
     V->ncell = (size_t)nx * ny * nz;
     V->tp = flow::tile_plan(G);
     const int nb = V->tp.nslots;
+    // the vector kernels run nb workgroups of one cell per thread
+    if ((size_t)nb * flow::FT < V->ncell) {
+        vc_free(V);
+        return fail(PCX_ERR_INVALID, "reduction slots do not cover the grid");
+    }
     const size_t nred = 2 * (size_t)nb + 2 * RED_WG + NSC;
     if (hipMalloc(&V->tab, t.size() * sizeof(double)) != hipSuccess ||
         hipMalloc(&V->ws, 4 * V->ncell * sizeof(double)) != hipSuccess ||

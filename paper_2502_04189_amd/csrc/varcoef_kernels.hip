@@ -54,14 +54,14 @@ __device__ __forceinline__ void put2(const VRed &R, int slot0, double a, double 
 }
 
 // (1/rho_f) G p on the +D face of the cell s steps along D; 0 on a wall face
-template <int D, class X> __device__ __forceinline__ double bflux(const X &x, const double *rho, const double *p, int s)
+template <int D, class X, class R, class P> __device__ __forceinline__ double bflux(const X &x, R rho, P p, int s)
 {
     if (x.template wall<D>(s)) return 0.0;
     return cgrad<D>(x, p, s) / cface<D>(x, rho, s);
 }
 
 // D((1/rho_f) G p) at the cell
-template <class X> __device__ __forceinline__ double vdiv_cell(const X &x, const double *rho, const double *p)
+template <class X, class R, class P> __device__ __forceinline__ double vdiv_cell(const X &x, R rho, P p)
 {
     return (bflux<0>(x, rho, p, 0) - bflux<0>(x, rho, p, -1)) * x.ih(0) +
            (bflux<1>(x, rho, p, 0) - bflux<1>(x, rho, p, -1)) * x.ih(1) +
@@ -86,7 +86,15 @@ __global__ __launch_bounds__(FT) void k_vc_apply(TileBox bx, int slot0, FGrid G,
     double a = 0.0;
     if (t.act) {
         double q = 0.0;
-        with_acc<FAST>(G, t, [&](const auto &x) { q = sign * vdiv_cell(x, rho, p); });
+        if constexpr (FAST) {
+            // rho and p from registers, loaded up front
+            double rg[2][27];
+            const double *const src[2] = {rho, p};
+            stage_regs<2>(G, t, src, rg);
+            q = sign * vdiv_cell(StageAcc<0>(G, t.i, t.j, t.k, nullptr, 0, rg), SField<0>{}, SField<1>{});
+        } else {
+            with_acc<false>(G, t, [&](const auto &x) { q = sign * vdiv_cell(x, rho, p); });
+        }
         const size_t c = at(G, t.i, t.j, t.k);
         out[c] = q;
         a = G.dzf[t.k] * p[c] * q;
@@ -110,97 +118,102 @@ __global__ __launch_bounds__(FT) void k_vc_rhs(TileBox bx, int slot0, FGrid G, c
     put2(R, slot0, a, 0.0);
 }
 
-// r -= m; partial sum of dzf r^2
-template <bool FAST>
-__global__ __launch_bounds__(FT) void k_vc_center(TileBox bx, int slot0, FGrid G, double *r, VRed R)
+// The vector kernels take the cells in memory order, one per thread, so a
+// workgroup streams 2 KB contiguous per field; workgroup b owns slot b of
+// the partials (the launch has nb workgroups, at least one per 256 cells;
+// the ones past the grid add zeros).
+struct LCell {
+    size_t c;
+    int k;
+    bool act;
+};
+__device__ __forceinline__ LCell lcell(const FGrid &G)
 {
-    const FTile t = btile(G, bx);
+    const unsigned plane = (unsigned)G.n[0] * (unsigned)G.n[1];
+    const unsigned n = plane * (unsigned)G.n[2]; // below 2^31 (grid validation)
+    const unsigned c = blockIdx.x * FT + threadIdx.x;
+    LCell l;
+    l.act = c < n;
+    l.c = c;
+    l.k = l.act ? (int)(c / plane) : 0;
+    return l;
+}
+
+// r -= m; partial sum of dzf r^2
+__global__ __launch_bounds__(FT) void k_vc_center(FGrid G, double *r, VRed R)
+{
+    const LCell l = lcell(G);
     double a = 0.0;
-    if (t.act) {
-        const size_t c = at(G, t.i, t.j, t.k);
-        const double q = r[c] - R.sc[S_M];
-        r[c] = q;
-        a = G.dzf[t.k] * q * q;
+    if (l.act) {
+        const double q = r[l.c] - R.sc[S_M];
+        r[l.c] = q;
+        a = G.dzf[l.k] * q * q;
     }
-    put2(R, slot0, a, 0.0);
+    put2(R, 0, a, 0.0);
 }
 
 // d = -rho0 z (z: the constant-coefficient solve of r); partial dzf r d
-template <bool FAST>
-__global__ __launch_bounds__(FT) void k_vc_dinit(TileBox bx, int slot0, FGrid G, const double *r, const double *z, double *d, double rho0,
+__global__ __launch_bounds__(FT) void k_vc_dinit(FGrid G, const double *r, const double *z, double *d, double rho0,
                                                  VRed R)
 {
-    const FTile t = btile(G, bx);
+    const LCell l = lcell(G);
     double a = 0.0;
-    if (t.act) {
-        const size_t c = at(G, t.i, t.j, t.k);
-        const double q = -rho0 * z[c];
-        d[c] = q;
-        a = G.dzf[t.k] * r[c] * q;
+    if (l.act) {
+        const double q = -rho0 * z[l.c];
+        d[l.c] = q;
+        a = G.dzf[l.k] * r[l.c] * q;
     }
-    put2(R, slot0, a, 0.0);
+    put2(R, 0, a, 0.0);
 }
 
 // p += alpha d; r -= alpha q; partial sums of dzf r and dzf r^2
-template <bool FAST>
-__global__ __launch_bounds__(FT) void k_vc_update(TileBox bx, int slot0, FGrid G, double *p, const double *d, double *r, const double *q,
+__global__ __launch_bounds__(FT) void k_vc_update(FGrid G, double *p, const double *d, double *r, const double *q,
                                                   VRed R)
 {
-    const FTile t = btile(G, bx);
+    const LCell l = lcell(G);
     double a = 0.0, b = 0.0;
-    if (t.act) {
-        const size_t c = at(G, t.i, t.j, t.k);
+    if (l.act) {
         const double al = R.sc[S_ALPHA];
-        p[c] += al * d[c];
-        const double rr = r[c] - al * q[c];
-        r[c] = rr;
-        const double wz = G.dzf[t.k];
+        p[l.c] += al * d[l.c];
+        const double rr = r[l.c] - al * q[l.c];
+        r[l.c] = rr;
+        const double wz = G.dzf[l.k];
         a = wz * rr;
         b = wz * rr * rr;
     }
-    put2(R, slot0, a, b);
+    put2(R, 0, a, b);
 }
 
 // r -= m (the mean the residual drifted by); partial dzf r (-rho0 z)
-template <bool FAST>
-__global__ __launch_bounds__(FT) void k_vc_dot(TileBox bx, int slot0, FGrid G, double *r, const double *z, double rho0, VRed R)
+__global__ __launch_bounds__(FT) void k_vc_dot(FGrid G, double *r, const double *z, double rho0, VRed R)
 {
-    const FTile t = btile(G, bx);
+    const LCell l = lcell(G);
     double a = 0.0;
-    if (t.act) {
-        const size_t c = at(G, t.i, t.j, t.k);
-        const double rr = r[c] - R.sc[S_M];
-        r[c] = rr;
-        a = G.dzf[t.k] * rr * (-rho0 * z[c]);
+    if (l.act) {
+        const double rr = r[l.c] - R.sc[S_M];
+        r[l.c] = rr;
+        a = G.dzf[l.k] * rr * (-rho0 * z[l.c]);
     }
-    put2(R, slot0, a, 0.0);
+    put2(R, 0, a, 0.0);
 }
 
 // d = -rho0 z + beta d
-template <bool FAST>
-__global__ __launch_bounds__(FT) void k_vc_dupd(TileBox bx, int slot0, FGrid G, const double *z, double *d, double rho0, VRed R)
+__global__ __launch_bounds__(FT) void k_vc_dupd(FGrid G, const double *z, double *d, double rho0, VRed R)
 {
-    const FTile t = btile(G, bx);
-    if (!t.act) return;
-    const size_t c = at(G, t.i, t.j, t.k);
-    d[c] = -rho0 * z[c] + R.sc[S_BETA] * d[c];
+    const LCell l = lcell(G);
+    if (l.act) d[l.c] = -rho0 * z[l.c] + R.sc[S_BETA] * d[l.c];
 }
 
-template <bool FAST>
-__global__ __launch_bounds__(FT) void k_vc_pmean(TileBox bx, int slot0, FGrid G, const double *p, VRed R)
+__global__ __launch_bounds__(FT) void k_vc_pmean(FGrid G, const double *p, VRed R)
 {
-    const FTile t = btile(G, bx);
-    double a = 0.0;
-    if (t.act) a = G.dzf[t.k] * p[at(G, t.i, t.j, t.k)];
-    put2(R, slot0, a, 0.0);
+    const LCell l = lcell(G);
+    put2(R, 0, l.act ? G.dzf[l.k] * p[l.c] : 0.0, 0.0);
 }
 
-template <bool FAST>
-__global__ __launch_bounds__(FT) void k_vc_pshift(TileBox bx, int slot0, FGrid G, double *p, VRed R)
+__global__ __launch_bounds__(FT) void k_vc_pshift(FGrid G, double *p, VRed R)
 {
-    const FTile t = btile(G, bx);
-    if (!t.act) return;
-    p[at(G, t.i, t.j, t.k)] -= R.sc[S_PMEAN];
+    const LCell l = lcell(G);
+    if (l.act) p[l.c] -= R.sc[S_PMEAN];
 }
 
 // u_out = u - dt (1/rho_f) G p on the +face of each direction, 0 on a wall face
@@ -292,31 +305,37 @@ hipError_t launch_rhs(const FGrid &G, const TilePlan &tp, const double *u, const
 }
 hipError_t launch_center(const FGrid &G, const TilePlan &tp, double *r, const VRed &R, hipStream_t s)
 {
-    return FLOW_LAUNCH_PLAN(tp, k_vc_center, s, G, r, R);
+    hipLaunchKernelGGL(k_vc_center, dim3((unsigned)R.nb), dim3(FT), 0, s, G, r, R);
+    return hipGetLastError();
 }
 hipError_t launch_dinit(const FGrid &G, const TilePlan &tp, const double *r, const double *z, double *d, double rho0,
                         const VRed &R, hipStream_t s)
 {
-    return FLOW_LAUNCH_PLAN(tp, k_vc_dinit, s, G, r, z, d, rho0, R);
+    hipLaunchKernelGGL(k_vc_dinit, dim3((unsigned)R.nb), dim3(FT), 0, s, G, r, z, d, rho0, R);
+    return hipGetLastError();
 }
 hipError_t launch_update(const FGrid &G, const TilePlan &tp, double *p, const double *d, double *r, const double *q,
                          const VRed &R, hipStream_t s)
 {
-    return FLOW_LAUNCH_PLAN(tp, k_vc_update, s, G, p, d, r, q, R);
+    hipLaunchKernelGGL(k_vc_update, dim3((unsigned)R.nb), dim3(FT), 0, s, G, p, d, r, q, R);
+    return hipGetLastError();
 }
 hipError_t launch_dot(const FGrid &G, const TilePlan &tp, double *r, const double *z, double rho0, const VRed &R,
                       hipStream_t s)
 {
-    return FLOW_LAUNCH_PLAN(tp, k_vc_dot, s, G, r, z, rho0, R);
+    hipLaunchKernelGGL(k_vc_dot, dim3((unsigned)R.nb), dim3(FT), 0, s, G, r, z, rho0, R);
+    return hipGetLastError();
 }
 hipError_t launch_dupd(const FGrid &G, const TilePlan &tp, const double *z, double *d, double rho0, const VRed &R,
                        hipStream_t s)
 {
-    return FLOW_LAUNCH_PLAN(tp, k_vc_dupd, s, G, z, d, rho0, R);
+    hipLaunchKernelGGL(k_vc_dupd, dim3((unsigned)R.nb), dim3(FT), 0, s, G, z, d, rho0, R);
+    return hipGetLastError();
 }
 hipError_t launch_pmean(const FGrid &G, const TilePlan &tp, const double *p, const VRed &R, hipStream_t s)
 {
-    return FLOW_LAUNCH_PLAN(tp, k_vc_pmean, s, G, p, R);
+    hipLaunchKernelGGL(k_vc_pmean, dim3((unsigned)R.nb), dim3(FT), 0, s, G, p, R);
+    return hipGetLastError();
 }
 hipError_t launch_correct(const FGrid &G, const TilePlan &tp, const double *rho, const double *p, const double *u,
                           const double *v, const double *w, double dt, double *uo, double *vo, double *wo,
@@ -326,7 +345,8 @@ hipError_t launch_correct(const FGrid &G, const TilePlan &tp, const double *rho,
 }
 hipError_t launch_pshift(const FGrid &G, const TilePlan &tp, double *p, const VRed &R, hipStream_t s)
 {
-    return FLOW_LAUNCH_PLAN(tp, k_vc_pshift, s, G, p, R);
+    hipLaunchKernelGGL(k_vc_pshift, dim3((unsigned)R.nb), dim3(FT), 0, s, G, p, R);
+    return hipGetLastError();
 }
 hipError_t red_scal(const VRed &R, int mode, hipStream_t s)
 {
