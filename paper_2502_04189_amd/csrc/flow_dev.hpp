@@ -25,8 +25,13 @@ struct FGrid {
     int n[3];          // nx, ny, nz
     int per[3];        // 1 periodic, 0 wall
     double h[2];       // dx, dy
+    double ih[2];      // 1/dx, 1/dy
     const double *dzf; // nz cell widths
     const double *dzc; // centre k -> k+1 (periodic wrap at nz-1)
+    // per plane k, 6 reciprocals (the z metrics the interior accessor uses):
+    // 1/dzf(k), 1/dzf(k+1), 1/dzc(k-1), 1/dzc(k), 1/(dzc(k) + dzc(k-1)),
+    // 1/(dzf(k) + dzf(k+1)), with dzf(.), dzc(.) as dzf_at, dzc_at below
+    const double *rz;
 };
 
 struct FParams {
@@ -155,14 +160,17 @@ struct Fast {
         zc_0 = dzc_at(G, k);
         hx = G.h[0];
         hy = G.h[1];
-        ihx = 1.0 / hx;
-        ihy = 1.0 / hy;
-        izf_0 = 1.0 / zf_0;
-        izf_p = 1.0 / zf_p;
-        izc_m = 1.0 / zc_m;
-        izc_0 = 1.0 / zc_0;
-        izc2_ = 1.0 / (zc_0 + zc_m);
-        izf2_ = 1.0 / (zf_0 + zf_p);
+        // reciprocals from the host tables (one scalar load each: k is
+        // uniform over a workgroup) instead of eight divisions per thread
+        ihx = G.ih[0];
+        ihy = G.ih[1];
+        const double *r = G.rz + 6 * (size_t)k;
+        izf_0 = r[0];
+        izf_p = r[1];
+        izc_m = r[2];
+        izc_0 = r[3];
+        izc2_ = r[4];
+        izf2_ = r[5];
     }
     __device__ __forceinline__ long off(int a, int b, int c) const
     {

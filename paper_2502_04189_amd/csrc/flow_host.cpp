@@ -25,7 +25,7 @@ struct pcx_flow_s {
     TilePlan tp;
     FParams P;
     pcx_plan plan = nullptr;
-    double *tab = nullptr;           // dzf, dzc
+    double *tab = nullptr;           // z metric tables (metric_tables)
     double *ws = nullptr;            // NWS fields
     unsigned long long *key = nullptr;
     unsigned long long *part = nullptr; // per-workgroup minimum keys
@@ -72,10 +72,7 @@ extern "C" pcx_status pcx_flow_create(const pcx_grid *grid, const pcx_flow_param
         return st;
     }
     const int nx = grid->nx, ny = grid->ny, nz = grid->nz;
-    std::vector<double> t(2 * (size_t)nz);
-    for (int k = 0; k < nz; ++k) t[k] = F->zf[k + 1] - F->zf[k];
-    for (int k = 0; k < nz - 1; ++k) t[nz + k] = 0.5 * (t[k] + t[k + 1]);
-    t[2 * nz - 1] = 0.5 * (t[nz - 1] + t[0]);
+    const std::vector<double> t = metric_tables(F->zf.data(), nz, grid->bc_z == PCX_BC_PERIODIC);
     F->ncell = (size_t)nx * ny * nz;
     if (hipMalloc(&F->tab, t.size() * sizeof(double)) != hipSuccess ||
         hipMalloc(&F->ws, NWS * F->ncell * sizeof(double)) != hipSuccess ||
@@ -94,8 +91,11 @@ extern "C" pcx_status pcx_flow_create(const pcx_grid *grid, const pcx_flow_param
     G.per[2] = grid->bc_z == PCX_BC_PERIODIC;
     G.h[0] = grid->lx / nx;
     G.h[1] = grid->ly / ny;
+    G.ih[0] = 1.0 / G.h[0];
+    G.ih[1] = 1.0 / G.h[1];
     G.dzf = F->tab;
     G.dzc = F->tab + nz;
+    G.rz = F->tab + 2 * nz;
     F->P = FParams{q.rho1, q.rho2, q.mu1, q.mu2, q.sigma, {q.gx, q.gy, q.gz}, q.gamma, q.eps, q.eps_s, 0.5 / q.eps};
     F->tp = tile_plan(G);
     if (hipMalloc(&F->part, (size_t)F->tp.nslots * sizeof(unsigned long long)) != hipSuccess) {

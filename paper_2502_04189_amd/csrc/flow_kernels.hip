@@ -172,7 +172,8 @@ static_assert(SLX == FTI + 2 && SLY == FTJ + 2, "stage shape follows the tile sh
 // Copies u, v, w and phi over the tile of (i0, j0, k) and its one-cell halo
 // into the stage: every load of a thread is issued before its first LDS
 // store.  Interior tiles only: a halo index leaves the grid only across a
-// periodic direction, where it wraps.
+// periodic direction, where it wraps (by one period: the tile plan has no
+// interior box when a periodic direction is shorter than the tile and halo).
 __device__ __forceinline__ void stage_fields(const FArgs &A, int i0, int j0, int k, double *st)
 {
     constexpr int NR = (SFLD + FT - 1) / FT;
@@ -186,9 +187,9 @@ __device__ __forceinline__ void stage_fields(const FArgs &A, int i0, int j0, int
         const int kk = e / SPL, r = e - kk * SPL;
         const int jj = r / SLX, ii = r - jj * SLX;
         int gi = i0 - 1 + ii, gj = j0 - 1 + jj, gk = k - 1 + kk;
-        gi = gi < 0 ? gi + nx : (gi >= nx ? gi % nx : gi);
-        gj = gj < 0 ? gj + ny : (gj >= ny ? gj % ny : gj);
-        gk = gk < 0 ? gk + nz : (gk >= nz ? gk % nz : gk);
+        gi = gi < 0 ? gi + nx : (gi >= nx ? gi - nx : gi);
+        gj = gj < 0 ? gj + ny : (gj >= ny ? gj - ny : gj);
+        gk = gk < 0 ? gk + nz : (gk >= nz ? gk - nz : gk);
         g[q] = ((size_t)gk * ny + gj) * nx + gi;
     }
     double v[SNF][NR];

@@ -13,6 +13,8 @@
 // box's tiles in the order below.
 #pragma once
 
+#include <vector>
+
 #include "flow_dev.hpp"
 
 namespace pcx {
@@ -45,6 +47,35 @@ struct TilePlan {
     int nslots;
 };
 
+// Host tables of a grid's z metrics: dzf (nz), dzc (nz, the periodic wrap
+// at nz-1), then the 6 nz reciprocals of FGrid::rz, each computed in the
+// order and from the values the device accessors would use.
+inline std::vector<double> metric_tables(const double *zf, int nz, bool zper)
+{
+    std::vector<double> t(8 * (size_t)nz);
+    double *dzf = t.data(), *dzc = dzf + nz, *rz = dzc + nz;
+    for (int k = 0; k < nz; ++k) dzf[k] = zf[k + 1] - zf[k];
+    for (int k = 0; k < nz - 1; ++k) dzc[k] = 0.5 * (dzf[k] + dzf[k + 1]);
+    dzc[nz - 1] = 0.5 * (dzf[nz - 1] + dzf[0]);
+    auto fat = [&](int k) { return k < 0 ? dzf[zper ? nz - 1 : 0] : (k >= nz ? dzf[zper ? 0 : nz - 1] : dzf[k]); };
+    auto cat = [&](int k) {
+        if (k < 0) return zper ? dzc[nz - 1] : dzf[0];
+        if (k >= nz - 1) return zper ? dzc[nz - 1] : dzf[nz - 1];
+        return dzc[k];
+    };
+    for (int k = 0; k < nz; ++k) {
+        double *r = rz + 6 * (size_t)k;
+        const double f0 = fat(k), fp = fat(k + 1), cm = cat(k - 1), c0 = cat(k);
+        r[0] = 1.0 / f0;
+        r[1] = 1.0 / fp;
+        r[2] = 1.0 / cm;
+        r[3] = 1.0 / c0;
+        r[4] = 1.0 / (c0 + cm);
+        r[5] = 1.0 / (f0 + fp);
+    }
+    return t;
+}
+
 // Tile boxes of a grid.  The stencils reach one cell (and one face) beyond
 // their cell, so a wall direction's interior tiles lie within [1, n-3]: x
 // tiles it >= 1 with (it + 1) FTI <= nx - 2, likewise y, planes 1 .. nz-3.
@@ -63,7 +94,9 @@ inline TilePlan tile_plan(const FGrid &G)
         p.nslots += box_grid(b);
         ++p.n;
     };
-    if (it1 <= it0 || jt1 <= jt0 || k1 <= k0) {
+    // the interior kernels' stages wrap a halo index by at most one period
+    const bool small = (G.per[0] && G.n[0] < FTI + 2) || (G.per[1] && G.n[1] < FTJ + 2) || (G.per[2] && nz < 3);
+    if (small || it1 <= it0 || jt1 <= jt0 || k1 <= k0) {
         add(TileBox{0, 0, 0, ti, tj, nz}, false);
         return p;
     }

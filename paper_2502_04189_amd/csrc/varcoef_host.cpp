@@ -21,7 +21,7 @@ struct pcx_varcoef_s {
     flow::FGrid G;
     flow::TilePlan tp;
     pcx_plan plan = nullptr;
-    double *tab = nullptr; // dzf, dzc
+    double *tab = nullptr; // z metric tables (metric_tables)
     double *ws = nullptr;  // r, z, d, q
     double *red = nullptr; // partials, first level, scalars
     size_t ncell = 0;
@@ -66,14 +66,9 @@ extern "C" pcx_status pcx_varcoef_create(const pcx_grid *grid, const pcx_options
         vc_free(V);
         return st;
     }
-    std::vector<double> t(2 * (size_t)nz);
+    const std::vector<double> t = flow::metric_tables(V->zf.data(), nz, grid->bc_z == PCX_BC_PERIODIC);
     double zsum = 0.0;
-    for (int k = 0; k < nz; ++k) {
-        t[k] = V->zf[k + 1] - V->zf[k];
-        zsum += t[k];
-    }
-    for (int k = 0; k < nz - 1; ++k) t[nz + k] = 0.5 * (t[k] + t[k + 1]);
-    t[2 * nz - 1] = 0.5 * (t[nz - 1] + t[0]);
+    for (int k = 0; k < nz; ++k) zsum += t[k];
     flow::FGrid &G = V->G;
     G.n[0] = nx; G.n[1] = ny; G.n[2] = nz;
     G.per[0] = grid->bc_x == PCX_BC_PERIODIC;
@@ -81,6 +76,8 @@ extern "C" pcx_status pcx_varcoef_create(const pcx_grid *grid, const pcx_options
     G.per[2] = grid->bc_z == PCX_BC_PERIODIC;
     G.h[0] = grid->lx / nx;
     G.h[1] = grid->ly / ny;
+    G.ih[0] = 1.0 / G.h[0];
+    G.ih[1] = 1.0 / G.h[1];
     V->ncell = (size_t)nx * ny * nz;
     V->tp = flow::tile_plan(G);
     const int nb = V->tp.nslots;
@@ -98,6 +95,7 @@ extern "C" pcx_status pcx_varcoef_create(const pcx_grid *grid, const pcx_options
     }
     G.dzf = V->tab;
     G.dzc = V->tab + nz;
+    G.rz = V->tab + 2 * nz;
     V->r = V->ws;
     V->z = V->ws + V->ncell;
     V->d = V->ws + 2 * V->ncell;
