@@ -125,6 +125,21 @@ struct FTile {
 // and every z neighbour was fetched again).
 constexpr int TKC = 16;
 
+// tile t (0 <= t < box_tiles(b)) of a box in the order above
+__host__ __device__ inline void box_tile(const TileBox &b, long t, int &it, int &jt, int &k)
+{
+    const long chunk = (long)b.nit * b.njt * TKC;
+    const int kc = (int)(t / chunk);
+    const int rem = (int)(t - (long)kc * chunk);
+    const int kb = kc * TKC;
+    const int nkc = b.nk - kb < TKC ? b.nk - kb : TKC; // planes in this chunk
+    const int ii = rem % b.nit;
+    const int q = rem / b.nit;
+    it = b.it0 + ii;
+    jt = b.jt0 + q / nkc;
+    k = b.k0 + kb + q % nkc;
+}
+
 // the thread's cell in the launch over box b (act false past the box or the grid)
 __device__ __forceinline__ FTile btile(const FGrid &G, const TileBox &b)
 {
@@ -136,17 +151,10 @@ __device__ __forceinline__ FTile btile(const FGrid &G, const TileBox &b)
     c.valid = t < n;
     c.i = c.j = c.k = 0;
     if (!c.valid) return c;
-    const long chunk = (long)b.nit * b.njt * TKC;
-    const int kc = (int)(t / chunk);
-    const int rem = (int)(t - (long)kc * chunk);
-    const int kb = kc * TKC;
-    const int nkc = b.nk - kb < TKC ? b.nk - kb : TKC; // planes in this chunk
-    const int ii = rem % b.nit;
-    const int q = rem / b.nit;
-    const int kk = q % nkc, jj = q / nkc;
-    c.i = (b.it0 + ii) * FTI + (threadIdx.x % FTI);
-    c.j = (b.jt0 + jj) * FTJ + (threadIdx.x / FTI);
-    c.k = b.k0 + kb + kk;
+    int it, jt;
+    box_tile(b, t, it, jt, c.k);
+    c.i = it * FTI + (threadIdx.x % FTI);
+    c.j = jt * FTJ + (threadIdx.x / FTI);
     c.act = c.i < G.n[0] && c.j < G.n[1];
     return c;
 }
