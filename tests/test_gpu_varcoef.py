@@ -178,3 +178,35 @@ def test_rejections(pcx):
     gs = W.GridSpec(16, 16, 8, 1.0, 1.0, W.zf_uniform(8, 1.0), 2, 0, 1)
     with pytest.raises(pcx.PcxError):
         pcx.VarCoef(gs)
+
+
+def test_projection_at_512_properties(pcx, orc):
+    """The benchmark's 512^3 inputs, as bench.py runs the projection (tol
+    1e-10): converged; divergence of the result within the stop test's bound
+    in the max norm (max|D u_out| / max|D u*| <= tol sqrt(sum V / min V):
+    D u_out = dt r and the volume-weighted 2-norm of r is within tol of that
+    of D u*/dt); the split step given this pressure as p* agrees with it to
+    the same order (its difference is the projection of that residual)."""
+    import torch
+    c = W.config3()
+    gs = c.grid
+    dev = [to_dev(a) for a in c.fields()]  # rho, p*, u, v, w
+    vc = pcx.VarCoef(gs)
+    tol = 1e-10
+    uo, vo, wo, p, it, rr, st = vc.project(c.dt, c.rho0, dev[0], *dev[2:], tol=tol, maxit=4000)
+    vc.close()
+    plan = pcx.Plan(gs, "fp64")
+    su, sv, sw, sp, _ = plan.step(c.dt, c.rho0, dev[0], p, *dev[2:])
+    plan.close()
+    split = max(float((a - b).abs().max() / b.abs().max()) for a, b in zip((su, sv, sw), (uo, vo, wo)))
+    g = orc.Grid.from_workload(gs)
+    d0 = np.abs(orc.div(g, c.u, c.v, c.w)).max()
+    d1 = np.abs(orc.div(g, uo.cpu().numpy(), vo.cpu().numpy(), wo.cpu().numpy())).max()
+    dz = np.diff(gs.zf)
+    factor = float(np.sqrt(gs.nx * gs.ny * dz.sum() / dz.min()))
+    _say(f"512^3 projection: {it} iterations, residual {rr:.2e}, max|D u| {d1 / d0:.2e} of the input's "
+         f"(bound {tol * factor:.1e}), split step with this p* {split:.2e}")
+    torch.cuda.synchronize()
+    assert st == pcx.PCX_OK and rr <= tol
+    assert d1 <= tol * factor * d0
+    assert split <= tol * factor
