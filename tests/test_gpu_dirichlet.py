@@ -91,3 +91,35 @@ def test_dirichlet_plans_reject_the_step_and_refined_solve(pcx):
         rplan.poisson_solve(z[1])
     assert e.value.status == pcx.PCX_ERR_UNSUPPORTED
     rplan.close()
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 1), (2, 2, 1)], ids=["periodic_xy", "dirichlet_xy"])
+def test_solve_at_512_residual(pcx, orc, bc):
+    """pcx_poisson_solve on the benchmark's 512^3 grid (tanh z, walls in z)
+    as bench.py times it, with its x/y boundaries and with Dirichlet x and
+    y: the oracle's operator applied to the GPU's p gives back f (minus its
+    volume mean where the problem is singular).  A direct transform solve is
+    backward stable: the residual is bounded by a modest multiple of
+    eps ||L||inf ||p||inf (||L||inf: the largest absolute row sum of the
+    7-point operator); 64 allows for the log2 n stages of each transform."""
+    import torch
+    gs0 = W.config3().grid
+    gs = W.GridSpec(gs0.nx, gs0.ny, gs0.nz, gs0.lx, gs0.ly, gs0.zf, *bc)
+    f = np.random.default_rng(512).normal(size=gs.shape)
+    plan = pcx.Plan(gs, "fp64")
+    p = plan.poisson_solve(to_dev(f)).cpu().numpy()
+    plan.close()
+    torch.cuda.synchronize()
+    g = orc.Grid.from_workload(gs)
+    lp = orc.apply_L_bc(g, p)
+    want = f if 2 in bc else f - orc.volume_mean(g, f)
+    dzf = np.diff(gs.zf)
+    dzc = 0.5 * (dzf[:-1] + dzf[1:])
+    lo = np.concatenate([[dzf[0]], dzc])
+    hi = np.concatenate([dzc, [dzf[-1]]])
+    linf = 4.0 / gs.dx ** 2 + 4.0 / gs.dy ** 2 + float(np.max(2.0 * (1.0 / lo + 1.0 / hi) / dzf))
+    r = float(np.abs(lp - want).max())
+    bound = 64 * np.finfo(np.float64).eps * linf * float(np.abs(p).max())
+    _say(f"512^3 solve bc {bc}: max|L p - f| = {r:.2e} ({r / np.abs(f).max():.2e} of max|f|), "
+         f"{r / bound * 64:.1f} eps ||L|| ||p||")
+    assert r <= bound
