@@ -226,8 +226,6 @@ pcx_status autotune_class(const pcx_grid &g, int prec, hipStream_t s, TuneParams
         return bestt;
     };
     const long cap = 96 * 1024;
-    TuneParams tp0;
-    RadixChoice rc0;
     Shapes base;
     choose_shapes(g, prec, nullptr, base, false);
     best.tj = base.tj; best.tk = base.tk; best.zg = base.zg;
