@@ -440,7 +440,7 @@ def flow_dt(gs, prm, umax):
     return min(0.5 * min(hx, hy, hz) / umax, 1.25 / ((prm["gamma"] * prm["eps"] + nu) * lam))
 
 
-def run_flow(case, steps, warmup):
+def run_flow(case, steps, warmup, split_check=True):
     """Whole Runge-Kutta steps (three substeps: phase field, momentum
     predictor, pressure-correction step) of the bubble channel."""
     import torch
@@ -481,13 +481,54 @@ def run_flow(case, steps, warmup):
     ms = e0.elapsed_time(e1) / steps
     phi = fin[0]
     ok = bool(torch.isfinite(fin[1]).all()) and float(phi.min()) > -1e-6 and float(phi.max()) < 1 + 1e-6
-    F.close()
     log(f"rk3 steps: {ms:.3f} ms per step of three substeps, phi in [{float(phi.min()):.3e}, {float(phi.max()):.6f}]")
+    split = None
+    if split_check:
+        # the splitting error on a settled state: the run starts from zero
+        # pressures, and an extrapolated p* is only as good as the pressures
+        # of the last substeps
+        fin = step_all(30)
+        split = splitting_error(F, gs, Dt, fin, pres, dtprev)
+        split["after_rk3_steps"] = warmup + steps + 30
+    F.close()
     cells = gs.cells
-    return {"ms_per_rk3_step": round(ms, 4), "ms_per_substep": round(ms / 3, 4),
-            "value": round(cells / (ms * 1e-3) / 1e6, 1), "unit": "Mpts/s (whole RK3 steps)",
-            "steps": steps, "Dt": Dt, "finite_and_bounded": ok,
-            "substep_kernel_bytes_per_cell": FLOW_BYTES}
+    out = {"ms_per_rk3_step": round(ms, 4), "ms_per_substep": round(ms / 3, 4),
+           "value": round(cells / (ms * 1e-3) / 1e6, 1), "unit": "Mpts/s (whole RK3 steps)",
+           "steps": steps, "Dt": Dt, "finite_and_bounded": ok,
+           "substep_kernel_bytes_per_cell": FLOW_BYTES}
+    if split is not None:
+        out["splitting_error_vs_varcoef"] = split
+    return out
+
+
+def splitting_error(F, gs, Dt, state, pres, dtprev, tol=1e-11):
+    """The splitting error on the flow's own state: the next substep's
+    predictor (pcx_flow_predict: u*, the new density, p* extrapolated from
+    the last two pressures) corrected by the split step and by the
+    variable-coefficient projection (tol 1e-11), and by the split step with
+    p* = 0 (no extrapolation) for comparison; max-norm differences relative
+    to the projection's velocity and pressure."""
+    import torch
+    from paper_2502_04189_amd import pcx
+    r = (8 / 15) * Dt / dtprev
+    h = [torch.zeros_like(state[0]) for _ in range(4)]
+    phi_o = torch.empty_like(state[0])
+    us, vs, ws, rho, ps, rho0, dt = F.predict(1, Dt, *state[:4], pres[0], pres[1], r, h, phi_o)
+    vc = pcx.VarCoef(gs)
+    uv, vv, wv, pv, it, rr, st = vc.project(dt, rho0, rho, us, vs, ws, tol=tol, maxit=4000)
+    vc.close()
+    plan = pcx.Plan(gs, "fp64")
+    out = {"varcoef_iterations": it, "varcoef_rel_residual": rr, "tol": tol}
+    for name, pst in (("pstar_extrapolated", ps), ("pstar_zero", torch.zeros_like(ps))):
+        su, sv, sw, sp, _ = plan.step(dt, rho0, rho, pst, us, vs, ws, report=False)
+        torch.cuda.synchronize()
+        eu = max(float((a - b).abs().max() / b.abs().max()) for a, b in zip((su, sv, sw), (uv, vv, wv)))
+        ep = float((sp - pv).abs().max() / pv.abs().max())
+        out[name] = {"u_rel": eu, "p_rel": ep}
+        del su, sv, sw, sp
+    plan.close()
+    log(f"splitting error on the flow state: {out}")
+    return out
 
 
 def main():
@@ -551,7 +592,7 @@ def main():
     if args.prof_flow:
         del dev, outs
         torch.cuda.empty_cache()
-        run_flow(case, args.steps, args.warmup)
+        run_flow(case, args.steps, args.warmup, split_check=False)
         log("prof mode done")
         return
 

@@ -69,13 +69,28 @@ pcx_status pcx_flow_momentum_rhs(pcx_flow flow, const double *phi, const double 
  * pressures p1, p2 of the two previous substeps and their ratio r.
  * hphi, hu, hv, hw: the previous substep's right-hand sides on entry
  * (ignored for s = 1), this substep's on return.  Outputs phi_out, u_out,
- * v_out, w_out, p_out must not alias any input.  The call reads back the
- * minimum density (one 8-byte copy: it synchronizes the stream once) and
- * then enqueues the correction; report as for pcx_step. */
+ * v_out, w_out, p_out must not alias any input or each other.  The call
+ * reads back the minimum density (one 8-byte copy: it synchronizes the
+ * stream once) and then enqueues the correction; report as for pcx_step. */
 pcx_status pcx_flow_substep(pcx_flow flow, int32_t s, double Dt, const double *phi, const double *u,
                             const double *v, const double *w, const double *p1, const double *p2, double r,
                             double *hphi, double *hu, double *hv, double *hw, double *phi_out, double *u_out,
                             double *v_out, double *w_out, double *p_out, void *stream, pcx_report *report);
+
+/* The same substep up to, not including, the pressure correction: the
+ * inputs, hphi .. hw and phi_out as in pcx_flow_substep; returns the
+ * predicted velocity u_star, v_star, w_star (0 on wall faces), the density
+ * of the updated phase field (rho), the extrapolated pressure p_star, and
+ * on the host *rho0 = min rho and *dt = (gamma_s + zeta_s) Dt: the inputs of
+ * the correction pcx_flow_substep applies (pcx_step with these gives its
+ * outputs bit for bit), for callers that correct otherwise, e.g. with the
+ * variable-coefficient projection of pcx_varcoef.h.  Outputs must not alias
+ * any input or each other; synchronizes the stream once (rho0). */
+pcx_status pcx_flow_predict(pcx_flow flow, int32_t s, double Dt, const double *phi, const double *u,
+                            const double *v, const double *w, const double *p1, const double *p2, double r,
+                            double *hphi, double *hu, double *hv, double *hw, double *phi_out, double *u_star,
+                            double *v_star, double *w_star, double *rho, double *p_star, double *rho0, double *dt,
+                            void *stream);
 
 #ifdef __cplusplus
 }

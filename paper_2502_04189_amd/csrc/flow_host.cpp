@@ -187,25 +187,16 @@ extern "C" pcx_status pcx_flow_momentum_rhs(pcx_flow F, const double *phi, const
     return PCX_OK;
 }
 
-extern "C" pcx_status pcx_flow_substep(pcx_flow F, int32_t sub, double Dt, const double *phi, const double *u,
-                                       const double *v, const double *w, const double *p1, const double *p2,
-                                       double r, double *hphi, double *hu, double *hv, double *hw, double *phi_out,
-                                       double *u_out, double *v_out, double *w_out, double *p_out, void *stream,
-                                       pcx_report *report)
+// The substep up to the correction: normals, flux and curvature, momentum
+// predictor, phase update; u*, the new density and p* into the given
+// buffers; rho0 read back (one 8-byte copy: synchronizes the stream).
+static pcx_status predictor(pcx_flow F, int32_t sub, double Dt, const double *phi, const double *u, const double *v,
+                            const double *w, const double *p1, const double *p2, double r, double *hphi, double *hu,
+                            double *hv, double *hw, double *phi_out, double *const us[3], double *rho_new,
+                            double *pstar, hipStream_t s, double *rho0, double *dt)
 {
     static const double GA[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
     static const double ZE[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
-    if (!F) return fail(PCX_ERR_INVALID, "flow is NULL");
-    if (sub < 1 || sub > 3) return fail(PCX_ERR_INVALID, "substep must be 1, 2 or 3");
-    if (!(Dt > 0.0) || !std::isfinite(Dt) || !std::isfinite(r)) return fail(PCX_ERR_INVALID, "Dt must be > 0, r finite");
-    const void *all[] = {phi, u, v, w, p1, p2, hphi, hu, hv, hw, phi_out, u_out, v_out, w_out, p_out};
-    for (const void *p : all)
-        if (!p) return fail(PCX_ERR_INVALID, "NULL field pointer");
-    for (const void *o : {(const void *)phi_out, (const void *)u_out, (const void *)v_out, (const void *)w_out,
-                          (const void *)p_out})
-        if (aliases(o, {phi, u, v, w, p1, p2, hphi, hu, hv, hw}))
-            return fail(PCX_ERR_INVALID, "an output aliases an input");
-    hipStream_t s = (hipStream_t)stream;
     FArgs A = base_args(F, phi, u, v, w);
     A.Dt = Dt;
     A.ga = GA[sub - 1];
@@ -213,10 +204,10 @@ extern "C" pcx_status pcx_flow_substep(pcx_flow F, int32_t sub, double Dt, const
     A.first = sub == 1;
     A.hphi = hphi; A.hu = hu; A.hv = hv; A.hw = hw;
     A.phi_out = phi_out;
-    for (int d = 0; d < 3; ++d) A.us[d] = F->us[d];
-    A.rho_new = F->rho_new;
+    for (int d = 0; d < 3; ++d) A.us[d] = us[d];
+    A.rho_new = rho_new;
     A.p1 = p1; A.p2 = p2; A.r = r;
-    A.pstar = F->pstar;
+    A.pstar = pstar;
     FCHK(launch_normals(A, F->tp, s));
     FCHK(launch_flux(A, F->tp, s));
     // both passes read the state at the start of the substep only
@@ -225,9 +216,60 @@ extern "C" pcx_status pcx_flow_substep(pcx_flow F, int32_t sub, double Dt, const
     unsigned long long key = 0;
     FCHK(hipMemcpyAsync(&key, F->key, sizeof(key), hipMemcpyDeviceToHost, s));
     FCHK(hipStreamSynchronize(s));
-    const double rho0 = key_to_double(key);
-    if (!(rho0 > 0.0) || !std::isfinite(rho0)) return fail(PCX_ERR_NONFINITE, "minimum density is not positive and finite");
-    const double dt = (GA[sub - 1] + ZE[sub - 1]) * Dt;
+    *rho0 = key_to_double(key);
+    if (!(*rho0 > 0.0) || !std::isfinite(*rho0)) return fail(PCX_ERR_NONFINITE, "minimum density is not positive and finite");
+    *dt = (GA[sub - 1] + ZE[sub - 1]) * Dt;
+    return PCX_OK;
+}
+
+static pcx_status check_substep_args(pcx_flow F, int32_t sub, double Dt, double r,
+                                     std::initializer_list<const void *> ins, std::initializer_list<const void *> outs)
+{
+    if (!F) return fail(PCX_ERR_INVALID, "flow is NULL");
+    if (sub < 1 || sub > 3) return fail(PCX_ERR_INVALID, "substep must be 1, 2 or 3");
+    if (!(Dt > 0.0) || !std::isfinite(Dt) || !std::isfinite(r)) return fail(PCX_ERR_INVALID, "Dt must be > 0, r finite");
+    for (const void *p : ins)
+        if (!p) return fail(PCX_ERR_INVALID, "NULL field pointer");
+    for (const void *p : outs)
+        if (!p) return fail(PCX_ERR_INVALID, "NULL field pointer");
+    for (const void *o : outs) {
+        if (aliases(o, ins)) return fail(PCX_ERR_INVALID, "an output aliases an input");
+        int same = 0;
+        for (const void *o2 : outs) same += o2 == o;
+        if (same > 1) return fail(PCX_ERR_INVALID, "outputs alias each other");
+    }
+    return PCX_OK;
+}
+
+extern "C" pcx_status pcx_flow_substep(pcx_flow F, int32_t sub, double Dt, const double *phi, const double *u,
+                                       const double *v, const double *w, const double *p1, const double *p2,
+                                       double r, double *hphi, double *hu, double *hv, double *hw, double *phi_out,
+                                       double *u_out, double *v_out, double *w_out, double *p_out, void *stream,
+                                       pcx_report *report)
+{
+    pcx_status st = check_substep_args(F, sub, Dt, r, {phi, u, v, w, p1, p2, hphi, hu, hv, hw},
+                                       {phi_out, u_out, v_out, w_out, p_out});
+    if (st != PCX_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    double rho0 = 0.0, dt = 0.0;
+    st = predictor(F, sub, Dt, phi, u, v, w, p1, p2, r, hphi, hu, hv, hw, phi_out, F->us, F->rho_new, F->pstar, s,
+                   &rho0, &dt);
+    if (st != PCX_OK) return st;
     return pcx_step(F->plan, dt, rho0, F->rho_new, F->pstar, F->us[0], F->us[1], F->us[2], u_out, v_out, w_out, p_out,
                     stream, report);
+}
+
+extern "C" pcx_status pcx_flow_predict(pcx_flow F, int32_t sub, double Dt, const double *phi, const double *u,
+                                       const double *v, const double *w, const double *p1, const double *p2,
+                                       double r, double *hphi, double *hu, double *hv, double *hw, double *phi_out,
+                                       double *u_star, double *v_star, double *w_star, double *rho, double *p_star,
+                                       double *rho0, double *dt, void *stream)
+{
+    pcx_status st = check_substep_args(F, sub, Dt, r, {phi, u, v, w, p1, p2, hphi, hu, hv, hw},
+                                       {phi_out, u_star, v_star, w_star, rho, p_star});
+    if (st != PCX_OK) return st;
+    if (!rho0 || !dt) return fail(PCX_ERR_INVALID, "rho0 and dt must not be NULL");
+    double *const us[3] = {u_star, v_star, w_star};
+    return predictor(F, sub, Dt, phi, u, v, w, p1, p2, r, hphi, hu, hv, hw, phi_out, us, rho, p_star,
+                     (hipStream_t)stream, rho0, dt);
 }

@@ -95,6 +95,7 @@ def lib():
         "pcx_flow_phase_rhs": (st, [vp] + [vp] * 5 + [vp]),
         "pcx_flow_momentum_rhs": (st, [vp] + [vp] * 7 + [vp]),
         "pcx_flow_substep": (st, [vp, i32, dbl] + [vp] * 6 + [dbl] + [vp] * 9 + [vp, C.POINTER(PcxReport)]),
+        "pcx_flow_predict": (st, [vp, i32, dbl] + [vp] * 6 + [dbl] + [vp] * 10 + [_DP, _DP, vp]),
         "pcx_varcoef_create": (st, [C.POINTER(PcxGrid), C.POINTER(PcxOptions), C.POINTER(vp)]),
         "pcx_varcoef_destroy": (st, [vp]),
         "pcx_varcoef_apply": (st, [vp, vp, vp, vp, vp]),
@@ -356,6 +357,20 @@ class Flow:
                                     C.byref(rep) if report else None)
         _check(st, "pcx_flow_substep")
         return rep.as_dict() if report else None
+
+    def predict(self, s, Dt, phi, u, v, w, p1, p2, r, h, phi_out, stream=None):
+        """pcx_flow_predict: the substep up to the correction.  h = [hphi,
+        hu, hv, hw] (updated in place).  Returns (u*, v*, w*, rho, p*, rho0,
+        dt), the inputs of the correction."""
+        import torch
+        outs = [torch.empty(self.shape, dtype=torch.float64, device=phi.device) for _ in range(5)]
+        p = self._ptrs((phi, u, v, w, p1, p2), ("phi", "u", "v", "w", "p1", "p2"))
+        ph = self._ptrs(h, ("hphi", "hu", "hv", "hw"))
+        po = self._ptrs([phi_out] + outs, ("phi_out", "u_star", "v_star", "w_star", "rho", "p_star"))
+        rho0, dt = C.c_double(), C.c_double()
+        _check(lib().pcx_flow_predict(self._h, int(s), float(Dt), *p, float(r), *ph, *po, C.byref(rho0), C.byref(dt),
+                                      _stream_handle(stream)), "pcx_flow_predict")
+        return (*outs, rho0.value, dt.value)
 
 
 class VarCoef:

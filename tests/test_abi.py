@@ -167,3 +167,10 @@ def test_varcoef_create_validation(L):
     it, rr = C.c_int32(), C.c_double()
     assert L.pcx_varcoef_project(None, 1.0, 1.0, *[None] * 4, 1e-12, 10, *[None] * 4, None, C.byref(it),
                                  C.byref(rr)) == P.PCX_ERR_INVALID
+
+
+def test_flow_predict_rejects_null(L):
+    """pcx_flow_predict rejects a NULL flow on the host."""
+    r0, dt = C.c_double(), C.c_double()
+    assert L.pcx_flow_predict(None, 1, 1e-3, *[None] * 6, 0.0, *[None] * 10, C.byref(r0), C.byref(dt),
+                              None) == P.PCX_ERR_INVALID

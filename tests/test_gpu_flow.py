@@ -213,3 +213,34 @@ def test_flow_bubble_channel_vs_oracle(pcx, orc):
         po, pg = [outs_o[4], po[0]], [outs_g[4], pg[0]]
         dtprev = al * Dt
     F.close()
+
+
+def test_predict_then_step_is_the_substep(pcx):
+    """pcx_flow_predict returns the inputs of the substep's correction: the
+    pressure-correction step applied to them gives the substep's outputs
+    bit for bit (same kernels, same order)."""
+    import torch
+    gs, eps, phi, u, v, w, p1, p2 = _case(41, 32, 24, 16, (0, 0, 1), 1.3)
+    F = pcx.Flow(gs, eps=eps, **PARAMS)
+    st = [to_dev(a) for a in (phi, u, v, w)]
+    pg = [to_dev(p1), to_dev(p2)]
+    Dt, r = 0.1 * gs.lx / gs.nx, 0.7
+    h0 = [torch.zeros(gs.shape, dtype=torch.float64, device="cuda") for _ in range(4)]
+    for s in (1, 2):
+        # substep 2 takes substep 1's right-hand sides (bitwise the same on
+        # both paths, checked below)
+        ha, hb = [t.clone() for t in h0], [t.clone() for t in h0]
+        outs = [torch.empty(gs.shape, dtype=torch.float64, device="cuda") for _ in range(5)]
+        F.substep(s, Dt, *st, *pg, r, ha, outs, report=False)
+        phi_b = torch.empty_like(outs[0])
+        us, vs, ws, rho, ps, rho0, dt = F.predict(s, Dt, *st, *pg, r, hb, phi_b)
+        plan = pcx.Plan(gs, "fp64")
+        uo, vo, wo, po, _ = plan.step(dt, rho0, rho, ps, us, vs, ws)
+        plan.close()
+        torch.cuda.synchronize()
+        same = [torch.equal(a, b) for a, b in zip(outs + ha, [phi_b, uo, vo, wo, po] + hb)]
+        _say(f"  predict + step vs substep {s}: bitwise equal {same}, rho0 {rho0:.4g}, dt/Dt {dt / Dt:.4f}")
+        assert all(same)
+        assert abs(rho0 - float(rho.min())) == 0.0
+        h0 = ha
+    F.close()
