@@ -68,8 +68,9 @@ pcx_status pcx_flow_momentum_rhs(pcx_flow flow, const double *phi, const double 
 /* One substep s (1..3) of step Dt > 0 from (phi, u, v, w) with the
  * pressures p1, p2 of the two previous substeps and their ratio r.
  * hphi, hu, hv, hw: the previous substep's right-hand sides on entry
- * (ignored for s = 1), this substep's on return.  Outputs phi_out, u_out,
- * v_out, w_out, p_out must not alias any input or each other.  The call
+ * (ignored for s = 1), this substep's on return.  These and the outputs
+ * phi_out, u_out, v_out, w_out, p_out must not alias any input or each
+ * other (INVALID).  The call
  * reads back the minimum density (one 8-byte copy: it synchronizes the
  * stream once) and then enqueues the correction; report as for pcx_step. */
 pcx_status pcx_flow_substep(pcx_flow flow, int32_t s, double Dt, const double *phi, const double *u,

@@ -222,22 +222,28 @@ static pcx_status predictor(pcx_flow F, int32_t sub, double Dt, const double *ph
     return PCX_OK;
 }
 
+// ins: read-only inputs; hs: the right-hand sides read and rewritten in
+// place (each only at its own cell); outs: written.  hs and outs must each
+// be distinct from everything else (other threads read the inputs'
+// neighbours while a cell is written).
 static pcx_status check_substep_args(pcx_flow F, int32_t sub, double Dt, double r,
-                                     std::initializer_list<const void *> ins, std::initializer_list<const void *> outs)
+                                     std::initializer_list<const void *> ins, std::initializer_list<const void *> hs,
+                                     std::initializer_list<const void *> outs)
 {
     if (!F) return fail(PCX_ERR_INVALID, "flow is NULL");
     if (sub < 1 || sub > 3) return fail(PCX_ERR_INVALID, "substep must be 1, 2 or 3");
     if (!(Dt > 0.0) || !std::isfinite(Dt) || !std::isfinite(r)) return fail(PCX_ERR_INVALID, "Dt must be > 0, r finite");
-    for (const void *p : ins)
-        if (!p) return fail(PCX_ERR_INVALID, "NULL field pointer");
-    for (const void *p : outs)
-        if (!p) return fail(PCX_ERR_INVALID, "NULL field pointer");
-    for (const void *o : outs) {
-        if (aliases(o, ins)) return fail(PCX_ERR_INVALID, "an output aliases an input");
-        int same = 0;
-        for (const void *o2 : outs) same += o2 == o;
-        if (same > 1) return fail(PCX_ERR_INVALID, "outputs alias each other");
-    }
+    for (auto l : {ins, hs, outs})
+        for (const void *p : l)
+            if (!p) return fail(PCX_ERR_INVALID, "NULL field pointer");
+    for (auto l : {hs, outs})
+        for (const void *o : l) {
+            if (aliases(o, ins)) return fail(PCX_ERR_INVALID, "an output aliases an input");
+            int same = 0;
+            for (auto m : {hs, outs})
+                for (const void *o2 : m) same += o2 == o;
+            if (same > 1) return fail(PCX_ERR_INVALID, "outputs alias each other");
+        }
     return PCX_OK;
 }
 
@@ -247,7 +253,7 @@ extern "C" pcx_status pcx_flow_substep(pcx_flow F, int32_t sub, double Dt, const
                                        double *u_out, double *v_out, double *w_out, double *p_out, void *stream,
                                        pcx_report *report)
 {
-    pcx_status st = check_substep_args(F, sub, Dt, r, {phi, u, v, w, p1, p2, hphi, hu, hv, hw},
+    pcx_status st = check_substep_args(F, sub, Dt, r, {phi, u, v, w, p1, p2}, {hphi, hu, hv, hw},
                                        {phi_out, u_out, v_out, w_out, p_out});
     if (st != PCX_OK) return st;
     hipStream_t s = (hipStream_t)stream;
@@ -265,7 +271,7 @@ extern "C" pcx_status pcx_flow_predict(pcx_flow F, int32_t sub, double Dt, const
                                        double *u_star, double *v_star, double *w_star, double *rho, double *p_star,
                                        double *rho0, double *dt, void *stream)
 {
-    pcx_status st = check_substep_args(F, sub, Dt, r, {phi, u, v, w, p1, p2, hphi, hu, hv, hw},
+    pcx_status st = check_substep_args(F, sub, Dt, r, {phi, u, v, w, p1, p2}, {hphi, hu, hv, hw},
                                        {phi_out, u_star, v_star, w_star, rho, p_star});
     if (st != PCX_OK) return st;
     if (!rho0 || !dt) return fail(PCX_ERR_INVALID, "rho0 and dt must not be NULL");

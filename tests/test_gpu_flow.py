@@ -244,3 +244,23 @@ def test_predict_then_step_is_the_substep(pcx):
         assert abs(rho0 - float(rho.min())) == 0.0
         h0 = ha
     F.close()
+
+
+def test_substep_rejects_aliased_fields(pcx):
+    """Right-hand-side buffers and outputs that alias an input or each other
+    are rejected before any launch."""
+    import torch
+    gs, eps, phi, u, v, w, p1, p2 = _case(43, 16, 12, 8, (0, 0, 1), 0.0)
+    F = pcx.Flow(gs, eps=eps, **PARAMS)
+    st = [to_dev(a) for a in (phi, u, v, w)]
+    pg = [to_dev(p1), to_dev(p2)]
+    z = lambda: torch.zeros(gs.shape, dtype=torch.float64, device="cuda")
+    h = [z() for _ in range(4)]
+    outs = [z() for _ in range(5)]
+    for bad_h, bad_o in (([st[0]] + h[1:], outs), (h, [h[0]] + outs[1:]), (h, [outs[0], outs[0]] + outs[2:]),
+                         ([h[0], h[0]] + h[2:], outs)):
+        with pytest.raises(pcx.PcxError):
+            F.substep(1, 1e-3, *st, *pg, 0.0, bad_h, bad_o, report=False)
+    F.substep(1, 1e-3, *st, *pg, 0.0, h, outs, report=False)  # the valid call still runs
+    torch.cuda.synchronize()
+    F.close()
