@@ -329,7 +329,7 @@ def prof_batch(steps, warmup, ndom):
 # projection: every field a kernel reads or writes, once (neighbours re-read
 # through the caches are overhead).
 FLOW_BYTES = {"normals": 8 + 32,          # phi -> psi, n
-              "flux": 32 + 32,            # phi, psi, n -> a (3 faces), kappa
+              "flux": 40 + 32,            # phi, psi, n (3) -> a (3 faces), kappa
               "phase": 64 + 24,           # phi, u, v, w, a, h -> phi', h, rho'
               "momentum": 104 + 56}       # phi, u, v, w, kappa, a, h (3), p1, p2 -> u* (3), h (3), p*
 

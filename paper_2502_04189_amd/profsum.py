@@ -12,6 +12,9 @@ size is given on the command line).
     python -m paper_2502_04189_amd.profsum --name fp64_512cube_step \\
         --trace DIR --fetch DIR --write DIR --field-bytes 1073741824 \\
         --cmd "rocprofv3 ..." [--cmd ...] --out profiles
+
+With --counters DIR (repeatable) and --kernel NAME (repeatable) it writes a
+table of SQ instruction and wait counters per kernel instead.
 """
 from __future__ import annotations
 
@@ -127,6 +130,50 @@ def summarize(name, trace, fetch, write, field_bytes, cmds, out_dir, prefix="pcx
     return kernels
 
 
+def counter_table(name, trace, runs, kernels, cmds, out_dir, prefix="pcx_", notes="", simds=1024, ghz=2.4):
+    """Instruction and wait counters per dispatch of the given kernels (name
+    substrings) from --pmc runs of SQ counters, with the VALU busy fraction
+    they imply: SQ_INSTS_VALU x 4 cycles (a wave64 VALU instruction holds its
+    SIMD for 4 cycles) over the SIMD cycles of the kernel's average duration
+    from the kernel-trace run (1024 SIMDs at 2.4 GHz)."""
+    ks = kernel_stats(trace)
+    vals = {}
+    for d in runs:
+        names = {r["Counter_Name"] for r in _csv(d, "counter_collection.csv")}
+        for c in sorted(names):
+            for k, v in counter_means(d, c).items():
+                vals.setdefault(k, {})[c] = v
+    lines = [f"# rocprofv3 counters: {name}", "", "Commands (from the repository root, on one MI355X):", "", "```"]
+    lines += list(cmds) + ["```", ""]
+    lines.append(f"Kernel sources hash (sha256 of csrc/{prefix}*, first 16 hex): `{src_hash(prefix)}`")
+    lines.append("")
+    lines.append("| Kernel | avg ms | waves | VALU / wave | VMEM rd / wave | LDS / wave | "
+                 "VALU busy | wait / wave cycles |")
+    lines.append("|---|---|---|---|---|---|---|---|")
+    out = {}
+    for part in kernels:
+        hits = [k for k in vals if part in k]
+        if not hits:
+            continue
+        k = hits[0]
+        v = vals[k]
+        ms = next((m for kn, (_, m) in ks.items() if part in kn), None)
+        waves = v.get("SQ_WAVES", 0.0)
+        per = lambda c: v[c] / waves if waves and c in v else float("nan")
+        busy = v["SQ_INSTS_VALU"] * 4 / (simds * ghz * 1e9 * ms * 1e-3) if ms and "SQ_INSTS_VALU" in v else float("nan")
+        wait = v["SQ_WAIT_INST_ANY"] / v["SQ_WAVE_CYCLES"] if v.get("SQ_WAVE_CYCLES") else float("nan")
+        out[k] = {"ms": ms, "counters": v, "valu_busy": busy, "wait_frac": wait}
+        short = k if len(k) <= 70 else k[:67] + "..."
+        lines.append(f"| `{short}` | {ms:.4f} | {waves:.0f} | {per('SQ_INSTS_VALU'):.0f} | "
+                     f"{per('SQ_INSTS_VMEM_RD'):.1f} | {per('SQ_INSTS_LDS'):.1f} | {busy:.2f} | {wait:.2f} |")
+    if notes:
+        lines += ["", notes.strip()]
+    os.makedirs(out_dir, exist_ok=True)
+    with open(os.path.join(out_dir, name + ".md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--name", required=True)
@@ -139,7 +186,14 @@ def main(argv=None):
     ap.add_argument("--notes", default="")
     ap.add_argument("--top", type=int, default=12)
     ap.add_argument("--out", default=os.path.join(os.path.dirname(HERE), "profiles"))
+    ap.add_argument("--counters", action="append", default=[],
+                    help="directory of a --pmc run of SQ counters (repeatable); with --kernel, "
+                         "writes the counter table instead of the byte summary")
+    ap.add_argument("--kernel", action="append", default=[], help="kernel name substring for --counters")
     a = ap.parse_args(argv)
+    if a.counters:
+        counter_table(a.name, a.trace, a.counters, a.kernel, a.cmd, a.out, a.prefix, a.notes)
+        return 0
     summarize(a.name, a.trace, a.fetch, a.write, a.field_bytes, a.cmd, a.out, a.prefix, a.notes, a.top)
     return 0
 
