@@ -39,6 +39,7 @@ extern "C" {
 #endif
 
 typedef struct {
+    /* every field finite (INVALID otherwise) */
     double rho1, rho2;   /* densities of phase 1 (phi = 1) and phase 2, > 0 */
     double mu1, mu2;     /* dynamic viscosities, >= 0 */
     double sigma;        /* surface tension, >= 0 */

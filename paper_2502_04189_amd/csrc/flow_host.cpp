@@ -59,7 +59,8 @@ extern "C" pcx_status pcx_flow_create(const pcx_grid *grid, const pcx_flow_param
     const pcx_flow_params &q = *prm;
     if (!(q.rho1 > 0.0) || !(q.rho2 > 0.0) || !(q.mu1 >= 0.0) || !(q.mu2 >= 0.0) || !(q.sigma >= 0.0) ||
         !(q.gamma >= 0.0) || !(q.eps > 0.0) || !(q.eps_s >= 0.0) || !fin(q.rho1) || !fin(q.rho2) || !fin(q.mu1) ||
-        !fin(q.mu2) || !fin(q.sigma) || !fin(q.gamma) || !fin(q.eps) || !fin(q.gx) || !fin(q.gy) || !fin(q.gz))
+        !fin(q.mu2) || !fin(q.sigma) || !fin(q.gamma) || !fin(q.eps) || !fin(q.eps_s) || !fin(q.gx) || !fin(q.gy) ||
+        !fin(q.gz))
         return fail(PCX_ERR_INVALID, "flow parameters out of range");
     pcx_flow F = new pcx_flow_s();
     F->grid = *grid;

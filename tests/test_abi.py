@@ -137,7 +137,9 @@ def test_flow_create_validation(L):
     g = P.make_grid(gs)
     good = P.PcxFlowParams(1000.0, 1.0, 1e-2, 1e-4, 0.07, 0.0, 0.0, -9.81, 1.0, 0.04, 1e-100)
     h = C.c_void_p()
-    for field, bad in (("rho1", 0.0), ("mu2", -1.0), ("eps", 0.0), ("gamma", -1.0), ("gz", float("nan"))):
+    inf = float("inf")
+    for field, bad in (("rho1", 0.0), ("mu2", -1.0), ("eps", 0.0), ("gamma", -1.0), ("gz", float("nan")),
+                       ("eps_s", -1e-3), ("eps_s", inf), ("sigma", inf), ("rho2", inf)):
         p = P.PcxFlowParams(*[getattr(good, f) for f, _ in P.PcxFlowParams._fields_])
         setattr(p, field, bad)
         assert L.pcx_flow_create(C.byref(g), C.byref(p), None, C.byref(h)) == P.PCX_ERR_INVALID, field
