@@ -10,12 +10,19 @@
 namespace pcx {
 namespace flow {
 
+// every output of these kernels is streamed: written once, read by a later
+// kernel only, so it is stored non-temporally (it does not evict the
+// neighbour values other workgroups of the same kernel still read)
+__device__ __forceinline__ void put(double *p, double v) { __builtin_nontemporal_store(v, p); }
+// inputs read at their own cell only (previous right-hand sides, pressures)
+__device__ __forceinline__ double own(const double *p) { return __builtin_nontemporal_load(p); }
+
 // psi of every cell (one logarithm per cell), then the normals from it
 __global__ __launch_bounds__(FT) void k_flow_psi(FArgs A)
 {
     const size_t n = (size_t)A.G.n[0] * A.G.n[1] * A.G.n[2];
     const size_t c = (size_t)blockIdx.x * FT + threadIdx.x;
-    if (c < n) A.psi[c] = psi_of(A.P, A.phi[c]);
+    if (c < n) put(A.psi + c, psi_of(A.P, A.phi[c]));
 }
 
 template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_normals(TileBox b, int, FArgs A)
@@ -32,9 +39,9 @@ template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_normals(TileBo
         with_acc<false>(A.G, t, [&](const auto &x) { normal_cell(x, A.psi, nx, ny, nz); });
     }
     const size_t c = at(A.G, t.i, t.j, t.k);
-    A.n[0][c] = nx;
-    A.n[1][c] = ny;
-    A.n[2][c] = nz;
+    put(A.n[0] + c, nx);
+    put(A.n[1] + c, ny);
+    put(A.n[2] + c, nz);
 }
 
 template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_flux(TileBox b, int, FArgs A)
@@ -49,17 +56,17 @@ template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_flux(TileBox b
         stage_regs<5>(A.G, t, src, rg);
         const StageAcc<0> x(A.G, t.i, t.j, t.k, nullptr, 0, rg);
         const SVec<2> n;
-        A.a[0][c] = flux_face<0>(x, A.P, SField<0>{}, SField<1>{}, SField<2>{});
-        A.a[1][c] = flux_face<1>(x, A.P, SField<0>{}, SField<1>{}, SField<3>{});
-        A.a[2][c] = flux_face<2>(x, A.P, SField<0>{}, SField<1>{}, SField<4>{});
-        A.kap[c] = curvature_cell(x, n);
+        put(A.a[0] + c, flux_face<0>(x, A.P, SField<0>{}, SField<1>{}, SField<2>{}));
+        put(A.a[1] + c, flux_face<1>(x, A.P, SField<0>{}, SField<1>{}, SField<3>{}));
+        put(A.a[2] + c, flux_face<2>(x, A.P, SField<0>{}, SField<1>{}, SField<4>{}));
+        put(A.kap + c, curvature_cell(x, n));
     } else {
         const PVec n{A.n[0], A.n[1], A.n[2]};
         with_acc<false>(A.G, t, [&](const auto &x) {
-            A.a[0][c] = flux_face<0>(x, A.P, A.phi, A.psi, A.n[0]);
-            A.a[1][c] = flux_face<1>(x, A.P, A.phi, A.psi, A.n[1]);
-            A.a[2][c] = flux_face<2>(x, A.P, A.phi, A.psi, A.n[2]);
-            A.kap[c] = curvature_cell(x, n);
+            put(A.a[0] + c, flux_face<0>(x, A.P, A.phi, A.psi, A.n[0]));
+            put(A.a[1] + c, flux_face<1>(x, A.P, A.phi, A.psi, A.n[1]));
+            put(A.a[2] + c, flux_face<2>(x, A.P, A.phi, A.psi, A.n[2]));
+            put(A.kap + c, curvature_cell(x, n));
         });
     }
 }
@@ -95,14 +102,14 @@ template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_phase(TileBox 
             with_acc<false>(A.G, t, [&](const auto &x) { r = acdi_cell(x, A.phi, vel, av); });
         }
         if (A.phi_out) {
-            const double old = A.first ? 0.0 : A.hphi[c];
+            const double old = A.first ? 0.0 : own(A.hphi + c);
             const double q = A.phi[c] + A.Dt * (A.ga * r + A.ze * old);
-            A.phi_out[c] = q;
+            put(A.phi_out + c, q);
             const double rho = A.P.rho2 + (A.P.rho1 - A.P.rho2) * q;
-            A.rho_new[c] = rho;
+            put(A.rho_new + c, rho);
             key = fkey(rho);
         }
-        A.hphi[c] = r;
+        put(A.hphi + c, r);
     }
     if (!A.phi_out) return;
 #pragma unroll
@@ -156,8 +163,8 @@ __device__ __forceinline__ void mom_put(const FArgs &A, const FTile &t, size_t c
                                         double *hc, double *qs)
 {
     const int s = C == 0 ? t.i : (C == 1 ? t.j : t.k);
-    if (qs) qs[c] = wallf(A.G, C, s) ? 0.0 : qv + A.Dt * (A.ga * m + A.ze * old);
-    hc[c] = m;
+    if (qs) put(qs + c, wallf(A.G, C, s) ? 0.0 : qv + A.Dt * (A.ga * m + A.ze * old));
+    put(hc + c, m);
 }
 template <int C>
 __device__ __forceinline__ void mom_store(const FArgs &A, const FTile &t, size_t c, double m, double *hc,
@@ -234,13 +241,13 @@ template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_momentum(TileB
         const size_t cc = at(A.G, t.act ? t.i : A.G.n[0] - 1, t.act ? t.j : A.G.n[1] - 1, t.k);
         double old[3] = {0.0, 0.0, 0.0}, pp1 = 0.0, pp2 = 0.0;
         if (!A.first) {
-            if (A.us[0]) old[0] = A.hu[cc];
-            if (A.us[1]) old[1] = A.hv[cc];
-            if (A.us[2]) old[2] = A.hw[cc];
+            if (A.us[0]) old[0] = own(A.hu + cc);
+            if (A.us[1]) old[1] = own(A.hv + cc);
+            if (A.us[2]) old[2] = own(A.hw + cc);
         }
         if (A.pstar) {
-            pp1 = A.p1[cc];
-            pp2 = A.p2[cc];
+            pp1 = own(A.p1 + cc);
+            pp2 = own(A.p2 + cc);
         }
         __syncthreads();
         if (!t.act) return;
@@ -253,7 +260,7 @@ template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_momentum(TileB
         mom_put<0>(A, t, cc, m0, old[0], x.cv(SField<0>{}, 0, 0, 0), A.hu, A.us[0]);
         mom_put<1>(A, t, cc, m1, old[1], x.cv(SField<1>{}, 0, 0, 0), A.hv, A.us[1]);
         mom_put<2>(A, t, cc, m2, old[2], x.cv(SField<2>{}, 0, 0, 0), A.hw, A.us[2]);
-        if (A.pstar) A.pstar[cc] = (1.0 + A.r) * pp1 - A.r * pp2;
+        if (A.pstar) put(A.pstar + cc, (1.0 + A.r) * pp1 - A.r * pp2);
     } else {
         if (!t.act) return;
         const PVel vel{A.u, A.v, A.w};
@@ -267,7 +274,7 @@ template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_momentum(TileB
         mom_store<0>(A, t, c, m0, A.hu, A.u, A.us[0]);
         mom_store<1>(A, t, c, m1, A.hv, A.v, A.us[1]);
         mom_store<2>(A, t, c, m2, A.hw, A.w, A.us[2]);
-        if (A.pstar) A.pstar[c] = (1.0 + A.r) * A.p1[c] - A.r * A.p2[c];
+        if (A.pstar) put(A.pstar + c, (1.0 + A.r) * A.p1[c] - A.r * A.p2[c]);
     }
 }
 
