@@ -328,8 +328,8 @@ def prof_batch(steps, warmup, ndom):
 # Algorithmic HBM bytes per cell of the substep kernels around the
 # projection: every field a kernel reads or writes, once (neighbours re-read
 # through the caches are overhead).
-FLOW_BYTES = {"normals": 8 + 32,          # phi -> psi, n
-              "flux": 40 + 32,            # phi, psi, n (3) -> a (3 faces), kappa
+FLOW_BYTES = {"psi": 8 + 8,               # phi -> psi
+              "flux": 16 + 32,            # phi, psi -> a (3 faces), kappa (normals evaluated in the kernel)
               "phase": 64 + 24,           # phi, u, v, w, a, h -> phi', h, rho'
               "momentum": 104 + 56}       # phi, u, v, w, kappa, a, h (3), p1, p2 -> u* (3), h (3), p*
 

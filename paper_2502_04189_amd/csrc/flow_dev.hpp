@@ -278,6 +278,22 @@ template <int NL> struct StageAcc : Fast {
 
 // ---------------------------------------------------------------- passes
 
+// g / |g| (0 where g = 0), with the fused multiply-adds written out, so that
+// every kernel that evaluates a normal rounds it the same way; one
+// reciprocal square root instead of a square root and a division
+__device__ __forceinline__ void unit_normal(double gx, double gy, double gz, double &nx, double &ny, double &nz)
+{
+    const double m2 = fma(gx, gx, fma(gy, gy, gz * gz));
+    if (m2 > 0.0) {
+        const double im = rsqrt(m2);
+        nx = gx * im;
+        ny = gy * im;
+        nz = gz * im;
+    } else {
+        nx = ny = nz = 0.0;
+    }
+}
+
 // the unit normal grad psi / |grad psi| at the cell, from stored psi
 template <class X, class PS>
 __device__ __forceinline__ void normal_cell(const X &x, PS psi, double &nx, double &ny, double &nz)
@@ -285,15 +301,7 @@ __device__ __forceinline__ void normal_cell(const X &x, PS psi, double &nx, doub
     const double gx = (x.cv(psi, 1, 0, 0) - x.cv(psi, -1, 0, 0)) * (0.5 * x.ih(0));
     const double gy = (x.cv(psi, 0, 1, 0) - x.cv(psi, 0, -1, 0)) * (0.5 * x.ih(1));
     const double gz = (x.cv(psi, 0, 0, 1) - x.cv(psi, 0, 0, -1)) * x.izc2();
-    const double m = sqrt(gx * gx + gy * gy + gz * gz);
-    if (m > 0.0) {
-        const double im = 1.0 / m;
-        nx = gx * im;
-        ny = gy * im;
-        nz = gz * im;
-    } else {
-        nx = ny = nz = 0.0;
-    }
+    unit_normal(gx, gy, gz, nx, ny, nz);
 }
 
 // regularization flux on the +D face of the cell (0 on a wall face)

@@ -22,7 +22,8 @@ struct pcx_flow_s {
     pcx_grid grid;
     std::vector<double> zf;
     FGrid G;
-    TilePlan tp;
+    TilePlan tp;  // phase and momentum kernels
+    TilePlan tpn; // normals and flux (interior planes from 2 on with walls in z)
     FParams P;
     pcx_plan plan = nullptr;
     double *tab = nullptr;           // z metric tables (metric_tables)
@@ -99,6 +100,7 @@ extern "C" pcx_status pcx_flow_create(const pcx_grid *grid, const pcx_flow_param
     G.rz = F->tab + 2 * nz;
     F->P = FParams{q.rho1, q.rho2, q.mu1, q.mu2, q.sigma, {q.gx, q.gy, q.gz}, q.gamma, q.eps, q.eps_s, 0.5 / q.eps};
     F->tp = tile_plan(G);
+    F->tpn = tile_plan(G, 2);
     if (hipMalloc(&F->part, (size_t)F->tp.nslots * sizeof(unsigned long long)) != hipSuccess) {
         flow_free(F);
         return fail(PCX_ERR_NOMEM, "flow workspace allocation failed");
@@ -166,8 +168,8 @@ extern "C" pcx_status pcx_flow_phase_rhs(pcx_flow F, const double *phi, const do
     hipStream_t s = (hipStream_t)stream;
     FArgs A = base_args(F, phi, u, v, w);
     A.hphi = rhs;
-    FCHK(launch_normals(A, F->tp, s));
-    FCHK(launch_flux(A, F->tp, s));
+    FCHK(launch_normals(A, F->tpn, s));
+    FCHK(launch_flux(A, F->tpn, s));
     FCHK(launch_phase(A, F->tp, s));
     return PCX_OK;
 }
@@ -182,8 +184,8 @@ extern "C" pcx_status pcx_flow_momentum_rhs(pcx_flow F, const double *phi, const
     hipStream_t s = (hipStream_t)stream;
     FArgs A = base_args(F, phi, u, v, w);
     A.hu = ru; A.hv = rv; A.hw = rw;
-    FCHK(launch_normals(A, F->tp, s));
-    FCHK(launch_flux(A, F->tp, s));
+    FCHK(launch_normals(A, F->tpn, s));
+    FCHK(launch_flux(A, F->tpn, s));
     FCHK(launch_momentum(A, F->tp, s));
     return PCX_OK;
 }
@@ -209,8 +211,8 @@ static pcx_status predictor(pcx_flow F, int32_t sub, double Dt, const double *ph
     A.rho_new = rho_new;
     A.p1 = p1; A.p2 = p2; A.r = r;
     A.pstar = pstar;
-    FCHK(launch_normals(A, F->tp, s));
-    FCHK(launch_flux(A, F->tp, s));
+    FCHK(launch_normals(A, F->tpn, s));
+    FCHK(launch_flux(A, F->tpn, s));
     // both passes read the state at the start of the substep only
     FCHK(launch_momentum(A, F->tp, s));
     FCHK(launch_phase(A, F->tp, s));

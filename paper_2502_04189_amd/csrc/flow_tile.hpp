@@ -45,6 +45,7 @@ struct TilePlan {
     bool fast[7];
     int slot0[7];
     int nslots;
+    int zlow; // first interior plane with walls in z (tile_plan's argument)
 };
 
 // Host tables of a grid's z metrics: dzf (nz), dzc (nz, the periodic wrap
@@ -79,13 +80,17 @@ inline std::vector<double> metric_tables(const double *zf, int nz, bool zper)
 // Tile boxes of a grid.  The stencils reach one cell (and one face) beyond
 // their cell, so a wall direction's interior tiles lie within [1, n-3]: x
 // tiles it >= 1 with (it + 1) FTI <= nx - 2, likewise y, planes 1 .. nz-3.
-inline TilePlan tile_plan(const FGrid &G)
+// With zlow = 2 the interior planes start at 2 (wall z; x and y tiles are
+// at least 4 cells from a wall anyway): the flux kernel's interior form
+// evaluates the normals of its neighbours, whose stencils reach two cells.
+inline TilePlan tile_plan(const FGrid &G, int zlow = 1)
 {
     const int ti = (G.n[0] + FTI - 1) / FTI, tj = (G.n[1] + FTJ - 1) / FTJ, nz = G.n[2];
     const int it0 = G.per[0] ? 0 : 1, it1 = G.per[0] ? ti : (G.n[0] - 2) / FTI;
     const int jt0 = G.per[1] ? 0 : 1, jt1 = G.per[1] ? tj : (G.n[1] - 2) / FTJ;
-    const int k0 = G.per[2] ? 0 : 1, k1 = G.per[2] ? nz : nz - 2;
+    const int k0 = G.per[2] ? 0 : zlow, k1 = G.per[2] ? nz : nz - 2;
     TilePlan p{};
+    p.zlow = zlow;
     auto add = [&](TileBox b, bool fast) {
         if (b.nit <= 0 || b.njt <= 0 || b.nk <= 0) return;
         p.box[p.n] = b;

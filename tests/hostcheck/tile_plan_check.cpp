@@ -19,12 +19,13 @@ static int fail(const char *what, int nx, int ny, int nz, int px, int py, int pz
     return 1;
 }
 
-static int check(int nx, int ny, int nz, int px, int py, int pz)
+static int check(int nx, int ny, int nz, int px, int py, int pz, int zlow)
 {
     FGrid G{};
     G.n[0] = nx; G.n[1] = ny; G.n[2] = nz;
     G.per[0] = px; G.per[1] = py; G.per[2] = pz;
-    const TilePlan p = tile_plan(G);
+    const TilePlan p = tile_plan(G, zlow);
+    if (p.zlow != zlow) return fail("plan's zlow", nx, ny, nz, px, py, pz);
     const int ti = (nx + FTI - 1) / FTI, tj = (ny + FTJ - 1) / FTJ;
     std::vector<int> seen((size_t)ti * tj * nz, 0);
     int slot = 0;
@@ -46,8 +47,16 @@ static int check(int nx, int ny, int nz, int px, int py, int pz)
                 const int i0 = it * FTI, j0 = jt * FTJ;
                 const bool okx = px ? nx >= FTI + 2 : (i0 >= 1 && i0 + FTI - 1 <= nx - 3);
                 const bool oky = py ? ny >= FTJ + 2 : (j0 >= 1 && j0 + FTJ - 1 <= ny - 3);
-                const bool okz = pz ? nz >= 3 : (k >= 1 && k <= nz - 3);
+                const bool okz = pz ? nz >= 3 : (k >= zlow && k <= nz - 3);
                 if (!okx || !oky || !okz) return fail("interior tile reaches a wall", nx, ny, nz, px, py, pz);
+                // zlow = 2: the normals of the neighbours read cells two steps
+                // away, which must exist (wall) or wrap once (periodic)
+                if (zlow == 2) {
+                    const bool rx = px ? nx >= 2 : (i0 >= 2 && i0 + FTI - 1 <= nx - 3);
+                    const bool ry = py ? ny >= 2 : (j0 >= 2 && j0 + FTJ - 1 <= ny - 3);
+                    const bool rz = pz ? nz >= 3 : (k >= 2 && k <= nz - 3);
+                    if (!rx || !ry || !rz) return fail("interior tile's two-cell reach leaves the grid", nx, ny, nz, px, py, pz);
+                }
             }
         }
     }
@@ -96,12 +105,14 @@ int main()
         for (int ny : {2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 18, 33})
             for (int nz : {2, 3, 4, 5, 8, 17, 33})
                 for (int m = 0; m < 8; ++m) {
-                    if (check(nx, ny, nz, m & 1, (m >> 1) & 1, (m >> 2) & 1)) return 1;
+                    for (int zl = 1; zl <= 2; ++zl)
+                        if (check(nx, ny, nz, m & 1, (m >> 1) & 1, (m >> 2) & 1, zl)) return 1;
                     ++grids;
                 }
     // a large grid (tile counts past a chunk of planes)
     for (int m = 0; m < 8; ++m)
-        if (check(512, 512, 40, m & 1, (m >> 1) & 1, (m >> 2) & 1)) return 1;
+        for (int zl = 1; zl <= 2; ++zl)
+            if (check(512, 512, 40, m & 1, (m >> 1) & 1, (m >> 2) & 1, zl)) return 1;
     for (int nz : {2, 3, 5, 64, 129})
         for (int pz = 0; pz < 2; ++pz)
             if (check_metrics(nz, pz, 7u * nz + pz)) return 1;
