@@ -68,6 +68,13 @@ CASES = [
     ((4, 6, 2), (0, 1, 0), 0.0),
     ((18, 24, 9), (1, 0, 0), 0.0),
 ]
+# grids with interior tiles next to walls in x and y (and z): the interior
+# kernels run beside the wall tiles, and the flux kernel's interior cells
+# next to a wall tile store the normals the wall tiles read
+CASES_INTERIOR = [
+    ((144, 24, 12), (1, 1, 1), 1.3),
+    ((144, 24, 10), (0, 1, 1), 0.0),
+]
 PARAMS = dict(rho1=1000.0, rho2=1.2, mu1=1e-2, mu2=2e-4, sigma=0.07, g=(0.0, 0.0, -9.81), gamma=1.5)
 
 
@@ -75,7 +82,7 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-@pytest.mark.parametrize("dims,bc,stretch", CASES)
+@pytest.mark.parametrize("dims,bc,stretch", CASES + CASES_INTERIOR)
 def test_flow_rhs_vs_oracle(pcx, orc, dims, bc, stretch):
     gs, eps, phi, u, v, w, _, _ = _case(sum(dims), *dims, bc, stretch)
     _say(f"flow rhs {dims} bc {bc} stretch {stretch}")
@@ -94,7 +101,7 @@ def test_flow_rhs_vs_oracle(pcx, orc, dims, bc, stretch):
     assert max(e.values()) <= TOL
 
 
-@pytest.mark.parametrize("dims,bc,stretch", CASES[:3])
+@pytest.mark.parametrize("dims,bc,stretch", CASES[:3] + CASES_INTERIOR)
 def test_flow_three_substeps_vs_oracle(pcx, orc, dims, bc, stretch):
     import torch
     gs, eps, phi, u, v, w, p1, p2 = _case(7 + sum(dims), *dims, bc, stretch)
