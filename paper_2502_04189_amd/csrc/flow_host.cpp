@@ -213,9 +213,9 @@ static pcx_status predictor(pcx_flow F, int32_t sub, double Dt, const double *ph
     A.pstar = pstar;
     FCHK(launch_normals(A, F->tpn, s));
     FCHK(launch_flux(A, F->tpn, s));
-    // both passes read the state at the start of the substep only
-    FCHK(launch_momentum(A, F->tp, s));
-    FCHK(launch_phase(A, F->tp, s));
+    // one pass: the momentum predictor and the phase update read the state at
+    // the start of the substep only
+    FCHK(launch_momentum_phase(A, F->tp, s));
     unsigned long long key = 0;
     FCHK(hipMemcpyAsync(&key, F->key, sizeof(key), hipMemcpyDeviceToHost, s));
     FCHK(hipStreamSynchronize(s));

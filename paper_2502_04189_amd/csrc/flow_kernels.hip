@@ -135,13 +135,45 @@ __device__ __forceinline__ unsigned long long fkey(double v)
     return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
 }
 
+// the substep's phase update of cell c from its right-hand side r: the new
+// phi and density, this substep's right-hand side; key: the density's
+// minimum key
+__device__ __forceinline__ void phase_put(const FArgs &A, size_t c, double r, double phi_c, double old,
+                                          unsigned long long &key)
+{
+    const double q = phi_c + A.Dt * (A.ga * r + A.ze * old);
+    put(A.phi_out + c, q);
+    const double rho = A.P.rho2 + (A.P.rho1 - A.P.rho2) * q;
+    put(A.rho_new + c, rho);
+    key = fkey(rho);
+    put(A.hphi + c, r);
+}
+
+// the workgroup's minimum key into its slot (every thread of the workgroup
+// takes part)
+__device__ __forceinline__ void key_to_slot(unsigned long long key, unsigned long long *slot)
+{
+    __shared__ unsigned long long red[FT / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long x = __shfl_xor(key, o, 64);
+        key = x < key ? x : key;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = key;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < FT / 64; ++i) key = red[i] < key ? red[i] : key;
+        key = red[0] < key ? red[0] : key;
+        *slot = key;
+    }
+}
+
 // Phase-field right-hand side; with phi_out, the substep's update, the new
 // density and the minimum key of the workgroup's densities (one slot per
 // workgroup, reduced by k_flow_min: an atomic per workgroup on one address
 // would serialize half a million workgroups).
 template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_phase(TileBox b, int slot0, FArgs A)
 {
-    __shared__ unsigned long long red[FT / 64];
     const FTile t = btile(A.G, b);
     unsigned long long key = ~0ull;
     if (t.act) {
@@ -158,29 +190,10 @@ template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_phase(TileBox 
             const PVec av{A.a[0], A.a[1], A.a[2]};
             with_acc<false>(A.G, t, [&](const auto &x) { r = acdi_cell(x, A.phi, vel, av); });
         }
-        if (A.phi_out) {
-            const double old = A.first ? 0.0 : own(A.hphi + c);
-            const double q = A.phi[c] + A.Dt * (A.ga * r + A.ze * old);
-            put(A.phi_out + c, q);
-            const double rho = A.P.rho2 + (A.P.rho1 - A.P.rho2) * q;
-            put(A.rho_new + c, rho);
-            key = fkey(rho);
-        }
-        put(A.hphi + c, r);
+        if (A.phi_out) phase_put(A, c, r, A.phi[c], A.first ? 0.0 : own(A.hphi + c), key);
+        else put(A.hphi + c, r);
     }
-    if (!A.phi_out) return;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const unsigned long long x = __shfl_xor(key, o, 64);
-        key = x < key ? x : key;
-    }
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = key;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = 1; i < FT / 64; ++i) key = red[i] < key ? red[i] : key;
-        key = red[0] < key ? red[0] : key;
-        A.rho_part[slot0 + blockIdx.x] = key;
-    }
+    if (A.phi_out) key_to_slot(key, A.rho_part + slot0 + blockIdx.x);
 }
 
 // minimum of the n workgroup keys into *rho_min_key (a few workgroups, one
@@ -276,63 +289,85 @@ __device__ __forceinline__ void stage_fields(const FArgs &A, int i0, int j0, int
 // stencil's neighbour values) from a stage in LDS that the workgroup fills
 // with one round of loads: read from memory one by one, in the rounds the
 // compiler's schedule allowed, they left the kernel waiting on memory
-// latency.  (One kernel per component took 13 % longer in all.)
-template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_momentum(TileBox b, int, FArgs A)
+// latency.  (One kernel per component took 13 % longer in all.)  With PH
+// the kernel also takes the phase field's right-hand side and update (the
+// substep), whose stencil reads only values the momentum stages already
+// hold: a separate phase pass read phi, u, v, w and a again.
+template <bool FAST, bool PH> __device__ __forceinline__ void momentum_body(const TileBox &b, int slot0, const FArgs &A)
 {
     const FTile t = btile(A.G, b);
     double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+    unsigned long long key = ~0ull;
     if constexpr (FAST) {
-        // hu, hv, hw are read and written in place: each thread reads and
-        // writes only its own cell
+        // hu, hv, hw (and hphi) are read and written in place: each thread
+        // reads and writes only its own cell
         __shared__ double st[SNF * SFLD];
-        if (!t.valid) return; // uniform over the workgroup
-        const int tx = threadIdx.x % FTI, ty = threadIdx.x / FTI;
-        stage_fields(A, t.i - tx, t.j - ty, t.k, st);
-        // register stage: issued with the LDS stage's loads, before the
-        // barrier (threads past the grid read their clamped cell)
-        double rg[SNR][27];
-        const double *const rsrc[SNR] = {A.a[0], A.a[1], A.a[2], A.kap};
-        stage_regs<SNR>(A.G, t, rsrc, rg);
-        // the cell's previous right-hand sides and pressures, loaded with the
-        // stages
-        const size_t cc = at(A.G, t.act ? t.i : A.G.n[0] - 1, t.act ? t.j : A.G.n[1] - 1, t.k);
-        double old[3] = {0.0, 0.0, 0.0}, pp1 = 0.0, pp2 = 0.0;
-        if (!A.first) {
-            if (A.us[0]) old[0] = own(A.hu + cc);
-            if (A.us[1]) old[1] = own(A.hv + cc);
-            if (A.us[2]) old[2] = own(A.hw + cc);
+        if (t.valid) { // uniform over the workgroup
+            const int tx = threadIdx.x % FTI, ty = threadIdx.x / FTI;
+            stage_fields(A, t.i - tx, t.j - ty, t.k, st);
+            // register stage: issued with the LDS stage's loads, before the
+            // barrier (threads past the grid read their clamped cell)
+            double rg[SNR][27];
+            const double *const rsrc[SNR] = {A.a[0], A.a[1], A.a[2], A.kap};
+            stage_regs<SNR>(A.G, t, rsrc, rg);
+            // the cell's previous right-hand sides and pressures, loaded with
+            // the stages
+            const size_t cc = at(A.G, t.act ? t.i : A.G.n[0] - 1, t.act ? t.j : A.G.n[1] - 1, t.k);
+            double old[3] = {0.0, 0.0, 0.0}, pp1 = 0.0, pp2 = 0.0, oldp = 0.0;
+            if (!A.first) {
+                if (A.us[0]) old[0] = own(A.hu + cc);
+                if (A.us[1]) old[1] = own(A.hv + cc);
+                if (A.us[2]) old[2] = own(A.hw + cc);
+                if (PH) oldp = own(A.hphi + cc);
+            }
+            if (A.pstar) {
+                pp1 = own(A.p1 + cc);
+                pp2 = own(A.p2 + cc);
+            }
+            __syncthreads();
+            if (t.act) {
+                const StageAcc<SNF> x(A.G, t.i, t.j, t.k, st, SPL + (ty + 1) * SLX + tx + 1, rg);
+                const SVel vel;
+                const SVec<4> av;
+                m0 = mom_rhs<0>(A, x, t, vel, SField<3>{}, SField<7>{}, av);
+                m1 = mom_rhs<1>(A, x, t, vel, SField<3>{}, SField<7>{}, av);
+                m2 = mom_rhs<2>(A, x, t, vel, SField<3>{}, SField<7>{}, av);
+                mom_put<0>(A, t, cc, m0, old[0], x.cv(SField<0>{}, 0, 0, 0), A.hu, A.us[0]);
+                mom_put<1>(A, t, cc, m1, old[1], x.cv(SField<1>{}, 0, 0, 0), A.hv, A.us[1]);
+                mom_put<2>(A, t, cc, m2, old[2], x.cv(SField<2>{}, 0, 0, 0), A.hw, A.us[2]);
+                if (A.pstar) put(A.pstar + cc, (1.0 + A.r) * pp1 - A.r * pp2);
+                if constexpr (PH)
+                    phase_put(A, cc, acdi_cell(x, SField<3>{}, vel, av), x.cv(SField<3>{}, 0, 0, 0), oldp, key);
+            }
         }
-        if (A.pstar) {
-            pp1 = own(A.p1 + cc);
-            pp2 = own(A.p2 + cc);
-        }
-        __syncthreads();
-        if (!t.act) return;
-        const StageAcc<SNF> x(A.G, t.i, t.j, t.k, st, SPL + (ty + 1) * SLX + tx + 1, rg);
-        const SVel vel;
-        const SVec<4> av;
-        m0 = mom_rhs<0>(A, x, t, vel, SField<3>{}, SField<7>{}, av);
-        m1 = mom_rhs<1>(A, x, t, vel, SField<3>{}, SField<7>{}, av);
-        m2 = mom_rhs<2>(A, x, t, vel, SField<3>{}, SField<7>{}, av);
-        mom_put<0>(A, t, cc, m0, old[0], x.cv(SField<0>{}, 0, 0, 0), A.hu, A.us[0]);
-        mom_put<1>(A, t, cc, m1, old[1], x.cv(SField<1>{}, 0, 0, 0), A.hv, A.us[1]);
-        mom_put<2>(A, t, cc, m2, old[2], x.cv(SField<2>{}, 0, 0, 0), A.hw, A.us[2]);
-        if (A.pstar) put(A.pstar + cc, (1.0 + A.r) * pp1 - A.r * pp2);
-    } else {
-        if (!t.act) return;
+    } else if (t.act) {
         const PVel vel{A.u, A.v, A.w};
         const PVec av{A.a[0], A.a[1], A.a[2]};
+        double r = 0.0;
         with_acc<false>(A.G, t, [&](const auto &x) {
             m0 = mom_rhs<0>(A, x, t, vel, A.phi, A.kap, av);
             m1 = mom_rhs<1>(A, x, t, vel, A.phi, A.kap, av);
             m2 = mom_rhs<2>(A, x, t, vel, A.phi, A.kap, av);
+            if constexpr (PH) r = acdi_cell(x, A.phi, vel, av);
         });
         const size_t c = at(A.G, t.i, t.j, t.k);
         mom_store<0>(A, t, c, m0, A.hu, A.u, A.us[0]);
         mom_store<1>(A, t, c, m1, A.hv, A.v, A.us[1]);
         mom_store<2>(A, t, c, m2, A.hw, A.w, A.us[2]);
         if (A.pstar) put(A.pstar + c, (1.0 + A.r) * A.p1[c] - A.r * A.p2[c]);
+        if constexpr (PH) phase_put(A, c, r, A.phi[c], A.first ? 0.0 : own(A.hphi + c), key);
     }
+    if constexpr (PH) key_to_slot(key, A.rho_part + slot0 + blockIdx.x);
+}
+
+template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_momentum(TileBox b, int slot0, FArgs A)
+{
+    momentum_body<FAST, false>(b, slot0, A);
+}
+// the substep's momentum predictor with the phase update
+template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_mom_phase(TileBox b, int slot0, FArgs A)
+{
+    momentum_body<FAST, true>(b, slot0, A);
 }
 
 __global__ void k_flow_key_reset(unsigned long long *k) { *k = ~0ull; }
@@ -377,6 +412,18 @@ hipError_t launch_phase(const FArgs &A, const TilePlan &tp, hipStream_t s)
 hipError_t launch_momentum(const FArgs &A, const TilePlan &tp, hipStream_t s)
 {
     return FLOW_LAUNCH_PLAN(tp, k_flow_momentum, s, A);
+}
+hipError_t launch_momentum_phase(const FArgs &A, const TilePlan &tp, hipStream_t s)
+{
+    if (!A.phi_out || !A.hphi || !A.rho_new) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_flow_key_reset, dim3(1), dim3(1), 0, s, A.rho_min_key);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = FLOW_LAUNCH_PLAN(tp, k_flow_mom_phase, s, A);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_flow_min, dim3(64), dim3(FT), 0, s, (const unsigned long long *)A.rho_part, tp.nslots,
+                       A.rho_min_key);
+    return hipGetLastError();
 }
 
 double key_to_double(unsigned long long k)

@@ -29,6 +29,9 @@ hipError_t launch_normals(const FArgs &A, const TilePlan &tp, hipStream_t s);
 hipError_t launch_flux(const FArgs &A, const TilePlan &tp, hipStream_t s);
 hipError_t launch_phase(const FArgs &A, const TilePlan &tp, hipStream_t s);
 hipError_t launch_momentum(const FArgs &A, const TilePlan &tp, hipStream_t s);
+// the substep's momentum predictor and phase update in one pass (phi_out,
+// hphi and rho_new set), then the density minimum
+hipError_t launch_momentum_phase(const FArgs &A, const TilePlan &tp, hipStream_t s);
 double key_to_double(unsigned long long k);
 
 } // namespace flow
