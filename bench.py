@@ -330,8 +330,8 @@ def prof_batch(steps, warmup, ndom):
 # through the caches are overhead).
 FLOW_BYTES = {"psi": 8 + 8,               # phi -> psi
               "flux": 16 + 32,            # phi, psi -> a (3 faces), kappa (normals evaluated in the kernel)
-              "phase": 64 + 24,           # phi, u, v, w, a, h -> phi', h, rho'
-              "momentum": 104 + 56}       # phi, u, v, w, kappa, a, h (3), p1, p2 -> u* (3), h (3), p*
+              # phi, u, v, w, kappa, a (3), h (3), h_phi, p1, p2 -> u* (3), h (3), p*, phi', rho', h_phi
+              "momentum_phase": 112 + 80}
 
 
 def flow_setup(case):
