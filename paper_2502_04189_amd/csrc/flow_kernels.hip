@@ -150,7 +150,8 @@ __device__ __forceinline__ void phase_put(const FArgs &A, size_t c, double r, do
 }
 
 // the workgroup's minimum key into its slot (every thread of the workgroup
-// takes part)
+// takes part; one slot per workgroup, reduced by k_flow_min: an atomic per
+// workgroup on one address would serialize half a million workgroups)
 __device__ __forceinline__ void key_to_slot(unsigned long long key, unsigned long long *slot)
 {
     __shared__ unsigned long long red[FT / 64];
@@ -168,32 +169,25 @@ __device__ __forceinline__ void key_to_slot(unsigned long long key, unsigned lon
     }
 }
 
-// Phase-field right-hand side; with phi_out, the substep's update, the new
-// density and the minimum key of the workgroup's densities (one slot per
-// workgroup, reduced by k_flow_min: an atomic per workgroup on one address
-// would serialize half a million workgroups).
-template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_phase(TileBox b, int slot0, FArgs A)
+// Phase-field right-hand side only (the phase right-hand side entry point;
+// the substep's update runs in the momentum pass)
+template <bool FAST> __global__ __launch_bounds__(FT) void k_flow_phase(TileBox b, int, FArgs A)
 {
     const FTile t = btile(A.G, b);
-    unsigned long long key = ~0ull;
-    if (t.act) {
-        const size_t c = at(A.G, t.i, t.j, t.k);
-        double r = 0.0;
-        if constexpr (FAST) {
-            // phi, u, v, w, a_x, a_y, a_z from registers, loaded up front
-            double rg[7][27];
-            const double *const src[7] = {A.phi, A.u, A.v, A.w, A.a[0], A.a[1], A.a[2]};
-            stage_regs<7>(A.G, t, src, rg);
-            r = acdi_cell(StageAcc<0>(A.G, t.i, t.j, t.k, nullptr, 0, rg), SField<0>{}, SVec<1>{}, SVec<4>{});
-        } else {
-            const PVel vel{A.u, A.v, A.w};
-            const PVec av{A.a[0], A.a[1], A.a[2]};
-            with_acc<false>(A.G, t, [&](const auto &x) { r = acdi_cell(x, A.phi, vel, av); });
-        }
-        if (A.phi_out) phase_put(A, c, r, A.phi[c], A.first ? 0.0 : own(A.hphi + c), key);
-        else put(A.hphi + c, r);
+    if (!t.act) return;
+    double r = 0.0;
+    if constexpr (FAST) {
+        // phi, u, v, w, a_x, a_y, a_z from registers, loaded up front
+        double rg[7][27];
+        const double *const src[7] = {A.phi, A.u, A.v, A.w, A.a[0], A.a[1], A.a[2]};
+        stage_regs<7>(A.G, t, src, rg);
+        r = acdi_cell(StageAcc<0>(A.G, t.i, t.j, t.k, nullptr, 0, rg), SField<0>{}, SVec<1>{}, SVec<4>{});
+    } else {
+        const PVel vel{A.u, A.v, A.w};
+        const PVec av{A.a[0], A.a[1], A.a[2]};
+        with_acc<false>(A.G, t, [&](const auto &x) { r = acdi_cell(x, A.phi, vel, av); });
     }
-    if (A.phi_out) key_to_slot(key, A.rho_part + slot0 + blockIdx.x);
+    put(A.hphi + at(A.G, t.i, t.j, t.k), r);
 }
 
 // minimum of the n workgroup keys into *rho_min_key (a few workgroups, one
@@ -398,16 +392,7 @@ hipError_t launch_flux(const FArgs &A, const TilePlan &tp, hipStream_t s)
 }
 hipError_t launch_phase(const FArgs &A, const TilePlan &tp, hipStream_t s)
 {
-    if (A.phi_out) {
-        hipLaunchKernelGGL(k_flow_key_reset, dim3(1), dim3(1), 0, s, A.rho_min_key);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    hipError_t e = FLOW_LAUNCH_PLAN(tp, k_flow_phase, s, A);
-    if (e != hipSuccess || !A.phi_out) return e;
-    hipLaunchKernelGGL(k_flow_min, dim3(64), dim3(FT), 0, s, (const unsigned long long *)A.rho_part, tp.nslots,
-                       A.rho_min_key);
-    return hipGetLastError();
+    return FLOW_LAUNCH_PLAN(tp, k_flow_phase, s, A);
 }
 hipError_t launch_momentum(const FArgs &A, const TilePlan &tp, hipStream_t s)
 {
