@@ -153,10 +153,13 @@ pcx_status pcx_plan_destroy(pcx_plan plan);
  * (else UNSUPPORTED).  Enqueues on stream. */
 pcx_status pcx_poisson_solve(pcx_plan plan, const double *f, double *p, void *stream);
 
-/* Per-pass device timing of a plan: when enabled, pcx_step records HIP
- * events on its stream between passes; pcx_plan_pass_times synchronizes on
- * the last recorded step and returns up to cap durations (ms) and, in
- * *n_out, the number of passes; pcx_plan_pass_name names pass i. */
+/* Per-pass device timing of a plan: with enable = 1 pcx_step records HIP
+ * events on its stream between passes; with enable = 2 only around the
+ * velocity correction (two events per step, for timing that kernel inside a
+ * timed loop at the least cost); 0 turns timing off (other values act as 1).
+ * pcx_plan_pass_times synchronizes on the last recorded step and returns up
+ * to cap durations (ms) of the timed passes and, in *n_out, their number;
+ * pcx_plan_pass_name names pass i. */
 pcx_status pcx_plan_set_timing(pcx_plan plan, int32_t enable);
 pcx_status pcx_plan_pass_times(pcx_plan plan, double *ms, int32_t cap, int32_t *n_out);
 const char *pcx_plan_pass_name(pcx_plan plan, int32_t i);

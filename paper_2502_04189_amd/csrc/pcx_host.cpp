@@ -525,11 +525,21 @@ extern "C" pcx_status pcx_plan_destroy(pcx_plan P) { return plan_free(P); }
 
 // --------------------------------------------------------------- timing
 // When timing is on, every step appends HIP events recorded on its stream
-// between passes; pcx_plan_pass_times returns the durations of all passes of
-// all steps since timing was (re)enabled.
+// between passes (mode 1), or only around the velocity correction (mode 2:
+// two events per step); pcx_plan_pass_times returns the durations of the
+// timed passes of all steps since timing was (re)enabled.  An unnamed event
+// starts an interval that is not reported.
+static void tmark_record(pcx_plan P, hipStream_t s, const char *name);
+
 static void tmark(pcx_plan P, hipStream_t s, const char *name)
 {
     if (!P->timing) return;
+    if (P->timing == 2 && !(name && !std::strcmp(name, "correct_div"))) return;
+    tmark_record(P, s, name);
+}
+
+static void tmark_record(pcx_plan P, hipStream_t s, const char *name)
+{
     if (P->nev >= (int)P->ev.size()) {
         if (P->ev.size() >= 4096) return;
         hipEvent_t e;
@@ -545,7 +555,7 @@ static void tmark(pcx_plan P, hipStream_t s, const char *name)
 extern "C" pcx_status pcx_plan_set_timing(pcx_plan P, int32_t enable)
 {
     if (!P) return fail(PCX_ERR_INVALID, "plan is NULL");
-    P->timing = enable != 0;
+    P->timing = enable == 2 ? 2 : (enable != 0 ? 1 : 0);
     P->nev = 0;
     P->npass = 0;
     return PCX_OK;
@@ -699,6 +709,7 @@ extern "C" pcx_status pcx_step(pcx_plan P, double dt, double rho0, const double 
         }
     }
     auto correct = [&]() -> pcx_status {
+        if (P->timing == 2) tmark_record(P, s, nullptr); // start of the correction
         HIPCHK(launch_corr(d, !inplace, s));
         tmark(P, s, "correct_div");
         if (inplace) {

@@ -101,7 +101,7 @@ struct pcx_plan_s {
     unsigned long long *stats = nullptr;
     size_t ws_bytes = 0;
     size_t lx = 0, ly = 0, lzs = 0;
-    bool timing = false;
+    int timing = 0; // 0 off, 1 every pass, 2 the velocity correction only
     std::vector<hipEvent_t> ev;
     std::vector<std::string> names, pass_names;
     int nev = 0, npass = 0;

@@ -172,12 +172,13 @@ class Plan:
         self._o = make_options(precision, rtol, max_iters, fixed_iters, check_finite, autotune, tune_cache)
         h = C.c_void_p()
         _check(L.pcx_plan_create(C.byref(self._g), C.byref(self._o), C.byref(h)), "pcx_plan_create")
+        self._L = L
         self._h = h
         self.shape = (grid.nz, grid.ny, grid.nx)
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().pcx_plan_destroy(self._h)
+            self._L.pcx_plan_destroy(self._h)  # the library handle outlives module teardown
             self._h = None
 
     __del__ = close
@@ -212,8 +213,9 @@ class Plan:
                                        _stream_handle(stream)), "pcx_poisson_solve")
         return p
 
-    def set_timing(self, on=True):
-        _check(lib().pcx_plan_set_timing(self._h, 1 if on else 0), "pcx_plan_set_timing")
+    def set_timing(self, on=True, correction_only=False):
+        mode = (2 if correction_only else 1) if on else 0
+        _check(lib().pcx_plan_set_timing(self._h, mode), "pcx_plan_set_timing")
 
     def pass_times(self, cap=4096):
         """(pass name, ms) of every pass of every step since set_timing()."""
@@ -268,6 +270,7 @@ class Batch:
         h = C.c_void_p()
         _check(L.pcx_batch_create(arr, len(domains), C.byref(self._o), _stream_handle(stream), C.byref(h)),
                "pcx_batch_create")
+        self._L = L
         self._h = h
         self.n = len(domains)
 
@@ -283,7 +286,7 @@ class Batch:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().pcx_batch_destroy(self._h)
+            self._L.pcx_batch_destroy(self._h)  # the library handle outlives module teardown
             self._h = None
 
     __del__ = close
